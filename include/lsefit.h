@@ -1,0 +1,240 @@
+/*
+ * lsefit.h -- C ABI of the MI355X (gfx950) moment-pass least-squares fit.
+ *
+ * The operation (Sec. II of Dasgupta, "An Analytical Evaluation of Matricizing
+ * Least-Square-Errors Curve Fitting ..."): given n >= 2 pairs (x_i, y_i) and a
+ * degree m, find a_0..a_m of f(x) = a_0 + a_1 x + ... + a_m x^m minimising
+ * Pi = sum_i [y_i - f(x_i)]^2.  The zero-gradient conditions are the normal
+ * equations sum_i x_i^j y_i = sum_k a_k sum_i x_i^(j+k), j = 0..m, i.e. AX = B
+ * with the Hankel matrix A_jk = S_(j+k) of power sums S_p = sum_i x_i^p (so
+ * A_00 = S_0 = n) and B_j = T_j = sum_i x_i^j y_i; the system is solved by
+ * Gaussian elimination (end of Sec. II).
+ *
+ * The library computes the power sums of the shifted, scaled variable
+ * t_i = (x_i - c)/s in one streaming pass over device memory, solves the
+ * (m+1)x(m+1) system in float64 with partial pivoting, and maps the solution b
+ * (t-basis) back to a (x-basis): a_k = sum_{j>=k} b_j C(j,k) (-c)^(j-k) s^-j.
+ * The least-squares minimiser does not depend on (c, s); they only improve
+ * conditioning.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers owned by the caller (for example
+ *    torch tensors), except the option structs, which are host memory read
+ *    during the call only.  The library never frees or retains them past the
+ *    call, except that a plan caches a captured graph that refers to the
+ *    arrays of its last call (see fit_batched).
+ *  - x and y share one dtype (LSEFIT_F32 or LSEFIT_F64); gradients have it too.
+ *    Coefficients and power sums are always float64, lowest power first.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL is the default stream).
+ *    No entry point synchronises the device except fit_plan_tune.
+ *  - The return value reports argument and launch errors found on the host
+ *    (INVALID_ARG, WORKSPACE, DEVICE, UNSUPPORTED); it never waits for the GPU.
+ *    Numerical outcomes are written per fit to the device array `status`
+ *    (OK, SINGULAR, NONFINITE, INVALID_ARG for a bad degree or segment); the
+ *    coefficients of a fit whose status is not OK are NaN.
+ *  - SINGULAR: fewer than m+1 points, or a pivot of magnitude at most 2^-40
+ *    times the largest entry of A (in the t variable).  Fewer than m+1
+ *    distinct x values always end there.  NONFINITE: a NaN or Inf reached the
+ *    power sums or the solution.
+ *  - Results are bitwise reproducible from run to run for the same inputs,
+ *    options and schedule: every reduction has a fixed order and no floating
+ *    point atomics are used.
+ */
+#ifndef LSEFIT_H
+#define LSEFIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LSEFIT_MAX_DEGREE 8
+
+typedef enum {
+    LSEFIT_OK = 0,
+    LSEFIT_ERR_INVALID_ARG = 1,
+    LSEFIT_ERR_SINGULAR = 2,
+    LSEFIT_ERR_NONFINITE = 3,
+    LSEFIT_ERR_WORKSPACE = 4,
+    LSEFIT_ERR_DEVICE = 5,
+    LSEFIT_ERR_UNSUPPORTED = 6
+} lsefit_status;
+
+typedef enum { LSEFIT_F32 = 0, LSEFIT_F64 = 1 } lsefit_dtype;
+
+/* How the power sums are accumulated.
+ *  LSEFIT_PREC_F64:  every point is promoted to float64; t, its powers and the
+ *                    lane sums are float64.
+ *  LSEFIT_PREC_F32C: float32 inputs only; t and its powers in float32, lane
+ *                    sums as compensated (Kahan) float32 pairs folded once per
+ *                    group of four points, promoted to float64 for the
+ *                    cross-lane and cross-wave combine; followed by
+ *                    `refine_steps` passes of iterative refinement in which the
+ *                    residual r_i = y_i - sum_j b_j t_i^j and the sums
+ *                    sum_i t_i^j r_i are float64, and A delta = R corrects b. */
+typedef enum { LSEFIT_PREC_F64 = 0, LSEFIT_PREC_F32C = 1 } lsefit_precision;
+
+/* Where (c, s) come from.
+ *  LSEFIT_RANGE_GIVEN: c = center, s = scale for every fit (s > 0; a power
+ *                      of two keeps t exact).
+ *  LSEFIT_RANGE_AUTO:  from a sample of x (single fit: up to 65,536 evenly
+ *                      strided points; batched: up to 16 per fit, first and
+ *                      last included): s = 2^ceil(log2(half-range)) and c =
+ *                      the mid-range rounded to a multiple of s/8, replaced
+ *                      by 0 when it is below 2^-6 times the half-range; c is
+ *                      then rounded to float32.  The result does not depend
+ *                      on this choice except through rounding. */
+typedef enum { LSEFIT_RANGE_GIVEN = 0, LSEFIT_RANGE_AUTO = 1 } lsefit_range_mode;
+
+typedef struct lsefit_options {
+    int32_t degree;        /* single fit: m in 1..LSEFIT_MAX_DEGREE; batched: the
+                              largest degree present (each degrees[f] must be <= it) */
+    int32_t precision;     /* lsefit_precision */
+    int32_t refine_steps;  /* LSEFIT_PREC_F32C: 0 or 1 refinement passes; ignored otherwise */
+    int32_t range_mode;    /* lsefit_range_mode */
+    double center;         /* c for LSEFIT_RANGE_GIVEN */
+    double scale;          /* s for LSEFIT_RANGE_GIVEN, > 0 */
+} lsefit_options;
+
+/* Launch schedule of the streaming kernels.  Any valid schedule gives the
+ * same numbers up to the summation order it implies.
+ *  waves:          total wavefronts of the persistent streaming grid; each owns
+ *                  an equal share of the tiles (balanced by tile count)
+ *  waves_per_block: 1, 2, 4, 8 or 16
+ *  tile:           balancing granularity in points (>= 64); a tile never spans
+ *                  two fits, a wave streams the consecutive tiles of one fit
+ *                  as one segment
+ *  unroll:         vector loads in flight per lane and array: 1, 2, 4 or 8 */
+typedef struct lsefit_schedule {
+    int32_t waves;
+    int32_t waves_per_block;
+    int32_t tile;
+    int32_t unroll;
+} lsefit_schedule;
+
+typedef struct lsefit_plan lsefit_plan;   /* opaque: schedule, workspace, captured graph */
+
+/* Bytes of workspace needed by fit_moments/fit_solve (batch = 1, total_points = n)
+ * or by fit_batched/fit_backward (batch fits) with `schedule` (NULL: the default
+ * schedule).  The workspace holds per-wave partial sums, the tile table and one
+ * record per fit (c, s, power sums, t-basis solution) that fit_backward reads. */
+size_t lsefit_workspace_bytes(int64_t batch, int32_t max_degree, const lsefit_schedule* schedule);
+
+/* The schedule used when no plan is given (initially sized to this device's
+ * compute units).  lsefit_set_default_schedule replaces it for the whole
+ * process (NULL restores the initial one); it is not synchronised with calls
+ * running on other host threads.  Workspace sizes depend on it. */
+lsefit_status lsefit_default_schedule(lsefit_schedule* out);
+lsefit_status lsefit_set_default_schedule(const lsefit_schedule* schedule);
+
+/* Power-sum pass of one fit (Sec. II: the sums that form A and B).
+ *  x, y:     n points, dtype dt, any alignment (16-byte aligned is fastest)
+ *  n:        >= degree + 1
+ *  opt:      degree, precision, range
+ *  ws:       >= lsefit_workspace_bytes(1, degree, NULL) bytes, device
+ *  moments:  output, device float64 [3m+4] = c, s, S_0..S_2m, T_0..T_m of
+ *            t = (x - c)/s (S_0 = n exactly)
+ * Errors: INVALID_ARG (null pointer, n < m+1, bad degree/option), UNSUPPORTED
+ * (F32C with float64 data), WORKSPACE (ws too small), DEVICE (launch failure). */
+lsefit_status fit_moments(const void* x, const void* y, int64_t n, lsefit_dtype dt,
+                          const lsefit_options* opt, void* ws, size_t ws_bytes,
+                          double* moments, void* stream);
+
+/* Assembly of A (Hankel, A_jk = S_(j+k)) and B (B_j = T_j), Gaussian
+ * elimination with partial pivoting (end of Sec. II), optional refinement
+ * (LSEFIT_PREC_F32C with refine_steps > 0: x, y, n, dt must then be the data
+ * the moments came from), and the change back to the x-basis.
+ *  moments:  device [3m+4] as written by fit_moments
+ *  coef:     output, device float64 [2(m+1)]: a_0..a_m (x-basis), then
+ *            b_0..b_m (t-basis)
+ *  status:   output, device int32 [1]
+ * x and y may be NULL when no refinement is requested. */
+lsefit_status fit_solve(const double* moments, const lsefit_options* opt,
+                        const void* x, const void* y, int64_t n, lsefit_dtype dt,
+                        void* ws, size_t ws_bytes, double* coef, int32_t* status, void* stream);
+
+/* fit_moments followed by fit_solve in one call, with fewer launches: the
+ * kernel that sums the per-block partial sums also solves (two launches for
+ * LSEFIT_PREC_F64; two more for the refinement pass of LSEFIT_PREC_F32C).
+ *  coef:     output, device float64 [2(m+1)]: a_0..a_m (x-basis), b_0..b_m (t-basis)
+ *  status:   output, device int32 [1]
+ *  moments:  optional output (NULL to skip), device float64 [3m+4] as in fit_moments
+ * Errors as fit_moments. */
+lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
+                         void* ws, size_t ws_bytes, double* coef, int32_t* status, double* moments, void* stream);
+
+/* B independent fits over CSR segments: fit f owns points offsets[f] ..
+ * offsets[f+1]-1 of x and y (Sec. II applied to each segment).
+ *  offsets:   device int64 [B+1], non-decreasing, offsets[0] = 0
+ *  degrees:   device int32 [B], each in 1..opt->degree
+ *  coef:      output, device float64 [B * coef_stride]: a_0..a_m of fit f at
+ *             f*coef_stride; coef_stride >= opt->degree + 1; entries past m untouched
+ *  status:    output, device int32 [B]
+ *  plan:      NULL -> the default schedule and the caller's workspace `ws`;
+ *             otherwise the plan's tuned schedule and its own workspace (ws
+ *             and ws_bytes ignored) and, after the first call with the same
+ *             arguments, one replay of a captured HIP graph.
+ * All fits run in one launch of the persistent streaming kernel (plus a tile
+ * table kernel before it and one solve kernel after it). */
+lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
+                          int64_t batch, lsefit_dtype dt, const lsefit_options* opt,
+                          lsefit_plan* plan, void* ws, size_t ws_bytes,
+                          double* coef, int32_t coef_stride, int32_t* status, void* stream);
+
+/* Reverse-mode derivative of the batched fit.  Given grad_coef = dL/da
+ * (device float64 [B * coef_stride]) for the coefficients that fit_batched
+ * returned, writes dL/dx and dL/dy (device, dtype dt, one per point):
+ *   lambda = A_t^-1 M^T dL/da  (M maps t-basis b to x-basis a; A_t symmetric)
+ *   dL/dy_i = q(t_i),  dL/dx_i = (q'(t_i) r_i - q(t_i) f'(t_i)) / s
+ * with q(t) = sum_j lambda_j t^j, f(t) = sum_j b_j t^j, r_i = y_i - f(t_i),
+ * powers recomputed per point (nothing per point is stored by the forward).
+ * Points of fits whose status is not OK get NaN.  `plan`/`ws` must be the ones
+ * the forward call used, unchanged since (the per-fit records and the tile
+ * table are read from there); lambda is written into that workspace. */
+lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
+                           int64_t batch, lsefit_dtype dt, const lsefit_options* opt,
+                           lsefit_plan* plan, void* ws, size_t ws_bytes,
+                           const double* grad_coef, int32_t coef_stride,
+                           void* grad_x, void* grad_y, void* stream);
+
+/* Plans for repeated batched calls of one shape.  fit_plan_create allocates
+ * the plan's workspace (device memory, freed by fit_plan_destroy) for up to
+ * `batch` fits of degree <= max_degree.  fit_plan_tune times candidate
+ * schedules on the given data (it synchronises `stream`) and keeps the
+ * fastest; fit_plan_set_schedule installs a known one (for example from a
+ * cache).  A plan must be used from one stream at a time. */
+lsefit_status fit_plan_create(lsefit_plan** plan, int64_t batch, int32_t max_degree, lsefit_dtype dt,
+                              int32_t precision);
+lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, const int64_t* offsets,
+                            const int32_t* degrees, int64_t batch, const lsefit_options* opt,
+                            double* coef, int32_t coef_stride, int32_t* status, void* stream,
+                            int32_t reps, double* best_ms_out);
+lsefit_status fit_plan_set_schedule(lsefit_plan* plan, const lsefit_schedule* schedule);
+lsefit_status fit_plan_get_schedule(const lsefit_plan* plan, lsefit_schedule* out);
+lsefit_status fit_plan_set_graph(lsefit_plan* plan, int32_t enable);
+void fit_plan_destroy(lsefit_plan* plan);
+
+const char* lsefit_status_string(lsefit_status s);
+
+/* Kernel timing for profiling.  While enabled, every launch of a streaming
+ * kernel made by the calls above (outside graph capture) is bracketed by a
+ * pair of HIP events recorded on the call's stream.  lsefit_timing_read waits
+ * for the recorded events of one kernel kind and returns the summed duration
+ * in milliseconds and the number of launches since the last reset.
+ *  kind: 0 = power-sum pass, 1 = refinement pass, 2 = adjoint pass,
+ *        3 = per-fit combine and solve.
+ * Not synchronised with calls on other host threads. */
+lsefit_status lsefit_timing_enable(int32_t enable);
+lsefit_status lsefit_timing_reset(void);
+lsefit_status lsefit_timing_read(int32_t kind, double* total_ms, int64_t* launches);
+
+/* Device ordinal's compute-unit count as the library sees it (0 on error). */
+int32_t lsefit_device_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSEFIT_H */

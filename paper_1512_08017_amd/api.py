@@ -1,0 +1,298 @@
+"""Python surface of the HIP library: tensors in, tensors out.
+
+Every function here only marshals arguments for the C ABI (include/lsefit.h):
+device pointers of torch tensors, the current HIP stream of their device, and
+a workspace tensor from torch's caching allocator.  All arithmetic of the fit
+runs in the library's kernels; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import Options, Schedule, check
+
+_DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
+_PREC = {"f64": _lib.PREC_F64, "f32c": _lib.PREC_F32C}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def options(degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None) -> Options:
+    if precision not in _PREC:
+        raise ValueError(f"precision must be one of {sorted(_PREC)}")
+    o = Options()
+    o.degree = int(degree)
+    o.precision = _PREC[precision]
+    o.refine_steps = int(refine) if precision == "f32c" else 0
+    if center is None and scale is None:
+        o.range_mode = _lib.RANGE_AUTO
+        o.center, o.scale = 0.0, 1.0
+    else:
+        o.range_mode = _lib.RANGE_GIVEN
+        o.center = float(0.0 if center is None else center)
+        o.scale = float(1.0 if scale is None else scale)
+    return o
+
+
+def _check_points(x, y):
+    if not (isinstance(x, torch.Tensor) and isinstance(y, torch.Tensor)):
+        raise TypeError("x and y must be tensors")
+    if not x.is_cuda or x.device != y.device:
+        raise ValueError("x and y must be on the same GPU")
+    if x.dtype not in _DT or y.dtype != x.dtype:
+        raise TypeError("x and y must both be float32 or both float64")
+    if x.dim() != 1 or y.shape != x.shape:
+        raise ValueError("x and y must be 1-D of equal length")
+    if not (x.is_contiguous() and y.is_contiguous()):
+        raise ValueError("x and y must be contiguous")
+
+
+def workspace_bytes(batch: int, max_degree: int, schedule: Schedule | None = None) -> int:
+    L = _lib.load()
+    n = L.lsefit_workspace_bytes(int(batch), int(max_degree), ctypes.byref(schedule) if schedule else None)
+    if n == 0:
+        raise ValueError("invalid batch/degree/schedule")
+    return int(n)
+
+
+def default_schedule() -> Schedule:
+    s = Schedule()
+    check(_lib.load().lsefit_default_schedule(ctypes.byref(s)), "lsefit_default_schedule")
+    return s
+
+
+def set_default_schedule(schedule: Schedule | dict | None):
+    if isinstance(schedule, dict):
+        s = Schedule()
+        for k, v in schedule.items():
+            setattr(s, k, int(v))
+        schedule = s
+    check(_lib.load().lsefit_set_default_schedule(ctypes.byref(schedule) if schedule is not None else None),
+          "lsefit_set_default_schedule")
+
+
+def device_cus() -> int:
+    return int(_lib.load().lsefit_device_cus())
+
+
+# ---------------------------------------------------------------------------
+# single fit
+# ---------------------------------------------------------------------------
+@dataclass
+class FitResult:
+    coef: torch.Tensor       # a_0..a_m, x-basis, float64 (device)
+    coef_t: torch.Tensor     # b_0..b_m, t-basis, float64 (device)
+    status: torch.Tensor     # int32 [1] (device)
+    moments: torch.Tensor    # [c, s, S_0..S_2m, T_0..T_m] (device)
+
+    @property
+    def center(self):
+        return float(self.moments[0])
+
+    @property
+    def scale(self):
+        return float(self.moments[1])
+
+
+def fit_moments(x, y, degree, precision="f64", center=None, scale=None, ws=None):
+    """Power sums [c, s, S_0..S_2m, T_0..T_m] of t = (x - c)/s (one streaming pass)."""
+    _check_points(x, y)
+    L = _lib.load()
+    o = options(degree, precision, 0, center, scale)
+    nbytes = workspace_bytes(1, degree)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    mom = torch.empty(3 * degree + 4, dtype=torch.float64, device=x.device)
+    check(L.fit_moments(_ptr(x), _ptr(y), x.numel(), _DT[x.dtype], ctypes.byref(o), _ptr(ws), ws.numel(),
+                        _ptr(mom), _stream(x.device)), "fit_moments")
+    return mom, ws
+
+
+def fit_solve(moments, degree, precision="f64", refine=1, x=None, y=None, ws=None, center=None, scale=None):
+    """Gaussian elimination on the Hankel system, optional refinement, x-basis coefficients."""
+    L = _lib.load()
+    o = options(degree, precision, refine, center, scale)
+    dev = moments.device
+    nbytes = workspace_bytes(1, degree)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    coef = torch.empty(2 * (degree + 1), dtype=torch.float64, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    n = x.numel() if x is not None else 0
+    dt = _DT[x.dtype] if x is not None else _lib.F32
+    check(L.fit_solve(_ptr(moments), ctypes.byref(o), _ptr(x), _ptr(y), n, dt, _ptr(ws), ws.numel(), _ptr(coef),
+                      _ptr(status), _stream(dev)), "fit_solve")
+    return coef, status
+
+
+def fit(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None,
+        ws=None) -> FitResult:
+    """Least-squares polynomial fit of degree ``degree`` (coefficients a_0 first), one fused call."""
+    _check_points(x, y)
+    L = _lib.load()
+    o = options(degree, precision, refine, center, scale)
+    nbytes = workspace_bytes(1, degree)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    m1 = degree + 1
+    coef = torch.empty(2 * m1, dtype=torch.float64, device=x.device)
+    status = torch.empty(1, dtype=torch.int32, device=x.device)
+    mom = torch.empty(3 * degree + 4, dtype=torch.float64, device=x.device)
+    check(L.fit_single(_ptr(x), _ptr(y), x.numel(), _DT[x.dtype], ctypes.byref(o), _ptr(ws), ws.numel(),
+                       _ptr(coef), _ptr(status), _ptr(mom), _stream(x.device)), "fit_single")
+    return FitResult(coef[:m1], coef[m1:], status, mom)
+
+
+def fit_split(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None) -> FitResult:
+    """The same fit through the two-call form (fit_moments, then fit_solve)."""
+    mom, ws = fit_moments(x, y, degree, precision, center, scale)
+    coef, status = fit_solve(mom, degree, precision, refine, x, y, ws, center, scale)
+    m1 = degree + 1
+    return FitResult(coef[:m1], coef[m1:], status, mom)
+
+
+# ---------------------------------------------------------------------------
+# batched fits
+# ---------------------------------------------------------------------------
+class Plan:
+    """A tuned schedule, its own workspace and a captured HIP graph for
+    repeated batched calls of one shape (fit_plan_* in the C ABI)."""
+
+    def __init__(self, batch: int, max_degree: int, dtype=torch.float32, precision: str = "f64"):
+        self._L = _lib.load()
+        h = ctypes.c_void_p()
+        check(self._L.fit_plan_create(ctypes.byref(h), int(batch), int(max_degree), _DT[dtype], _PREC[precision]),
+              "fit_plan_create")
+        self.handle = h
+        self.batch, self.max_degree, self.dtype, self.precision = batch, max_degree, dtype, precision
+
+    def close(self):
+        if self.handle:
+            self._L.fit_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def schedule(self) -> dict:
+        s = Schedule()
+        check(self._L.fit_plan_get_schedule(self.handle, ctypes.byref(s)), "fit_plan_get_schedule")
+        return s.as_dict()
+
+    def set_schedule(self, sched: dict):
+        s = Schedule()
+        for k, v in sched.items():
+            setattr(s, k, int(v))
+        check(self._L.fit_plan_set_schedule(self.handle, ctypes.byref(s)), "fit_plan_set_schedule")
+
+    def set_graph(self, enable: bool):
+        check(self._L.fit_plan_set_graph(self.handle, 1 if enable else 0), "fit_plan_set_graph")
+
+    def tune(self, x, y, offsets, degrees, max_degree=None, precision=None, refine=1, center=None, scale=None,
+             reps=3) -> float:
+        _check_batch(x, y, offsets, degrees)
+        m = self.max_degree if max_degree is None else max_degree
+        o = options(m, precision or self.precision, refine, center, scale)
+        B = degrees.numel()
+        coef = torch.empty(B * (m + 1), dtype=torch.float64, device=x.device)
+        status = torch.empty(B, dtype=torch.int32, device=x.device)
+        best = ctypes.c_double(0.0)
+        check(self._L.fit_plan_tune(self.handle, _ptr(x), _ptr(y), _ptr(offsets), _ptr(degrees), B, ctypes.byref(o),
+                                    _ptr(coef), m + 1, _ptr(status), _stream(x.device), int(reps),
+                                    ctypes.byref(best)), "fit_plan_tune")
+        return best.value
+
+
+def _check_batch(x, y, offsets, degrees):
+    _check_points(x, y)
+    if offsets.dtype != torch.int64 or degrees.dtype != torch.int32:
+        raise TypeError("offsets must be int64 and degrees int32")
+    if offsets.device != x.device or degrees.device != x.device:
+        raise ValueError("offsets and degrees must be on the device of x")
+    if offsets.dim() != 1 or degrees.dim() != 1 or offsets.numel() != degrees.numel() + 1:
+        raise ValueError("offsets must have one more entry than degrees")
+    if not (offsets.is_contiguous() and degrees.is_contiguous()):
+        raise ValueError("offsets and degrees must be contiguous")
+
+
+def fit_batched(x, y, offsets, degrees, max_degree: int, precision: str = "f64", refine: int = 1,
+                center=None, scale=None, plan: Plan | None = None, coef_stride: int | None = None,
+                ws: torch.Tensor | None = None, out=None):
+    """Independent fits over CSR segments; returns (coef [B, stride], status [B], ws)."""
+    _check_batch(x, y, offsets, degrees)
+    L = _lib.load()
+    B = degrees.numel()
+    o = options(max_degree, precision, refine, center, scale)
+    stride = coef_stride or (max_degree + 1)
+    if out is None:
+        coef = torch.zeros((B, stride), dtype=torch.float64, device=x.device)
+        status = torch.empty(B, dtype=torch.int32, device=x.device)
+    else:
+        coef, status = out
+    if plan is None:
+        nbytes = workspace_bytes(max(B, 1), max_degree)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    check(L.fit_batched(_ptr(x), _ptr(y), _ptr(offsets), _ptr(degrees), B, _DT[x.dtype], ctypes.byref(o),
+                        plan.handle if plan is not None else None, _ptr(ws) if plan is None else None,
+                        ws.numel() if plan is None else 0, _ptr(coef), stride, _ptr(status), _stream(x.device)),
+          "fit_batched")
+    return coef, status, ws
+
+
+def fit_backward(x, y, offsets, degrees, max_degree, grad_coef, ws=None, plan=None, precision="f64",
+                 center=None, scale=None):
+    """dL/dx, dL/dy from dL/da (grad_coef [B, stride] float64) after fit_batched."""
+    _check_batch(x, y, offsets, degrees)
+    L = _lib.load()
+    B = degrees.numel()
+    o = options(max_degree, precision, 0, center, scale)
+    grad_coef = grad_coef.to(torch.float64).contiguous()
+    gx = torch.empty_like(x)
+    gy = torch.empty_like(y)
+    check(L.fit_backward(_ptr(x), _ptr(y), _ptr(offsets), _ptr(degrees), B, _DT[x.dtype], ctypes.byref(o),
+                         plan.handle if plan is not None else None, _ptr(ws) if plan is None else None,
+                         ws.numel() if (plan is None and ws is not None) else 0, _ptr(grad_coef),
+                         grad_coef.shape[-1], _ptr(gx), _ptr(gy), _stream(x.device)), "fit_backward")
+    return gx, gy
+
+
+class LseFit(torch.autograd.Function):
+    """Differentiable batched fit: coef = LseFit.apply(x, y, offsets, degrees, max_degree, precision,
+    center, scale).  The backward is the library's adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, x, y, offsets, degrees, max_degree, precision="f64", center=None, scale=None):
+        coef, status, ws = fit_batched(x, y, offsets, degrees, max_degree, precision, 1, center, scale)
+        ctx.save_for_backward(x, y, offsets, degrees)
+        ctx.ws = ws
+        ctx.cfg = (max_degree, precision, center, scale)
+        ctx.status = status
+        return coef
+
+    @staticmethod
+    def backward(ctx, grad_coef):
+        x, y, offsets, degrees = ctx.saved_tensors
+        max_degree, precision, center, scale = ctx.cfg
+        gx, gy = fit_backward(x, y, offsets, degrees, max_degree, grad_coef, ws=ctx.ws, precision=precision,
+                              center=center, scale=scale)
+        return gx, gy, None, None, None, None, None, None
+
+
+def lsefit(x, y, offsets, degrees, max_degree: int, precision: str = "f64", center=None, scale=None):
+    """Differentiable batched fit (autograd through the hand-written adjoint)."""
+    return LseFit.apply(x, y, offsets, degrees, max_degree, precision, center, scale)

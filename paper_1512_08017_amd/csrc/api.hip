@@ -1,0 +1,624 @@
+// C ABI of the moment-pass least-squares fit (declared in include/lsefit.h).
+//
+// Host side only: argument validation, workspace carving, the launch schedule,
+// plans (tuned schedule + own workspace + captured HIP graph) and the order of
+// kernel launches for each call.  Every step of the computation runs in the
+// kernels of kernels_impl.hpp and dispatch.hip.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lsefit.h"
+
+using namespace lsefit;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kDefaultWavesPerCU = 16;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t tile_start, pstatus, rec, part, total;
+};
+
+Layout layout(int64_t B, int maxM, int64_t W) {
+    Layout L{};
+    size_t off = 0;
+    L.tile_start = off;
+    off = align_up(off + sizeof(int64_t) * (size_t)(B + 1));
+    L.pstatus = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)B);
+    L.rec = off;
+    off = align_up(off + sizeof(double) * (size_t)B * rec_len(maxM));
+    L.part = off;
+    off = align_up(off + sizeof(double) * (size_t)(W + B) * nacc(maxM));
+    L.total = off + kAlign;   // slack for aligning the caller's base pointer
+    return L;
+}
+
+Work carve(void* ws, const Layout& L) {
+    uintptr_t base = ((uintptr_t)ws + kAlign - 1) / kAlign * kAlign;
+    Work w;
+    w.tile_start = (int64_t*)(base + L.tile_start);
+    w.pstatus = (int32_t*)(base + L.pstatus);
+    w.rec = (double*)(base + L.rec);
+    w.part = (double*)(base + L.part);
+    return w;
+}
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
+
+lsefit_schedule initial_schedule() {
+    int cus = device_cus();
+    if (cus <= 0) cus = 256;
+    lsefit_schedule s;
+    s.waves = cus * kDefaultWavesPerCU;
+    s.waves_per_block = 4;
+    s.tile = 256;
+    s.unroll = 2;
+    return s;
+}
+
+std::mutex g_sched_mu;
+bool g_sched_set = false;
+lsefit_schedule g_sched;
+
+lsefit_schedule current_default() {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    if (!g_sched_set) {
+        g_sched = initial_schedule();
+        g_sched_set = true;
+    }
+    return g_sched;
+}
+
+bool schedule_ok(const lsefit_schedule& s) {
+    const int wpb = s.waves_per_block;
+    return s.waves >= 1 && s.waves <= (1 << 22) && (wpb == 1 || wpb == 2 || wpb == 4) && s.tile >= 64 &&
+           (s.unroll == 1 || s.unroll == 2 || s.unroll == 4);
+}
+
+Launch to_launch(const lsefit_schedule& s) {
+    Launch L;
+    L.wpb = s.waves_per_block;
+    L.waves = (int64_t)(s.waves + L.wpb - 1) / L.wpb * L.wpb;   // whole blocks
+    L.tile = s.tile;
+    L.unroll = s.unroll;
+    return L;
+}
+
+// common misalignment (elements modulo the 16-byte vector width) of the given
+// pointers, or -1 when they differ or are not element-aligned
+int common_mis(int dt, std::initializer_list<const void*> ptrs) {
+    const uintptr_t es = dt == LSEFIT_F32 ? 4 : 8;
+    const uintptr_t vw = 16 / es;
+    int mis = -1;
+    for (const void* p : ptrs) {
+        if (!p) continue;
+        const uintptr_t a = (uintptr_t)p;
+        if (a % es) return -1;
+        const int m = (int)((a / es) % vw);
+        if (mis < 0) mis = m;
+        else if (mis != m) return -1;
+    }
+    return mis;
+}
+
+bool opts_ok(const lsefit_options* o, int dt, bool batched) {
+    if (!o) return false;
+    if (o->degree < 1 || o->degree > LSEFIT_MAX_DEGREE) return false;
+    if (o->precision != LSEFIT_PREC_F64 && o->precision != LSEFIT_PREC_F32C) return false;
+    if (o->refine_steps < 0 || o->refine_steps > 1) return false;
+    if (o->range_mode != LSEFIT_RANGE_GIVEN && o->range_mode != LSEFIT_RANGE_AUTO) return false;
+    if (o->range_mode == LSEFIT_RANGE_GIVEN && !(std::isfinite(o->center) && std::isfinite(o->scale) && o->scale > 0))
+        return false;
+    if (dt != LSEFIT_F32 && dt != LSEFIT_F64) return false;
+    (void)batched;
+    return true;
+}
+
+bool refining(const lsefit_options* o) { return o->precision == LSEFIT_PREC_F32C && o->refine_steps > 0; }
+
+#define LSEFIT_TRY(expr)                                   \
+    do {                                                   \
+        if ((expr) != hipSuccess) return LSEFIT_ERR_DEVICE; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// optional kernel timing: event pairs around streaming launches
+// ---------------------------------------------------------------------------
+enum TimedKind { kTimeMoments = 0, kTimeRefine = 1, kTimeAdjoint = 2, kTimeCombine = 3, kTimeKinds = 4 };
+
+struct Timing {
+    std::mutex mu;
+    bool enabled = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kTimeKinds];
+    std::vector<hipEvent_t> pool;
+    double total_ms[kTimeKinds] = {0, 0, 0, 0};
+    int64_t launches[kTimeKinds] = {0, 0, 0, 0};
+};
+Timing g_timing;
+
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
+}
+
+hipEvent_t take_event() {
+    if (!g_timing.pool.empty()) {
+        hipEvent_t e = g_timing.pool.back();
+        g_timing.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// runs `launch` on `st`, bracketed by events when timing is on
+template <class F>
+hipError_t timed(int kind, hipStream_t st, F&& launch) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        on = g_timing.enabled;
+    }
+    if (!on || capturing(st)) return launch();
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        a = take_event();
+        b = take_event();
+    }
+    if (!a || !b) return launch();
+    hipError_t e = hipEventRecord(a, st);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, st);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.pending[kind].push_back({a, b});
+    return hipSuccess;
+}
+
+// the whole batched forward on one stream
+lsefit_status enqueue_batched(const FitDesc& d, const Work& w, const lsefit_options* o, int dt, const void* x,
+                              const void* y, double* coef, int32_t coef_stride, int32_t* status,
+                              const lsefit_schedule& sched, hipStream_t st) {
+    const Launch L = to_launch(sched);
+    const int maxM = o->degree;
+    const bool given = o->range_mode == LSEFIT_RANGE_GIVEN;
+    const int mis = common_mis(dt, {x, y});
+    const bool by_block = L.waves >= 64 * d.batch;
+    const Finish solve{kSolve, coef, coef_stride, 0, status, nullptr};
+    const Finish refine{kRefine, coef, coef_stride, 0, status, nullptr};
+    LSEFIT_TRY(launch_plan(d, w, maxM, L.tile, given, o->center, o->scale, st));
+    if (!given) LSEFIT_TRY(launch_range(d, w, maxM, dt, x, st));
+    const RangeArg ra{LSEFIT_RANGE_GIVEN, 0.0, 1.0};   // per-fit (c, s) are in the records
+    LSEFIT_TRY(timed(kTimeMoments, st, [&] { return launch_moments(d, w, maxM, o->precision, dt, x, y, L, mis, ra, st); }));
+    LSEFIT_TRY(timed(kTimeCombine, st, [&] { return launch_combine(d, w, maxM, L, by_block, solve, st); }));
+    if (refining(o)) {
+        LSEFIT_TRY(timed(kTimeRefine, st, [&] { return launch_refine(d, w, maxM, dt, x, y, L, mis, st); }));
+        LSEFIT_TRY(timed(kTimeCombine, st, [&] { return launch_combine(d, w, maxM, L, by_block, refine, st); }));
+    }
+    return LSEFIT_OK;
+}
+
+// validation shared by the single-fit entry points
+lsefit_status check_single(const void* x, const void* y, int64_t n, int dt, const lsefit_options* opt, void* ws,
+                           size_t ws_bytes, Layout* lay, lsefit_schedule* sched) {
+    if (!x || !y || !ws || !opts_ok(opt, dt, false)) return LSEFIT_ERR_INVALID_ARG;
+    if (n < (int64_t)opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
+    if (opt->precision == LSEFIT_PREC_F32C && dt != LSEFIT_F32) return LSEFIT_ERR_UNSUPPORTED;
+    *sched = current_default();
+    *lay = layout(1, opt->degree, to_launch(*sched).waves);
+    if (ws_bytes < lay->total) return LSEFIT_ERR_WORKSPACE;
+    return LSEFIT_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+struct lsefit_plan {
+    int64_t batch = 0;
+    int32_t max_degree = 0;
+    int32_t dtype = 0;
+    int32_t precision = 0;
+    int device = 0;
+    int64_t max_waves = 0;
+    lsefit_schedule sched{};
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool graph_enabled = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct Key {
+        const void *x, *y;
+        const int64_t* offsets;
+        const int32_t* degrees;
+        int64_t batch;
+        int32_t dt;
+        lsefit_options opt;
+        double* coef;
+        int32_t coef_stride;
+        int32_t* status;
+    } key{};
+    bool have_key = false;
+
+    void drop_graph() {
+        if (exec) hipGraphExecDestroy(exec);
+        exec = nullptr;
+        have_key = false;
+    }
+};
+
+namespace {
+
+bool same_key(const lsefit_plan::Key& a, const lsefit_plan::Key& b) {
+    return a.x == b.x && a.y == b.y && a.offsets == b.offsets && a.degrees == b.degrees && a.batch == b.batch &&
+           a.dt == b.dt && a.coef == b.coef && a.coef_stride == b.coef_stride && a.status == b.status &&
+           std::memcmp(&a.opt, &b.opt, sizeof(lsefit_options)) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lsefit_status_string(lsefit_status s) {
+    switch (s) {
+        case LSEFIT_OK: return "ok";
+        case LSEFIT_ERR_INVALID_ARG: return "invalid argument";
+        case LSEFIT_ERR_SINGULAR: return "singular normal system";
+        case LSEFIT_ERR_NONFINITE: return "non-finite value";
+        case LSEFIT_ERR_WORKSPACE: return "workspace too small";
+        case LSEFIT_ERR_DEVICE: return "device or launch error";
+        case LSEFIT_ERR_UNSUPPORTED: return "unsupported combination";
+    }
+    return "unknown status";
+}
+
+int32_t lsefit_device_cus(void) { return device_cus(); }
+
+lsefit_status lsefit_default_schedule(lsefit_schedule* out) {
+    if (!out) return LSEFIT_ERR_INVALID_ARG;
+    *out = current_default();
+    return LSEFIT_OK;
+}
+
+lsefit_status lsefit_set_default_schedule(const lsefit_schedule* s) {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    if (!s) {
+        g_sched = initial_schedule();
+        g_sched_set = true;
+        return LSEFIT_OK;
+    }
+    if (!schedule_ok(*s)) return LSEFIT_ERR_INVALID_ARG;
+    g_sched = *s;
+    g_sched_set = true;
+    return LSEFIT_OK;
+}
+
+size_t lsefit_workspace_bytes(int64_t batch, int32_t max_degree, const lsefit_schedule* schedule) {
+    if (batch < 1 || max_degree < 1 || max_degree > LSEFIT_MAX_DEGREE) return 0;
+    const lsefit_schedule s = schedule ? *schedule : current_default();
+    if (!schedule_ok(s)) return 0;
+    return layout(batch, max_degree, to_launch(s).waves).total;
+}
+
+int64_t grid_blocks(const Launch& L) { return L.waves / L.wpb; }
+
+lsefit_status fit_moments(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
+                          void* ws, size_t ws_bytes, double* moments, void* stream) {
+    if (!moments) return LSEFIT_ERR_INVALID_ARG;
+    Layout lay;
+    lsefit_schedule sched;
+    const lsefit_status v = check_single(x, y, n, dt, opt, ws, ws_bytes, &lay, &sched);
+    if (v != LSEFIT_OK) return v;
+    hipStream_t st = (hipStream_t)stream;
+    const FitDesc d{nullptr, nullptr, n, 1, opt->degree};
+    const Work w = carve(ws, lay);
+    const Launch L = to_launch(sched);
+    const int mis = common_mis(dt, {x, y});
+    const RangeArg ra{opt->range_mode, opt->center, opt->scale};
+    const Finish fz{kMomentsOnly, nullptr, 0, 0, nullptr, moments};
+    LSEFIT_TRY(timed(kTimeMoments, st,
+                     [&] { return launch_moments(d, w, opt->degree, opt->precision, dt, x, y, L, mis, ra, st); }));
+    LSEFIT_TRY(timed(kTimeCombine, st, [&] { return launch_finish_single(d, w, opt->degree, grid_blocks(L), fz, st); }));
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_solve(const double* moments, const lsefit_options* opt, const void* x, const void* y, int64_t n,
+                        lsefit_dtype dt, void* ws, size_t ws_bytes, double* coef, int32_t* status, void* stream) {
+    if (!moments || !ws || !coef || !status || !opts_ok(opt, dt, false)) return LSEFIT_ERR_INVALID_ARG;
+    const bool refine = refining(opt);
+    if (refine) {
+        if (!x || !y || n < (int64_t)opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
+        if (dt != LSEFIT_F32) return LSEFIT_ERR_UNSUPPORTED;
+    }
+    const lsefit_schedule sched = current_default();
+    const Layout lay = layout(1, opt->degree, to_launch(sched).waves);
+    if (ws_bytes < lay.total) return LSEFIT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const FitDesc d{nullptr, nullptr, refine ? n : 0, 1, opt->degree};
+    const Work w = carve(ws, lay);
+    const Launch L = to_launch(sched);
+    LSEFIT_TRY(launch_solve_moments(moments, w, opt->degree, opt->degree, coef, status, st));
+    if (refine) {
+        const int mis = common_mis(dt, {x, y});
+        const Finish fz{kRefine, coef, 2 * (opt->degree + 1), 1, status, nullptr};
+        LSEFIT_TRY(timed(kTimeRefine, st, [&] { return launch_refine(d, w, opt->degree, dt, x, y, L, mis, st); }));
+        LSEFIT_TRY(timed(kTimeCombine, st,
+                         [&] { return launch_finish_single(d, w, opt->degree, grid_blocks(L), fz, st); }));
+    }
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
+                         void* ws, size_t ws_bytes, double* coef, int32_t* status, double* moments, void* stream) {
+    if (!coef || !status) return LSEFIT_ERR_INVALID_ARG;
+    Layout lay;
+    lsefit_schedule sched;
+    const lsefit_status v = check_single(x, y, n, dt, opt, ws, ws_bytes, &lay, &sched);
+    if (v != LSEFIT_OK) return v;
+    hipStream_t st = (hipStream_t)stream;
+    const FitDesc d{nullptr, nullptr, n, 1, opt->degree};
+    const Work w = carve(ws, lay);
+    const Launch L = to_launch(sched);
+    const int mis = common_mis(dt, {x, y});
+    const int stride = 2 * (opt->degree + 1);
+    const RangeArg ra{opt->range_mode, opt->center, opt->scale};
+    const Finish solve{kSolve, coef, stride, 1, status, moments};
+    LSEFIT_TRY(timed(kTimeMoments, st,
+                     [&] { return launch_moments(d, w, opt->degree, opt->precision, dt, x, y, L, mis, ra, st); }));
+    LSEFIT_TRY(timed(kTimeCombine, st,
+                     [&] { return launch_finish_single(d, w, opt->degree, grid_blocks(L), solve, st); }));
+    if (refining(opt)) {
+        const Finish fz{kRefine, coef, stride, 1, status, nullptr};
+        LSEFIT_TRY(timed(kTimeRefine, st, [&] { return launch_refine(d, w, opt->degree, dt, x, y, L, mis, st); }));
+        LSEFIT_TRY(timed(kTimeCombine, st,
+                         [&] { return launch_finish_single(d, w, opt->degree, grid_blocks(L), fz, st); }));
+    }
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
+                          int64_t batch, lsefit_dtype dt, const lsefit_options* opt, lsefit_plan* plan, void* ws,
+                          size_t ws_bytes, double* coef, int32_t coef_stride, int32_t* status, void* stream) {
+    if (batch < 0 || !opts_ok(opt, dt, true)) return LSEFIT_ERR_INVALID_ARG;
+    if (batch == 0) return LSEFIT_OK;
+    if (!x || !y || !offsets || !degrees || !coef || !status) return LSEFIT_ERR_INVALID_ARG;
+    if (coef_stride < opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
+    if (opt->precision == LSEFIT_PREC_F32C && dt != LSEFIT_F32) return LSEFIT_ERR_UNSUPPORTED;
+    hipStream_t st = (hipStream_t)stream;
+    const FitDesc d{offsets, degrees, 0, batch, opt->degree};
+    if (!plan) {
+        const lsefit_schedule sched = current_default();
+        const Layout lay = layout(batch, opt->degree, to_launch(sched).waves);
+        if (!ws || ws_bytes < lay.total) return LSEFIT_ERR_WORKSPACE;
+        return enqueue_batched(d, carve(ws, lay), opt, dt, x, y, coef, coef_stride, status, sched, st);
+    }
+    if (batch > plan->batch || opt->degree > plan->max_degree || dt != plan->dtype) return LSEFIT_ERR_INVALID_ARG;
+    const Layout lay = layout(plan->batch, plan->max_degree, plan->max_waves);
+    const Work w = carve(plan->ws, lay);
+    if (!plan->graph_enabled)
+        return enqueue_batched(d, w, opt, dt, x, y, coef, coef_stride, status, plan->sched, st);
+    lsefit_plan::Key key{x, y, offsets, degrees, batch, (int32_t)dt, *opt, coef, coef_stride, status};
+    if (!(plan->exec && plan->have_key && same_key(plan->key, key))) {
+        plan->drop_graph();
+        if (!plan->cap_stream) LSEFIT_TRY(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+        LSEFIT_TRY(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+        const lsefit_status s =
+            enqueue_batched(d, w, opt, dt, x, y, coef, coef_stride, status, plan->sched, plan->cap_stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(plan->cap_stream, &graph);
+        if (s != LSEFIT_OK || e != hipSuccess || !graph) {
+            if (graph) hipGraphDestroy(graph);
+            return s != LSEFIT_OK ? s : LSEFIT_ERR_DEVICE;
+        }
+        const hipError_t ie = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            plan->exec = nullptr;
+            return LSEFIT_ERR_DEVICE;
+        }
+        plan->key = key;
+        plan->have_key = true;
+    }
+    LSEFIT_TRY(hipGraphLaunch(plan->exec, st));
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
+                           int64_t batch, lsefit_dtype dt, const lsefit_options* opt, lsefit_plan* plan, void* ws,
+                           size_t ws_bytes, const double* grad_coef, int32_t coef_stride, void* grad_x,
+                           void* grad_y, void* stream) {
+    if (batch < 0 || !opts_ok(opt, dt, true)) return LSEFIT_ERR_INVALID_ARG;
+    if (batch == 0) return LSEFIT_OK;
+    if (!x || !y || !offsets || !degrees || !grad_coef || !grad_x || !grad_y) return LSEFIT_ERR_INVALID_ARG;
+    if (coef_stride < opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const FitDesc d{offsets, degrees, 0, batch, opt->degree};
+    Work w;
+    lsefit_schedule sched;
+    if (plan) {
+        if (batch > plan->batch || opt->degree > plan->max_degree || dt != plan->dtype) return LSEFIT_ERR_INVALID_ARG;
+        w = carve(plan->ws, layout(plan->batch, plan->max_degree, plan->max_waves));
+        sched = plan->sched;
+    } else {
+        sched = current_default();
+        const Layout lay = layout(batch, opt->degree, to_launch(sched).waves);
+        if (!ws || ws_bytes < lay.total) return LSEFIT_ERR_WORKSPACE;
+        w = carve(ws, lay);
+    }
+    const int mis = common_mis(dt, {x, y, grad_x, grad_y});
+    LSEFIT_TRY(timed(kTimeAdjoint, st, [&] {
+        return launch_adjoint(d, w, opt->degree, dt, x, y, grad_coef, coef_stride, grad_x, grad_y, to_launch(sched),
+                              mis, st);
+    }));
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_plan_create(lsefit_plan** out, int64_t batch, int32_t max_degree, lsefit_dtype dt,
+                              int32_t precision) {
+    if (!out || batch < 1 || max_degree < 1 || max_degree > LSEFIT_MAX_DEGREE) return LSEFIT_ERR_INVALID_ARG;
+    if (dt != LSEFIT_F32 && dt != LSEFIT_F64) return LSEFIT_ERR_INVALID_ARG;
+    if (precision != LSEFIT_PREC_F64 && precision != LSEFIT_PREC_F32C) return LSEFIT_ERR_INVALID_ARG;
+    lsefit_plan* p = new (std::nothrow) lsefit_plan();
+    if (!p) return LSEFIT_ERR_DEVICE;
+    p->batch = batch;
+    p->max_degree = max_degree;
+    p->dtype = dt;
+    p->precision = precision;
+    hipGetDevice(&p->device);
+    p->sched = current_default();
+    int cus = device_cus();
+    if (cus <= 0) cus = 256;
+    p->max_waves = (int64_t)cus * 64;
+    if (to_launch(p->sched).waves > p->max_waves) p->max_waves = to_launch(p->sched).waves;
+    const Layout lay = layout(batch, max_degree, p->max_waves);
+    if (hipMalloc(&p->ws, lay.total) != hipSuccess) {
+        delete p;
+        return LSEFIT_ERR_DEVICE;
+    }
+    p->ws_bytes = lay.total;
+    *out = p;
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_plan_set_schedule(lsefit_plan* plan, const lsefit_schedule* s) {
+    if (!plan || !s || !schedule_ok(*s) || to_launch(*s).waves > plan->max_waves) return LSEFIT_ERR_INVALID_ARG;
+    plan->sched = *s;
+    plan->drop_graph();
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_plan_get_schedule(const lsefit_plan* plan, lsefit_schedule* out) {
+    if (!plan || !out) return LSEFIT_ERR_INVALID_ARG;
+    *out = plan->sched;
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_plan_set_graph(lsefit_plan* plan, int32_t enable) {
+    if (!plan) return LSEFIT_ERR_INVALID_ARG;
+    plan->graph_enabled = enable != 0;
+    plan->drop_graph();
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, const int64_t* offsets,
+                            const int32_t* degrees, int64_t batch, const lsefit_options* opt, double* coef,
+                            int32_t coef_stride, int32_t* status, void* stream, int32_t reps, double* best_ms_out) {
+    if (!plan || !opts_ok(opt, plan->dtype, true) || batch < 1 || batch > plan->batch) return LSEFIT_ERR_INVALID_ARG;
+    if (reps < 1) reps = 3;
+    hipStream_t st = (hipStream_t)stream;
+    const FitDesc d{offsets, degrees, 0, batch, opt->degree};
+    const Work w = carve(plan->ws, layout(plan->batch, plan->max_degree, plan->max_waves));
+    int cus = device_cus();
+    if (cus <= 0) cus = 256;
+    std::vector<lsefit_schedule> cands;
+    for (int wpc : {4, 8, 16, 32})
+        for (int wpb : {2, 4})
+            for (int tile : {256, 2048})
+                for (int unroll : {1, 2, 4}) {
+                    lsefit_schedule s{cus * wpc, wpb, tile, unroll};
+                    if (to_launch(s).waves <= plan->max_waves) cands.push_back(s);
+                }
+    hipEvent_t e0, e1;
+    LSEFIT_TRY(hipEventCreate(&e0));
+    LSEFIT_TRY(hipEventCreate(&e1));
+    double best = 1e300;
+    lsefit_schedule best_s = plan->sched;
+    for (const auto& s : cands) {
+        // one untimed run, then the timed ones
+        lsefit_status r = enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, s, st);
+        if (r != LSEFIT_OK) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return r;
+        }
+        LSEFIT_TRY(hipEventRecord(e0, st));
+        for (int i = 0; i < reps; ++i) enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, s, st);
+        LSEFIT_TRY(hipEventRecord(e1, st));
+        LSEFIT_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        LSEFIT_TRY(hipEventElapsedTime(&ms, e0, e1));
+        const double per = ms / reps;
+        if (per < best) {
+            best = per;
+            best_s = s;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    plan->sched = best_s;
+    plan->drop_graph();
+    if (best_ms_out) *best_ms_out = best;
+    return LSEFIT_OK;
+}
+
+lsefit_status lsefit_timing_enable(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.enabled = enable != 0;
+    return LSEFIT_OK;
+}
+
+lsefit_status lsefit_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    for (int k = 0; k < kTimeKinds; ++k) {
+        for (auto& p : g_timing.pending[k]) {
+            hipEventSynchronize(p.second);
+            g_timing.pool.push_back(p.first);
+            g_timing.pool.push_back(p.second);
+        }
+        g_timing.pending[k].clear();
+        g_timing.total_ms[k] = 0.0;
+        g_timing.launches[k] = 0;
+    }
+    return LSEFIT_OK;
+}
+
+lsefit_status lsefit_timing_read(int32_t kind, double* total_ms, int64_t* launches) {
+    if (kind < 0 || kind >= kTimeKinds || !total_ms || !launches) return LSEFIT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    for (auto& p : g_timing.pending[kind]) {
+        if (hipEventSynchronize(p.second) != hipSuccess) return LSEFIT_ERR_DEVICE;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess) return LSEFIT_ERR_DEVICE;
+        g_timing.total_ms[kind] += ms;
+        g_timing.launches[kind] += 1;
+        g_timing.pool.push_back(p.first);
+        g_timing.pool.push_back(p.second);
+    }
+    g_timing.pending[kind].clear();
+    *total_ms = g_timing.total_ms[kind];
+    *launches = g_timing.launches[kind];
+    return LSEFIT_OK;
+}
+
+void fit_plan_destroy(lsefit_plan* plan) {
+    if (!plan) return;
+    plan->drop_graph();
+    if (plan->cap_stream) hipStreamDestroy(plan->cap_stream);
+    if (plan->ws) hipFree(plan->ws);
+    delete plan;
+}
+
+}  // extern "C"

@@ -1,0 +1,278 @@
+// Device-side building blocks of the moment-pass least-squares fit (gfx950).
+//
+// Everything here runs inside the kernels (kernels_impl.hpp, dispatch.hip): the per-fit table
+// of CSR segments, the balanced tile walk of the persistent streaming grid,
+// the wave-level float64 reduction, the range map (c, s), elimination with
+// partial pivoting on the Hankel normal matrix and the change of basis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lsefit.h"
+
+namespace lsefit {
+
+constexpr int kWave = 64;
+constexpr int kMaxDeg = LSEFIT_MAX_DEGREE;
+
+// Per-wave partial sums of one degree-m segment: S_1..S_2m then T_0..T_m.
+__host__ __device__ constexpr int nacc(int m) { return 3 * m + 1; }
+
+// Per-fit record kept in the workspace (float64 slots), for a call whose
+// largest degree is M:
+//   [0] c   [1] s   [2 .. 2+2M] S_0..S_2M   [3+2M .. 3+3M] T_0..T_M
+//   [4+3M .. 4+4M] b_0..b_M (t-basis solution)   [5+4M .. 5+5M] lambda_0..lambda_M
+__host__ __device__ constexpr int rec_len(int M) { return 6 + 5 * M; }
+__host__ __device__ constexpr int rec_S(int) { return 2; }
+__host__ __device__ constexpr int rec_T(int M) { return 3 + 2 * M; }
+__host__ __device__ constexpr int rec_b(int M) { return 4 + 3 * M; }
+__host__ __device__ constexpr int rec_lam(int M) { return 5 + 4 * M; }
+
+// The fits of one call: CSR offsets (NULL for a single fit of n_single
+// points) and per-fit degrees (NULL for one degree for all).
+struct FitDesc {
+    const int64_t* offsets;
+    const int32_t* degrees;
+    int64_t n_single;
+    int64_t batch;
+    int32_t degree;   // uniform degree, or the largest degree allowed
+};
+
+__device__ inline bool is_single(const FitDesc& d) { return d.offsets == nullptr; }
+
+__device__ inline int64_t fit_lo(const FitDesc& d, int64_t f) { return d.offsets ? d.offsets[f] : 0; }
+__device__ inline int64_t fit_hi(const FitDesc& d, int64_t f) { return d.offsets ? d.offsets[f + 1] : d.n_single; }
+__device__ inline int fit_deg(const FitDesc& d, int64_t f) { return d.degrees ? d.degrees[f] : d.degree; }
+
+// Workspace regions (device pointers carved out of the caller's buffer).
+struct Work {
+    int64_t* tile_start;  // [B+1] first tile of each fit; tile_start[B] = number of tiles
+    int32_t* pstatus;     // [B] status found while building the tile table
+    double* rec;          // [B * rec_len(M)]
+    double* part;         // [(W + B) * nacc(M)] per-(wave, fit) partial sums (batched) or
+                          // per-block partial sums (single fit)
+};
+
+// ---------------------------------------------------------------------------
+// wave-level reductions (fixed butterfly: every lane ends with the same bits,
+// since each step adds the same two operands in either order)
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+__device__ inline double wave_min(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ inline int wave_id_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
+__device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// ---------------------------------------------------------------------------
+// range map: (c, s) from the sampled extremes of x.  s is the power of two at
+// or above the half-range; c is the mid-range on a grid of s/8 (0 when small
+// against the half-range), rounded to float32 so that x - c is formed the same
+// way by float32 and float64 passes.  Any (c, s) gives the same minimiser.
+// ---------------------------------------------------------------------------
+__device__ inline void snap_range(double lo, double hi, double* c_out, double* s_out) {
+    if (!(lo <= hi)) {  // no finite sample
+        *c_out = 0.0;
+        *s_out = 1.0;
+        return;
+    }
+    double half = 0.5 * hi - 0.5 * lo;
+    double mid = 0.5 * hi + 0.5 * lo;
+    double s = 1.0, c = mid;
+    if (half > 0.0) {
+        int e;
+        double f = frexp(half, &e);      // half = f 2^e, f in [0.5, 1)
+        s = ldexp(1.0, f == 0.5 ? e - 1 : e);
+        double q = ldexp(s, -3);
+        c = fabs(mid) < ldexp(half, -6) ? 0.0 : rint(mid / q) * q;
+    }
+    *c_out = (double)(float)c;
+    *s_out = s;
+}
+
+// ---------------------------------------------------------------------------
+// the balanced tile walk of the persistent grid.  Fit f owns tiles
+// tile_start[f] .. tile_start[f+1]-1 (tile points each, the last one ragged);
+// wave w owns tiles floor(w NT / W) .. floor((w+1) NT / W) - 1 and streams the
+// part of each fit inside that range as one segment.  (w, f) pairs that share
+// a tile map one-to-one onto partial slots w + f.
+// ---------------------------------------------------------------------------
+template <class Fn>
+__device__ inline void walk_segments(const FitDesc& d, const int64_t* __restrict__ tile_start, int64_t tile,
+                                     int64_t wave, int64_t W, Fn&& fn) {
+    const int64_t NT = tile_start[d.batch];
+    const int64_t t0 = wave * NT / W;
+    const int64_t t1 = (wave + 1) * NT / W;
+    if (t0 >= t1) return;
+    int64_t lo = 0, hi = d.batch;   // largest f with tile_start[f] <= t0
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (tile_start[mid] <= t0) lo = mid;
+        else hi = mid;
+    }
+    int64_t f = lo;
+    int64_t t = t0;
+    while (t < t1) {
+        const int64_t fs = tile_start[f], fe = tile_start[f + 1];
+        if (fe <= t) {
+            ++f;
+            continue;
+        }
+        const int64_t te = fe < t1 ? fe : t1;
+        const int64_t base = fit_lo(d, f);
+        const int64_t end = fit_hi(d, f);
+        const int64_t plo = base + (t - fs) * tile;
+        int64_t phi = base + (te - fs) * tile;
+        if (phi > end) phi = end;
+        fn(f, plo, phi, wave + f);
+        t = te;
+        ++f;
+    }
+}
+
+// the wave that owns tile t (inverse of the split above)
+__device__ inline int64_t wave_of_tile(int64_t t, int64_t NT, int64_t W) { return ((t + 1) * W - 1) / NT; }
+
+// whether wave w owns at least one tile (with more waves than tiles some own none
+// and write no partial)
+__device__ inline bool wave_owns_tiles(int64_t w, int64_t NT, int64_t W) { return w * NT / W < (w + 1) * NT / W; }
+
+// ---------------------------------------------------------------------------
+// Gaussian elimination with partial pivoting on A_jk = S_(j+k) (Sec. II).
+// Pivot: first row of largest magnitude.  Singular when a pivot is at most
+// 2^-40 max|A|.  N = m + 1; several right-hand sides are eliminated together.
+// ---------------------------------------------------------------------------
+template <int N, int R>
+__device__ inline int hankel_solve(const double* S, const double (&rhs)[R][N], double (&X)[R][N]) {
+    double A[N][N + R];
+    double amax = 0.0;
+    bool finite = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            A[j][k] = S[j + k];
+            finite = finite && isfinite(A[j][k]);
+            amax = fmax(amax, fabs(A[j][k]));
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            A[j][N + r] = rhs[r][j];
+            finite = finite && isfinite(rhs[r][j]);
+        }
+    }
+    if (!finite) return LSEFIT_ERR_NONFINITE;
+    const double tiny = ldexp(amax, -40);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        int p = k;
+        double best = fabs(A[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            double v = fabs(A[r][k]);
+            if (v > best) {
+                best = v;
+                p = r;
+            }
+        }
+        if (!(best > tiny)) return LSEFIT_ERR_SINGULAR;
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            if (r == p) {
+#pragma unroll
+                for (int c = 0; c < N + R; ++c) {
+                    double tmp = A[k][c];
+                    A[k][c] = A[r][c];
+                    A[r][c] = tmp;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            const double l = A[r][k] / A[k][k];
+#pragma unroll
+            for (int c = k; c < N + R; ++c) A[r][c] -= l * A[k][c];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) {
+            double acc = A[i][N + r];
+#pragma unroll
+            for (int c = i + 1; c < N; ++c) acc -= A[i][c] * X[r][c];
+            X[r][i] = acc / A[i][i];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (!isfinite(X[r][i])) return LSEFIT_ERR_NONFINITE;
+    return LSEFIT_OK;
+}
+
+// t-basis b (t = (x - c)/s) to x-basis a: a_k = sum_{j>=k} b_j C(j,k) (-c)^(j-k) s^-j
+template <int N>
+__device__ inline void to_x_basis(const double (&b)[N], double c, double s, double (&a)[N]) {
+    const double inv_s = 1.0 / s;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double acc = 0.0;
+        double binom = 1.0;      // C(j, k), starting at j = k
+        double cpow = 1.0;       // (-c)^(j-k)
+        double spow = 1.0;       // s^-j
+#pragma unroll
+        for (int i = 0; i < k; ++i) spow *= inv_s;
+#pragma unroll
+        for (int j = k; j < N; ++j) {
+            acc += b[j] * binom * cpow * spow;
+            binom = binom * (double)(j + 1) / (double)(j + 1 - k);
+            cpow *= -c;
+            spow *= inv_s;
+        }
+        a[k] = acc;
+    }
+}
+
+// (M^T g)_j = sum_{k<=j} C(j,k) (-c)^(j-k) s^-j g_k : the adjoint of to_x_basis
+template <int N>
+__device__ inline void to_t_basis_adjoint(const double (&g)[N], double c, double s, double (&gt)[N]) {
+    const double inv_s = 1.0 / s;
+    double spow = 1.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double acc = 0.0;
+        double binom = 1.0;   // C(j, k), k from 0
+        double cpow_jk[N];
+        // (-c)^(j-k) for k = j down to 0
+        double cp = 1.0;
+#pragma unroll
+        for (int k = j; k >= 0; --k) {
+            cpow_jk[k] = cp;
+            cp *= -c;
+        }
+#pragma unroll
+        for (int k = 0; k <= j; ++k) {
+            acc += binom * cpow_jk[k] * g[k];
+            binom = binom * (double)(j - k) / (double)(k + 1);
+        }
+        gt[j] = acc * spow;
+        spow *= inv_s;
+    }
+}
+
+}  // namespace lsefit

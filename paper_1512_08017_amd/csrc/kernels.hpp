@@ -1,0 +1,73 @@
+// Host-side launchers of the streaming and solve kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace lsefit {
+
+struct Launch {
+    int64_t waves;        // total waves of the persistent grid
+    int32_t wpb;          // waves per block
+    int64_t tile;         // points per tile
+    int32_t unroll;       // vector loads in flight per lane and array
+};
+
+enum CombineMode { kNoFinish = -1, kMomentsOnly = 0, kSolve = 1, kRefine = 2 };
+
+// What happens once the partial sums of a fit are complete: write its power
+// sums (kMomentsOnly), solve (kSolve), or apply the refinement correction
+// (kRefine).  Passed to the combine and finish kernels.
+struct Finish {
+    int mode;
+    double* coef;          // [B * coef_stride] x-basis coefficients
+    int32_t coef_stride;
+    int write_b;           // also write the t-basis solution after a_0..a_m
+    int32_t* status;       // [B]
+    double* moments_out;   // nullable: [3m+4] = c, s, S_0..S_2m, T_0..T_m
+};
+
+// Range of a single fit: given (c, s), or derived by the streaming kernel itself.
+struct RangeArg {
+    int mode;   // lsefit_range_mode
+    double c, s;
+};
+
+// Tile table, plan status and (for a given range) c, s of every fit.
+hipError_t launch_plan(const FitDesc& d, const Work& w, int maxM, int64_t tile, bool range_given, double c,
+                       double s, hipStream_t st);
+
+// Batched: sampled range -> (c, s) per fit (a wave per fit).
+hipError_t launch_range(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, hipStream_t st);
+
+// The power-sum pass: per-(wave, fit) partial sums (batched) or per-block
+// partial sums (single fit) into w.part.
+hipError_t launch_moments(const FitDesc& d, const Work& w, int maxM, int prec, int dtype, const void* x,
+                          const void* y, const Launch& L, int mis, const RangeArg& ra, hipStream_t st);
+
+// Single fit: sum the block partials and finish (mode of fz).
+hipError_t launch_finish_single(const FitDesc& d, const Work& w, int maxM, int64_t blocks, const Finish& fz,
+                                hipStream_t st);
+
+// Fixed-order sum of the partial slots of each fit, then (mode) write the power
+// sums, solve, or apply the refinement correction.  by_block: one block per fit
+// (few fits), else one thread per fit.
+hipError_t launch_combine(const FitDesc& d, const Work& w, int maxM, const Launch& L, bool by_block,
+                          const Finish& fz, hipStream_t st);
+
+// Solve one fit from caller-provided power sums [c, s, S_0..S_2m, T_0..T_m].
+hipError_t launch_solve_moments(const double* moments, const Work& w, int m, int maxM, double* coef,
+                                int32_t* status, hipStream_t st);
+
+// Refinement pass: per-(wave, fit) partial sums of t^j (y - f(t)) into w.part.
+hipError_t launch_refine(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, const void* y,
+                         const Launch& L, int mis, hipStream_t st);
+
+// Adjoint: lambda per fit, then dL/dx, dL/dy per point.
+hipError_t launch_adjoint(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, const void* y,
+                          const double* grad_coef, int32_t coef_stride, void* gx, void* gy, const Launch& L,
+                          int mis, hipStream_t st);
+
+}  // namespace lsefit

@@ -1,0 +1,918 @@
+// Kernels of the moment-pass least-squares fit for gfx950 (CDNA4, wave64).
+//
+// The power sums S_p = sum t^p and T_j = sum t^j y of Sec. II are one
+// HBM-bound streaming pass: each wave of a persistent grid owns a balanced,
+// contiguous share of the points, loads x and y with 16-byte vector loads,
+// forms t = (x - c)/s and its powers by repeated multiplication, accumulates
+// per lane, reduces across the wave with a fixed butterfly and writes one
+// partial per (wave, fit).  A second kernel sums the partials of each fit in
+// wave order and solves the Hankel normal system (Gaussian elimination with
+// partial pivoting, end of Sec. II) in float64.
+#pragma once
+
+#include "kernels.hpp"
+#include "launchers.hpp"
+
+#include <type_traits>
+
+namespace lsefit {
+
+template <typename In>
+struct VecOf;
+template <>
+struct VecOf<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int W = 4;
+};
+template <>
+struct VecOf<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int W = 2;
+};
+
+template <typename V>
+__device__ inline V ld_stream(const V* p) {
+    return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ inline T ld_scalar(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+
+// ---------------------------------------------------------------------------
+// per-lane accumulators
+// ---------------------------------------------------------------------------
+
+// float64 form: t, powers and sums in float64 (full-rate on CDNA4 vector ALUs).
+template <int M>
+struct AccF64 {
+    double S[2 * M];  // S_1..S_2M
+    double T[M + 1];  // T_0..T_M
+    double inv_s, nc;
+    __device__ inline void init(double c, double is) {
+#pragma unroll
+        for (int k = 0; k < 2 * M; ++k) S[k] = 0.0;
+#pragma unroll
+        for (int j = 0; j <= M; ++j) T[j] = 0.0;
+        inv_s = is;
+        nc = -c * is;
+    }
+    __device__ inline void point(double xv, double yv) {
+        const double t = fma(xv, inv_s, nc);
+        double p = t;
+        T[0] += yv;
+        S[0] += p;
+        T[1] = fma(yv, p, T[1]);
+#pragma unroll
+        for (int k = 2; k <= 2 * M; ++k) {
+            p *= t;
+            S[k - 1] += p;
+            if (k <= M) T[k] = fma(yv, p, T[k]);
+        }
+    }
+    template <typename V, int VW>
+    __device__ inline void vec(const V& xv, const V& yv) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) point((double)xv[e], (double)yv[e]);
+    }
+    __device__ inline void scalar(double xv, double yv) { point(xv, yv); }
+    __device__ inline void out(double (&v)[nacc(M)]) const {
+#pragma unroll
+        for (int k = 0; k < 2 * M; ++k) v[k] = S[k];
+#pragma unroll
+        for (int j = 0; j <= M; ++j) v[2 * M + j] = T[j];
+    }
+};
+
+// compensated float32 form: t and powers in float32; the sums of a group of
+// points (one 16-byte vector) are plain float32 and are folded into (sum,
+// compensation) pairs by Kahan's method once per group.
+template <int M>
+struct AccF32C {
+    float S[2 * M], cS[2 * M];
+    float T[M + 1], cT[M + 1];
+    float inv_s, nc;
+    __device__ static inline void kahan(float& s, float& c, float v) {
+        const float yv = v - c;
+        const float t = s + yv;
+        c = (t - s) - yv;
+        s = t;
+    }
+    __device__ inline void init(double c, double is) {
+#pragma unroll
+        for (int k = 0; k < 2 * M; ++k) S[k] = cS[k] = 0.0f;
+#pragma unroll
+        for (int j = 0; j <= M; ++j) T[j] = cT[j] = 0.0f;
+        inv_s = (float)is;
+        nc = (float)(-c * is);
+    }
+    template <int G>
+    __device__ inline void group(const float (&xs)[G], const float (&ys)[G]) {
+        float t[G], p[G];
+#pragma unroll
+        for (int e = 0; e < G; ++e) {
+            t[e] = fmaf(xs[e], inv_s, nc);
+            p[e] = t[e];
+        }
+        float g = ys[0];
+#pragma unroll
+        for (int e = 1; e < G; ++e) g += ys[e];
+        kahan(T[0], cT[0], g);
+#pragma unroll
+        for (int k = 1; k <= 2 * M; ++k) {
+            if (k > 1) {
+#pragma unroll
+                for (int e = 0; e < G; ++e) p[e] *= t[e];
+            }
+            float gs = p[0];
+#pragma unroll
+            for (int e = 1; e < G; ++e) gs += p[e];
+            kahan(S[k - 1], cS[k - 1], gs);
+            if (k <= M) {
+                float gt = ys[0] * p[0];
+#pragma unroll
+                for (int e = 1; e < G; ++e) gt = fmaf(ys[e], p[e], gt);
+                kahan(T[k], cT[k], gt);
+            }
+        }
+    }
+    template <typename V, int VW>
+    __device__ inline void vec(const V& xv, const V& yv) {
+        float xs[VW], ys[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            xs[e] = xv[e];
+            ys[e] = yv[e];
+        }
+        group<VW>(xs, ys);
+    }
+    __device__ inline void scalar(float xv, float yv) {
+        float xs[1] = {xv}, ys[1] = {yv};
+        group<1>(xs, ys);
+    }
+    __device__ inline void out(double (&v)[nacc(M)]) const {
+#pragma unroll
+        for (int k = 0; k < 2 * M; ++k) v[k] = (double)S[k] - (double)cS[k];
+#pragma unroll
+        for (int j = 0; j <= M; ++j) v[2 * M + j] = (double)T[j] - (double)cT[j];
+    }
+};
+
+// refinement: r = y - sum_j b_j t^j and R_j = sum t^j r, all float64.
+template <int M>
+struct AccRefine {
+    double R[M + 1];
+    double b[M + 1];
+    double inv_s, nc;
+    __device__ inline void init(double c, double is, const double* bb) {
+#pragma unroll
+        for (int j = 0; j <= M; ++j) {
+            R[j] = 0.0;
+            b[j] = bb[j];
+        }
+        inv_s = is;
+        nc = -c * is;
+    }
+    __device__ inline void point(double xv, double yv) {
+        const double t = fma(xv, inv_s, nc);
+        double f = b[M];
+#pragma unroll
+        for (int j = M - 1; j >= 0; --j) f = fma(f, t, b[j]);
+        const double r = yv - f;
+        double p = t;
+        R[0] += r;
+        R[1] = fma(p, r, R[1]);
+#pragma unroll
+        for (int j = 2; j <= M; ++j) {
+            p *= t;
+            R[j] = fma(p, r, R[j]);
+        }
+    }
+    template <typename V, int VW>
+    __device__ inline void vec(const V& xv, const V& yv) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) point((double)xv[e], (double)yv[e]);
+    }
+    __device__ inline void scalar(double xv, double yv) { point(xv, yv); }
+};
+
+// ---------------------------------------------------------------------------
+// one wave streams points [lo, hi) of x and y into an accumulator.  `mis` is
+// the common misalignment (in elements, modulo the vector width) of the base
+// pointers, or -1 when they differ (then every load is scalar).
+// ---------------------------------------------------------------------------
+template <int U, typename In, class Acc>
+__device__ inline void stream_segment(const In* __restrict__ x, const In* __restrict__ y, int64_t lo, int64_t hi,
+                                      int mis, Acc& acc) {
+    constexpr int VW = VecOf<In>::W;
+    using V = typename VecOf<In>::type;
+    const int lane = lane_id();
+    if (mis >= 0) {
+        int64_t a = lo + (int64_t)((VW - (int)((lo + mis) % VW)) % VW);
+        if (a > hi) a = hi;
+        const int64_t nv = (hi - a) / VW;
+        const int64_t b = a + nv * VW;
+        if (lane < a - lo) acc.scalar(ld_scalar(x + lo + lane), ld_scalar(y + lo + lane));
+        const V* __restrict__ xv = reinterpret_cast<const V*>(x + a);
+        const V* __restrict__ yv = reinterpret_cast<const V*>(y + a);
+        int64_t j = lane;
+        const int64_t rounds = nv / (kWave * U);
+        for (int64_t r = 0; r < rounds; ++r) {
+            V xs[U], ys[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                xs[u] = ld_stream(xv + j + u * kWave);
+                ys[u] = ld_stream(yv + j + u * kWave);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc.template vec<V, VW>(xs[u], ys[u]);
+            j += (int64_t)kWave * U;
+        }
+        for (; j < nv; j += kWave) acc.template vec<V, VW>(ld_stream(xv + j), ld_stream(yv + j));
+        if (lane < hi - b) acc.scalar(ld_scalar(x + b + lane), ld_scalar(y + b + lane));
+    } else {
+        for (int64_t i = lo + lane; i < hi; i += kWave) acc.scalar(ld_scalar(x + i), ld_scalar(y + i));
+    }
+}
+
+// run body.template operator()<m>() for the runtime degree m (1 <= m <= MAXM)
+template <int MAXM, class Body>
+__device__ inline void dispatch_degree(int m, Body&& body) {
+    switch (m) {
+        case 1: if constexpr (MAXM >= 1) body.template operator()<1>(); break;
+        case 2: if constexpr (MAXM >= 2) body.template operator()<2>(); break;
+        case 3: if constexpr (MAXM >= 3) body.template operator()<3>(); break;
+        case 4: if constexpr (MAXM >= 4) body.template operator()<4>(); break;
+        case 5: if constexpr (MAXM >= 5) body.template operator()<5>(); break;
+        case 6: if constexpr (MAXM >= 6) body.template operator()<6>(); break;
+        case 7: if constexpr (MAXM >= 7) body.template operator()<7>(); break;
+        case 8: if constexpr (MAXM >= 8) body.template operator()<8>(); break;
+        default: break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-fit combine and solve
+// ---------------------------------------------------------------------------
+template <int M, int MAXM>
+__device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, const double (&v)[nacc(M)],
+                                  const Finish& fz) {
+    constexpr int N = M + 1;
+    constexpr int rl = rec_len(MAXM);
+    double* r = w.rec + f * rl;
+    const double c = r[0], s = r[1];
+    double* a_out = fz.coef + f * (int64_t)fz.coef_stride;
+    double S[2 * M + 1];
+    double b[1][N], a[N];
+    int st;
+    if (fz.mode == kRefine) {
+#pragma unroll
+        for (int k = 0; k <= 2 * M; ++k) S[k] = r[rec_S(MAXM) + k];
+        double R[1][N], delta[1][N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) R[0][j] = v[j];
+        st = hankel_solve<N, 1>(S, R, delta);
+#pragma unroll
+        for (int j = 0; j < N; ++j) b[0][j] = r[rec_b(MAXM) + j] + delta[0][j];
+    } else {
+        S[0] = (double)(fit_hi(d, f) - fit_lo(d, f));
+#pragma unroll
+        for (int k = 1; k <= 2 * M; ++k) S[k] = v[k - 1];
+        double T[1][N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) T[0][j] = v[2 * M + j];
+#pragma unroll
+        for (int k = 0; k <= 2 * M; ++k) r[rec_S(MAXM) + k] = S[k];
+#pragma unroll
+        for (int j = 0; j < N; ++j) r[rec_T(MAXM) + j] = T[0][j];
+        if (fz.moments_out) {
+            fz.moments_out[0] = c;
+            fz.moments_out[1] = s;
+#pragma unroll
+            for (int k = 0; k <= 2 * M; ++k) fz.moments_out[2 + k] = S[k];
+#pragma unroll
+            for (int j = 0; j < N; ++j) fz.moments_out[3 + 2 * M + j] = T[0][j];
+        }
+        if (fz.mode == kMomentsOnly) return;
+        st = hankel_solve<N, 1>(S, T, b);
+    }
+    if (st == LSEFIT_OK) {
+        to_x_basis<N>(b[0], c, s, a);
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            if (!isfinite(a[k])) st = LSEFIT_ERR_NONFINITE;
+    }
+    if (st != LSEFIT_OK) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) a[k] = b[0][k] = NAN;
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        r[rec_b(MAXM) + k] = b[0][k];
+        a_out[k] = a[k];
+        if (fz.write_b) a_out[N + k] = b[0][k];
+    }
+    w.pstatus[f] = st;
+    fz.status[f] = st;
+}
+
+// a fit that never reached elimination: NaN coefficients (all coef_stride of
+// them when the degree itself is out of range) and its status
+template <int MAXM>
+__device__ inline void fail_fit(const FitDesc& d, const Work& w, int64_t f, const Finish& fz, int st) {
+    const int m = fit_deg(d, f);
+    const bool valid = m >= 1 && m <= MAXM;
+    const int n = valid ? m + 1 : fz.coef_stride;
+    double* a_out = fz.coef + f * (int64_t)fz.coef_stride;
+    for (int k = 0; k < n; ++k) a_out[k] = NAN;
+    if (fz.write_b && valid)
+        for (int k = 0; k < n; ++k) a_out[n + k] = NAN;
+    fz.status[f] = st;
+}
+
+// the threads of one block sum the partial slots of fit f in a fixed order
+// (strided per thread, butterfly per wave, waves in order), then one thread
+// finishes the fit
+template <int MAXM>
+__device__ inline void block_combine_fit(const FitDesc& d, const Work& w, int64_t f, int64_t W, const Finish& fz) {
+    constexpr int stride = nacc(MAXM);
+    __shared__ double sh[4][stride];
+    const int pst = w.pstatus[f];
+    if (pst != LSEFIT_OK) {
+        if (threadIdx.x == 0 && fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, f, fz, pst);
+        return;
+    }
+    const int nw = blockDim.x / kWave;
+    const int64_t NT = w.tile_start[d.batch];
+    const int64_t ts = w.tile_start[f], te = w.tile_start[f + 1];
+    const int64_t w0 = wave_of_tile(ts, NT, W), w1 = wave_of_tile(te - 1, NT, W);
+    auto body = [&]<int M>() {
+        constexpr int K = nacc(M);
+        const int nk = fz.mode == kRefine ? M + 1 : K;
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = 0.0;
+        for (int64_t wv = w0 + threadIdx.x; wv <= w1; wv += blockDim.x) {
+            if (!wave_owns_tiles(wv, NT, W)) continue;
+            const double* p = w.part + (wv + f) * stride;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k < nk) v[k] += p[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+        const int wv = wave_id_in_block();
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) sh[wv][k] = v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                double acc = sh[0][k];
+                for (int i = 1; i < nw; ++i) acc += sh[i][k];
+                v[k] = acc;
+            }
+            finish_fit<M, MAXM>(d, w, f, v, fz);
+        }
+        __syncthreads();
+    };
+    dispatch_degree<MAXM>(fit_deg(d, f), body);
+}
+
+// ---------------------------------------------------------------------------
+// single fit: every block of the streaming grid derives (c, s) itself, from the
+// same sample (kSingleRangeSamples evenly strided points, first and last
+// included; exact min/max, so the result does not depend on the block shape)
+// ---------------------------------------------------------------------------
+constexpr int kSingleRangeSamples = 256;
+
+template <typename In>
+__device__ inline void single_range(const FitDesc& d, const Work& w, const In* __restrict__ x, const RangeArg& ra,
+                                    double* c_out, double* inv_s_out) {
+    __shared__ double smin[4], smax[4];
+    double c = ra.c, s = ra.s;
+    if (ra.mode == LSEFIT_RANGE_AUTO) {
+        const int64_t n = d.n_single;
+        const int64_t K = n < kSingleRangeSamples ? n : kSingleRangeSamples;
+        double lo = INFINITY, hi = -INFINITY;
+        double v[kSingleRangeSamples / kWave];
+#pragma unroll
+        for (int j = 0; j < kSingleRangeSamples / kWave; ++j) {
+            const int64_t i = threadIdx.x + (int64_t)j * blockDim.x;
+            v[j] = NAN;
+            if (i < K) v[j] = (double)x[K == 1 ? 0 : i * (n - 1) / (K - 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < kSingleRangeSamples / kWave; ++j) {
+            if (isfinite(v[j])) {
+                lo = fmin(lo, v[j]);
+                hi = fmax(hi, v[j]);
+            }
+        }
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        if (lane_id() == 0) {
+            smin[wave_id_in_block()] = lo;
+            smax[wave_id_in_block()] = hi;
+        }
+        __syncthreads();
+        const int nw = blockDim.x / kWave;
+        lo = smin[0];
+        hi = smax[0];
+        for (int i = 1; i < nw; ++i) {
+            lo = fmin(lo, smin[i]);
+            hi = fmax(hi, smax[i]);
+        }
+        snap_range(lo, hi, &c, &s);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        w.rec[0] = c;
+        w.rec[1] = s;
+        w.pstatus[0] = LSEFIT_OK;
+    }
+    *c_out = c;
+    *inv_s_out = 1.0 / s;
+}
+
+// single fit: the waves of a block add their wave sums in order into one
+// partial per block (part[blockIdx.x]); blocks whose waves own no tiles write zeros
+template <int K, int STRIDE>
+__device__ inline void single_block_partial(const Work& w, const double (&v)[K]) {
+    __shared__ double sh[4][STRIDE];
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[wave_id_in_block()][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int nw = blockDim.x / kWave;
+        double acc = sh[0][threadIdx.x];
+        for (int i = 1; i < nw; ++i) acc += sh[i][threadIdx.x];
+        w.part[(int64_t)blockIdx.x * STRIDE + threadIdx.x] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// power-sum pass
+// ---------------------------------------------------------------------------
+template <int MAXM, int PREC, typename In, int U>
+__global__ void __launch_bounds__(256)
+    k_moments(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t tile, int64_t W,
+              int mis, RangeArg ra) {
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    constexpr int stride = nacc(MAXM);
+    constexpr int rl = rec_len(MAXM);
+    if (is_single(d)) {
+        double c, inv_s;
+        single_range(d, w, x, ra, &c, &inv_s);
+        auto body = [&]<int M>() {
+            using Acc = std::conditional_t<PREC == LSEFIT_PREC_F64, AccF64<M>, AccF32C<M>>;
+            double v[nacc(M)];
+#pragma unroll
+            for (int k = 0; k < nacc(M); ++k) v[k] = 0.0;
+            const int64_t NT = (d.n_single + tile - 1) / tile;
+            const int64_t t0 = wave * NT / W, t1 = (wave + 1) * NT / W;
+            if (t0 < t1) {
+                Acc acc;
+                acc.init(c, inv_s);
+                const int64_t hi = t1 * tile < d.n_single ? t1 * tile : d.n_single;
+                stream_segment<U>(x, y, t0 * tile, hi, mis, acc);
+                acc.out(v);
+#pragma unroll
+                for (int k = 0; k < nacc(M); ++k) v[k] = wave_sum(v[k]);
+            }
+            single_block_partial<nacc(M), stride>(w, v);
+        };
+        dispatch_degree<MAXM>(d.degree, body);
+        return;
+    }
+    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
+        if (w.pstatus[f] != LSEFIT_OK) return;
+        const double c = w.rec[f * rl + 0];
+        const double inv_s = 1.0 / w.rec[f * rl + 1];
+        double* __restrict__ out = w.part + slot * stride;
+        auto body = [&]<int M>() {
+            using Acc = std::conditional_t<PREC == LSEFIT_PREC_F64, AccF64<M>, AccF32C<M>>;
+            Acc acc;
+            acc.init(c, inv_s);
+            stream_segment<U>(x, y, lo, hi, mis, acc);
+            double v[nacc(M)];
+            acc.out(v);
+#pragma unroll
+            for (int k = 0; k < nacc(M); ++k) v[k] = wave_sum(v[k]);
+            if (lane_id() == 0) {
+#pragma unroll
+                for (int k = 0; k < nacc(M); ++k) out[k] = v[k];
+            }
+        };
+        dispatch_degree<MAXM>(fit_deg(d, f), body);
+    });
+}
+
+template <int MAXM, typename In, int U>
+__global__ void __launch_bounds__(256)
+    k_refine(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t tile, int64_t W,
+             int mis) {
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    constexpr int stride = nacc(MAXM);
+    constexpr int rl = rec_len(MAXM);
+    if (is_single(d)) {
+        const double* r = w.rec;
+        const bool ok = w.pstatus[0] == LSEFIT_OK;
+        const double c = r[0];
+        const double inv_s = 1.0 / r[1];
+        auto body = [&]<int M>() {
+            double v[M + 1];
+#pragma unroll
+            for (int k = 0; k <= M; ++k) v[k] = 0.0;
+            const int64_t NT = (d.n_single + tile - 1) / tile;
+            const int64_t t0 = wave * NT / W, t1 = (wave + 1) * NT / W;
+            if (ok && t0 < t1) {
+                AccRefine<M> acc;
+                acc.init(c, inv_s, r + rec_b(MAXM));
+                const int64_t hi = t1 * tile < d.n_single ? t1 * tile : d.n_single;
+                stream_segment<U>(x, y, t0 * tile, hi, mis, acc);
+#pragma unroll
+                for (int k = 0; k <= M; ++k) v[k] = wave_sum(acc.R[k]);
+            }
+            single_block_partial<M + 1, stride>(w, v);
+        };
+        dispatch_degree<MAXM>(d.degree, body);
+        return;
+    }
+    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
+        if (w.pstatus[f] != LSEFIT_OK) return;
+        const double* r = w.rec + f * rl;
+        const double c = r[0];
+        const double inv_s = 1.0 / r[1];
+        double* __restrict__ out = w.part + slot * stride;
+        auto body = [&]<int M>() {
+            AccRefine<M> acc;
+            acc.init(c, inv_s, r + rec_b(MAXM));
+            stream_segment<U>(x, y, lo, hi, mis, acc);
+            double v[M + 1];
+#pragma unroll
+            for (int k = 0; k <= M; ++k) v[k] = wave_sum(acc.R[k]);
+            if (lane_id() == 0) {
+#pragma unroll
+                for (int k = 0; k <= M; ++k) out[k] = v[k];
+            }
+        };
+        dispatch_degree<MAXM>(fit_deg(d, f), body);
+    });
+}
+
+// single fit: one block sums the G block partials (thread t takes blocks t,
+// t + blockDim, ...; then waves in order) and finishes the fit
+constexpr int kFinishThreads = 1024;
+
+template <int MAXM>
+__global__ void __launch_bounds__(kFinishThreads) k_finish_single(FitDesc d, Work w, int64_t G, Finish fz) {
+    constexpr int stride = nacc(MAXM);
+    __shared__ double sh[kFinishThreads / kWave][stride];
+    const int pst = w.pstatus[0];
+    if (pst != LSEFIT_OK) {
+        if (threadIdx.x == 0 && fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, 0, fz, pst);
+        return;
+    }
+    auto body = [&]<int M>() {
+        constexpr int K = nacc(M);
+        const int nk = fz.mode == kRefine ? M + 1 : K;
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = 0.0;
+        for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
+            const double* p = w.part + g * stride;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k < nk) v[k] += p[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) sh[wave_id_in_block()][k] = v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int nw = blockDim.x / kWave;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                double acc = sh[0][k];
+                for (int i = 1; i < nw; ++i) acc += sh[i][k];
+                v[k] = acc;
+            }
+            finish_fit<M, MAXM>(d, w, 0, v, fz);
+        }
+    };
+    dispatch_degree<MAXM>(d.degree, body);
+}
+
+template <int MAXM>
+__global__ void __launch_bounds__(256) k_combine_lane(FitDesc d, Work w, int64_t W, Finish fz) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= d.batch) return;
+    const int pst = w.pstatus[f];
+    if (pst != LSEFIT_OK) {
+        if (fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, f, fz, pst);
+        return;
+    }
+    constexpr int stride = nacc(MAXM);
+    const int64_t NT = w.tile_start[d.batch];
+    const int64_t ts = w.tile_start[f], te = w.tile_start[f + 1];
+    const int64_t w0 = wave_of_tile(ts, NT, W), w1 = wave_of_tile(te - 1, NT, W);
+    auto body = [&]<int M>() {
+        constexpr int K = nacc(M);
+        const int nk = fz.mode == kRefine ? M + 1 : K;
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = 0.0;
+        for (int64_t wv = w0; wv <= w1; ++wv) {
+            if (!wave_owns_tiles(wv, NT, W)) continue;
+            const double* p = w.part + (wv + f) * stride;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k < nk) v[k] += p[k];
+        }
+        finish_fit<M, MAXM>(d, w, f, v, fz);
+    };
+    dispatch_degree<MAXM>(fit_deg(d, f), body);
+}
+
+constexpr int kCombineThreads = 256;
+
+template <int MAXM>
+__global__ void __launch_bounds__(kCombineThreads) k_combine_block(FitDesc d, Work w, int64_t W, Finish fz) {
+    for (int64_t f = blockIdx.x; f < d.batch; f += gridDim.x) block_combine_fit<MAXM>(d, w, f, W, fz);
+}
+
+template <int M, int MAXM>
+__global__ void k_solve_moments(const double* __restrict__ mom, Work w, double* coef, int32_t* status) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    constexpr int N = M + 1;
+    constexpr int rl = rec_len(MAXM);
+    double* r = w.rec;
+    const double c = mom[0], s = mom[1];
+    double S[2 * M + 1], T[1][N], b[1][N], a[N];
+#pragma unroll
+    for (int k = 0; k <= 2 * M; ++k) S[k] = mom[2 + k];
+#pragma unroll
+    for (int j = 0; j < N; ++j) T[0][j] = mom[3 + 2 * M + j];
+    r[0] = c;
+    r[1] = s;
+#pragma unroll
+    for (int k = 0; k <= 2 * M; ++k) r[rec_S(MAXM) + k] = S[k];
+#pragma unroll
+    for (int j = 0; j < N; ++j) r[rec_T(MAXM) + j] = T[0][j];
+    int st = (s > 0.0 && isfinite(c) && isfinite(s)) ? hankel_solve<N, 1>(S, T, b) : LSEFIT_ERR_NONFINITE;
+    if (st == LSEFIT_OK) {
+        to_x_basis<N>(b[0], c, s, a);
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            if (!isfinite(a[k])) st = LSEFIT_ERR_NONFINITE;
+    }
+    if (st != LSEFIT_OK) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) a[k] = b[0][k] = NAN;
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        r[rec_b(MAXM) + k] = b[0][k];
+        coef[k] = a[k];
+        coef[N + k] = b[0][k];
+    }
+    (void)rl;
+    w.pstatus[0] = st;
+    status[0] = st;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+template <int MAXM>
+__global__ void __launch_bounds__(256)
+    k_adjoint_solve(FitDesc d, Work w, const double* __restrict__ gcoef, int32_t coef_stride) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= d.batch) return;
+    if (w.pstatus[f] != LSEFIT_OK) return;
+    constexpr int rl = rec_len(MAXM);
+    double* r = w.rec + f * rl;
+    auto body = [&]<int M>() {
+        constexpr int N = M + 1;
+        double g[N], gt[1][N], lam[1][N], S[2 * M + 1];
+#pragma unroll
+        for (int k = 0; k < N; ++k) g[k] = gcoef[f * (int64_t)coef_stride + k];
+        to_t_basis_adjoint<N>(g, r[0], r[1], gt[0]);
+#pragma unroll
+        for (int k = 0; k <= 2 * M; ++k) S[k] = r[rec_S(MAXM) + k];
+        const int st = hankel_solve<N, 1>(S, gt, lam);
+#pragma unroll
+        for (int k = 0; k < N; ++k) r[rec_lam(MAXM) + k] = st == LSEFIT_OK ? lam[0][k] : NAN;
+    };
+    dispatch_degree<MAXM>(fit_deg(d, f), body);
+}
+
+template <int M, typename In>
+struct AdjointPoint {
+    double b[M + 1], lam[M + 1];
+    double inv_s, nc;
+    __device__ inline void init(const double* r, int MAXM_) {
+        inv_s = 1.0 / r[1];
+        nc = -r[0] * inv_s;
+#pragma unroll
+        for (int j = 0; j <= M; ++j) {
+            b[j] = r[rec_b(MAXM_) + j];
+            lam[j] = r[rec_lam(MAXM_) + j];
+        }
+    }
+    __device__ inline void point(double xv, double yv, In& gx, In& gy) const {
+        const double t = fma(xv, inv_s, nc);
+        double f = b[M], df = 0.0, q = lam[M], dq = 0.0;
+#pragma unroll
+        for (int j = M - 1; j >= 0; --j) {
+            df = fma(df, t, f);
+            f = fma(f, t, b[j]);
+            dq = fma(dq, t, q);
+            q = fma(q, t, lam[j]);
+        }
+        const double rr = yv - f;
+        gx = (In)((dq * rr - q * df) * inv_s);
+        gy = (In)q;
+    }
+};
+
+template <int MAXM, typename In>
+__global__ void __launch_bounds__(256)
+    k_adjoint_stream(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ gx,
+                     In* __restrict__ gy, int64_t tile, int64_t W, int mis) {
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    constexpr int rl = rec_len(MAXM);
+    constexpr int VW = VecOf<In>::W;
+    using V = typename VecOf<In>::type;
+    const int lane = lane_id();
+    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t) {
+        if (w.pstatus[f] != LSEFIT_OK) {
+            for (int64_t i = lo + lane; i < hi; i += kWave) {
+                gx[i] = (In)NAN;
+                gy[i] = (In)NAN;
+            }
+            return;
+        }
+        const double* r = w.rec + f * rl;
+        auto body = [&]<int M>() {
+            AdjointPoint<M, In> P;
+            P.init(r, MAXM);
+            if (mis >= 0) {
+                int64_t a = lo + (int64_t)((VW - (int)((lo + mis) % VW)) % VW);
+                if (a > hi) a = hi;
+                const int64_t nv = (hi - a) / VW;
+                const int64_t b = a + nv * VW;
+                if (lane < a - lo) P.point((double)x[lo + lane], (double)y[lo + lane], gx[lo + lane], gy[lo + lane]);
+                const V* xv = reinterpret_cast<const V*>(x + a);
+                const V* yv = reinterpret_cast<const V*>(y + a);
+                V* gxv = reinterpret_cast<V*>(gx + a);
+                V* gyv = reinterpret_cast<V*>(gy + a);
+                for (int64_t j = lane; j < nv; j += kWave) {
+                    const V xs = ld_stream(xv + j), ys = ld_stream(yv + j);
+                    V ox, oy;
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) {
+                        In gxe, gye;
+                        P.point((double)xs[e], (double)ys[e], gxe, gye);
+                        ox[e] = gxe;
+                        oy[e] = gye;
+                    }
+                    __builtin_nontemporal_store(ox, gxv + j);
+                    __builtin_nontemporal_store(oy, gyv + j);
+                }
+                if (lane < hi - b) P.point((double)x[b + lane], (double)y[b + lane], gx[b + lane], gy[b + lane]);
+            } else {
+                for (int64_t i = lo + lane; i < hi; i += kWave) P.point((double)x[i], (double)y[i], gx[i], gy[i]);
+            }
+        };
+        dispatch_degree<MAXM>(fit_deg(d, f), body);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// per-degree launchers (explicitly instantiated once per largest degree)
+// ---------------------------------------------------------------------------
+inline int64_t blocks_for(const Launch& L) { return (L.waves + L.wpb - 1) / L.wpb; }
+
+template <int MAXM>
+template <int PREC, typename In>
+hipError_t Launchers<MAXM>::moments_t(const FitDesc& d, const Work& w, const void* x, const void* y,
+                                      const Launch& L, int mis, const RangeArg& ra, hipStream_t st) {
+    const dim3 grid(blocks_for(L)), block(L.wpb * kWave);
+    const In* xx = (const In*)x;
+    const In* yy = (const In*)y;
+    switch (L.unroll) {
+        case 1: hipLaunchKernelGGL((k_moments<MAXM, PREC, In, 1>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis, ra); break;
+        case 2: hipLaunchKernelGGL((k_moments<MAXM, PREC, In, 2>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis, ra); break;
+        case 4: hipLaunchKernelGGL((k_moments<MAXM, PREC, In, 4>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis, ra); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int MAXM>
+hipError_t Launchers<MAXM>::moments(const FitDesc& d, const Work& w, int prec, int dtype, const void* x,
+                                    const void* y, const Launch& L, int mis, const RangeArg& ra, hipStream_t st) {
+    if (prec == LSEFIT_PREC_F64 && dtype == LSEFIT_F64)
+        return moments_t<LSEFIT_PREC_F64, double>(d, w, x, y, L, mis, ra, st);
+    if (prec == LSEFIT_PREC_F64 && dtype == LSEFIT_F32)
+        return moments_t<LSEFIT_PREC_F64, float>(d, w, x, y, L, mis, ra, st);
+    if (prec == LSEFIT_PREC_F32C && dtype == LSEFIT_F32)
+        return moments_t<LSEFIT_PREC_F32C, float>(d, w, x, y, L, mis, ra, st);
+    return hipErrorInvalidValue;
+}
+
+template <int MAXM>
+hipError_t Launchers<MAXM>::combine(const FitDesc& d, const Work& w, const Launch& L, bool by_block, const Finish& fz,
+                                    hipStream_t st) {
+    if (by_block) {
+        int64_t blocks = d.batch < 65536 ? d.batch : 65536;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(k_combine_block<MAXM>, dim3(blocks), dim3(kCombineThreads), 0, st, d, w, L.waves, fz);
+    } else {
+        const int64_t blocks = (d.batch + 255) / 256;
+        hipLaunchKernelGGL(k_combine_lane<MAXM>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, d, w, L.waves, fz);
+    }
+    return hipGetLastError();
+}
+
+template <int MAXM>
+hipError_t Launchers<MAXM>::finish_single(const FitDesc& d, const Work& w, int64_t G, const Finish& fz, hipStream_t st) {
+    hipLaunchKernelGGL(k_finish_single<MAXM>, dim3(1), dim3(kFinishThreads), 0, st, d, w, G, fz);
+    return hipGetLastError();
+}
+
+template <int MAXM>
+hipError_t Launchers<MAXM>::solve_moments(const double* moments, const Work& w, int m, double* coef,
+                                          int32_t* status, hipStream_t st) {
+    switch (m) {
+#define LSEFIT_SOLVE_CASE(MV)                                                                                   \
+    case MV:                                                                                                    \
+        if constexpr (MV <= MAXM) {                                                                             \
+            hipLaunchKernelGGL((k_solve_moments<MV, MAXM>), dim3(1), dim3(64), 0, st, moments, w, coef, status); \
+            return hipGetLastError();                                                                           \
+        }                                                                                                       \
+        break;
+        LSEFIT_SOLVE_CASE(1)
+        LSEFIT_SOLVE_CASE(2)
+        LSEFIT_SOLVE_CASE(3)
+        LSEFIT_SOLVE_CASE(4)
+        LSEFIT_SOLVE_CASE(5)
+        LSEFIT_SOLVE_CASE(6)
+        LSEFIT_SOLVE_CASE(7)
+        LSEFIT_SOLVE_CASE(8)
+#undef LSEFIT_SOLVE_CASE
+        default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int MAXM>
+template <typename In>
+hipError_t Launchers<MAXM>::refine_t(const FitDesc& d, const Work& w, const void* x, const void* y, const Launch& L,
+                                     int mis, hipStream_t st) {
+    const dim3 grid(blocks_for(L)), block(L.wpb * kWave);
+    const In* xx = (const In*)x;
+    const In* yy = (const In*)y;
+    switch (L.unroll) {
+        case 1: hipLaunchKernelGGL((k_refine<MAXM, In, 1>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis); break;
+        case 2: hipLaunchKernelGGL((k_refine<MAXM, In, 2>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis); break;
+        case 4: hipLaunchKernelGGL((k_refine<MAXM, In, 4>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int MAXM>
+hipError_t Launchers<MAXM>::refine(const FitDesc& d, const Work& w, int dtype, const void* x, const void* y,
+                                   const Launch& L, int mis, hipStream_t st) {
+    return dtype == LSEFIT_F32 ? refine_t<float>(d, w, x, y, L, mis, st) : refine_t<double>(d, w, x, y, L, mis, st);
+}
+
+template <int MAXM>
+hipError_t Launchers<MAXM>::adjoint(const FitDesc& d, const Work& w, int dtype, const void* x, const void* y,
+                                    const double* grad_coef, int32_t coef_stride, void* gx, void* gy,
+                                    const Launch& L, int mis, hipStream_t st) {
+    const int64_t sblocks = (d.batch + 255) / 256;
+    hipLaunchKernelGGL(k_adjoint_solve<MAXM>, dim3(sblocks > 0 ? sblocks : 1), dim3(256), 0, st, d, w, grad_coef,
+                       coef_stride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid(blocks_for(L)), block(L.wpb * kWave);
+    if (dtype == LSEFIT_F32)
+        hipLaunchKernelGGL((k_adjoint_stream<MAXM, float>), grid, block, 0, st, d, w, (const float*)x,
+                           (const float*)y, (float*)gx, (float*)gy, L.tile, L.waves, mis);
+    else
+        hipLaunchKernelGGL((k_adjoint_stream<MAXM, double>), grid, block, 0, st, d, w, (const double*)x,
+                           (const double*)y, (double*)gx, (double*)gy, L.tile, L.waves, mis);
+    return hipGetLastError();
+}
+
+}  // namespace lsefit

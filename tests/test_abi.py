@@ -1,0 +1,122 @@
+"""The C ABI loads on a machine without a GPU, exports every symbol that
+include/lsefit.h declares, and rejects bad arguments on the host before any
+device work (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1512_08017_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lsefit.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+\*?([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_header_declares_the_expected_entry_points():
+    assert set(declared_functions()) == set(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = _lib.load()
+    assert L.lsefit_status_string(_lib.OK) == b"ok"
+    assert L.lsefit_status_string(_lib.SINGULAR) == b"singular normal system"
+    assert L.lsefit_status_string(99) == b"unknown status"
+
+
+def _opt(**kw):
+    o = _lib.Options()
+    o.degree, o.precision, o.refine_steps, o.range_mode, o.center, o.scale = 3, 0, 0, 1, 0.0, 1.0
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_workspace_bytes_grows_with_batch_and_degree():
+    L = _lib.load()
+    s = _lib.Schedule(4096, 4, 256, 2)
+    a = L.lsefit_workspace_bytes(1, 3, ctypes.byref(s))
+    b = L.lsefit_workspace_bytes(1000, 3, ctypes.byref(s))
+    c = L.lsefit_workspace_bytes(1000, 8, ctypes.byref(s))
+    assert 0 < a < b < c
+    assert L.lsefit_workspace_bytes(0, 3, ctypes.byref(s)) == 0
+    assert L.lsefit_workspace_bytes(1, 9, ctypes.byref(s)) == 0
+    bad = _lib.Schedule(4096, 3, 256, 2)
+    assert L.lsefit_workspace_bytes(1, 3, ctypes.byref(bad)) == 0
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("kw,n,dt,expect", [
+    ({"degree": 0}, 100, _lib.F32, _lib.INVALID_ARG),
+    ({"degree": 9}, 100, _lib.F32, _lib.INVALID_ARG),
+    ({}, 3, _lib.F32, _lib.INVALID_ARG),                       # n < m + 1
+    ({"precision": 1}, 100, _lib.F64, _lib.UNSUPPORTED),       # compensated FP32 needs FP32 data
+    ({"range_mode": 0, "scale": 0.0}, 100, _lib.F32, _lib.INVALID_ARG),
+    ({"range_mode": 0, "scale": float("nan")}, 100, _lib.F32, _lib.INVALID_ARG),
+    ({"refine_steps": 2}, 100, _lib.F32, _lib.INVALID_ARG),
+    ({}, 100, 7, _lib.INVALID_ARG),
+])
+def test_fit_moments_host_validation(kw, n, dt, expect):
+    L = _lib.load()
+    o = _opt(**kw)
+    assert L.fit_moments(FAKE, FAKE, n, dt, ctypes.byref(o), FAKE, 1 << 30, FAKE, None) == expect
+
+
+def test_fit_moments_workspace_too_small():
+    L = _lib.load()
+    o = _opt()
+    assert L.fit_moments(FAKE, FAKE, 100, _lib.F32, ctypes.byref(o), FAKE, 16, FAKE, None) == _lib.WORKSPACE
+
+
+def test_null_pointers_rejected():
+    L = _lib.load()
+    o = _opt()
+    assert L.fit_moments(None, FAKE, 100, _lib.F32, ctypes.byref(o), FAKE, 1 << 30, FAKE, None) == _lib.INVALID_ARG
+    assert L.fit_solve(None, ctypes.byref(o), None, None, 0, _lib.F32, FAKE, 1 << 30, FAKE, FAKE,
+                       None) == _lib.INVALID_ARG
+    assert L.fit_batched(FAKE, FAKE, None, FAKE, 10, _lib.F32, ctypes.byref(o), None, FAKE, 1 << 30, FAKE, 4,
+                         FAKE, None) == _lib.INVALID_ARG
+    assert L.fit_batched(FAKE, FAKE, FAKE, FAKE, 10, _lib.F32, ctypes.byref(o), None, FAKE, 1 << 30, FAKE, 3,
+                         FAKE, None) == _lib.INVALID_ARG           # coef_stride < m + 1
+    assert L.fit_batched(FAKE, FAKE, FAKE, FAKE, 10, _lib.F32, ctypes.byref(o), None, FAKE, 8, FAKE, 4,
+                         FAKE, None) == _lib.WORKSPACE
+    assert L.fit_batched(FAKE, FAKE, FAKE, FAKE, 0, _lib.F32, ctypes.byref(o), None, None, 0, None, 4,
+                         None, None) == _lib.OK                    # empty batch: nothing to do
+    assert L.fit_backward(FAKE, FAKE, FAKE, FAKE, 10, _lib.F32, ctypes.byref(o), None, FAKE, 1 << 30, None, 4,
+                          FAKE, FAKE, None) == _lib.INVALID_ARG
+    assert L.fit_plan_create(None, 10, 3, _lib.F32, 0) == _lib.INVALID_ARG
+    h = ctypes.c_void_p()
+    assert L.fit_plan_create(ctypes.byref(h), 10, 9, _lib.F32, 0) == _lib.INVALID_ARG
+    L.fit_plan_destroy(None)
+
+
+def test_default_schedule_setter_validates():
+    L = _lib.load()
+    bad = _lib.Schedule(0, 4, 256, 2)
+    assert L.lsefit_set_default_schedule(ctypes.byref(bad)) == _lib.INVALID_ARG
+    s = _lib.Schedule()
+    assert L.lsefit_default_schedule(ctypes.byref(s)) == _lib.OK
+    assert s.waves > 0 and s.waves_per_block in (1, 2, 4) and s.tile >= 64
+
+
+def test_package_import_does_not_load_or_fall_back():
+    import paper_1512_08017_amd as lf
+    assert callable(lf.fit)
+    with pytest.raises((ValueError, TypeError)):
+        import torch
+        lf.fit(torch.zeros(10), torch.zeros(10), 1)   # CPU tensors are refused, never computed

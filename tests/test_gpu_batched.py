@@ -1,0 +1,186 @@
+"""GPU parity of the batched path (one persistent launch over CSR segments)
+and of the adjoint, against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_common import announce, normwise, to_dev, torch
+from oracle import adjoint, c_oracle
+from paper_1512_08017_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+lf = pytest.importorskip("paper_1512_08017_amd")
+
+
+def run_batched(bf, max_degree, precision="f64", plan=None, **kw):
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, deg = to_dev(bf.offsets), to_dev(bf.degrees)
+    coef, status, ws = lf.fit_batched(x, y, off, deg, max_degree, precision=precision, plan=plan, **kw)
+    torch.cuda.synchronize()
+    return coef.cpu().numpy(), status.cpu().numpy()
+
+
+def check_against_oracle(bf, coef, status, tol):
+    ref, rst = c_oracle.fit_batched(bf.x, bf.y, bf.offsets, bf.degrees, stride=coef.shape[1])
+    worst = 0.0
+    for f in range(bf.batch):
+        m = int(bf.degrees[f])
+        assert int(status[f]) == int(rst[f]), (f, status[f], rst[f])
+        if rst[f] == 0:
+            e = normwise(coef[f, : m + 1], ref[f, : m + 1])
+            worst = max(worst, e)
+        else:
+            assert np.isnan(coef[f, : m + 1]).all()
+    assert worst <= tol, worst
+    return worst
+
+
+RAGGED = [0, 1, 2, 3, 4, 5, 15, 16, 17, 63, 64, 65, 255, 256, 257, 1000, 4097, 70_001, 0, 7, 300_000, 2, 12_345]
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-9), ("f32c", 1e-6)])
+def test_ragged_mixed_degrees(precision, tol):
+    announce(f"ragged batch {precision}")
+    rng = np.random.default_rng(1)
+    deg = rng.integers(1, 4, len(RAGGED))
+    bf = W.random_batch(RAGGED, deg, seed=2, lo=-5.0, hi=5.0)
+    coef, status = run_batched(bf, 3, precision)
+    check_against_oracle(bf, coef, status, tol)
+    assert status[0] == 2 and status[1] == 2     # empty and one-point fits are singular
+
+
+@pytest.mark.parametrize("schedule", [
+    {"waves": 64, "waves_per_block": 1, "tile": 64, "unroll": 1},
+    {"waves": 1024, "waves_per_block": 2, "tile": 512, "unroll": 2},
+    {"waves": 4096, "waves_per_block": 4, "tile": 4096, "unroll": 4},
+    {"waves": 8192, "waves_per_block": 4, "tile": 256, "unroll": 2},
+])
+def test_schedules_agree(schedule):
+    announce(f"schedule {schedule}")
+    rng = np.random.default_rng(3)
+    L = W.ragged_lengths(500, 16, 20_000, rng)
+    deg = rng.integers(1, 4, 500)
+    bf = W.random_batch(L, deg, seed=4, lo=-5.0, hi=5.0)
+    old = lf.default_schedule().as_dict()
+    try:
+        lf.set_default_schedule(schedule)
+        coef, status = run_batched(bf, 3)
+    finally:
+        lf.set_default_schedule(old)
+    check_against_oracle(bf, coef, status, 1e-9)
+
+
+def test_degree_out_of_range_is_flagged():
+    bf = W.random_batch([100, 100, 100], [1, 3, 2], seed=5)
+    coef, status = run_batched(bf, 2)      # fit 1 asks for more than max_degree
+    assert list(status) == [0, 1, 0]
+    assert np.isnan(coef[1]).all()         # every entry of an out-of-range fit
+
+
+def test_nonfinite_fit_does_not_touch_neighbours():
+    bf = W.random_batch([1000, 1000, 1000], [2, 2, 2], seed=6)
+    bf.y[1500] = np.nan
+    coef, status = run_batched(bf, 2)
+    assert list(status) == [0, 3, 0]
+    ref, _ = c_oracle.fit_batched(bf.x, bf.y, bf.offsets, bf.degrees, stride=3)
+    assert normwise(coef[0], ref[0]) <= 1e-9 and normwise(coef[2], ref[2]) <= 1e-9
+
+
+def test_batched_equals_single_fits():
+    bf = W.random_batch([5000, 70_000, 333], [3, 2, 1], seed=7)
+    coef, status = run_batched(bf, 3)
+    for f in range(3):
+        lo, hi = bf.offsets[f], bf.offsets[f + 1]
+        m = int(bf.degrees[f])
+        r = lf.fit(to_dev(bf.x[lo:hi]), to_dev(bf.y[lo:hi]), m)
+        assert normwise(coef[f, : m + 1], r.coef.cpu().numpy()) <= 1e-12
+
+
+def test_plan_graph_replays_match_eager():
+    announce("plan + graph")
+    rng = np.random.default_rng(8)
+    L = W.ragged_lengths(2000, 16, 30_000, rng)
+    deg = rng.integers(1, 4, 2000)
+    bf = W.random_batch(L, deg, seed=9, lo=-5.0, hi=5.0)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    eager, est, _ = lf.fit_batched(x, y, off, dg, 3)
+    plan = lf.Plan(bf.batch, 3)
+    best = plan.tune(x, y, off, dg, reps=1)
+    assert best > 0
+    coef = torch.zeros_like(eager)
+    status = torch.zeros_like(est)
+    outs = []
+    for _ in range(4):
+        coef.zero_()
+        lf.fit_batched(x, y, off, dg, 3, plan=plan, out=(coef, status))
+        torch.cuda.synchronize()
+        outs.append(coef.cpu().numpy().copy())
+        _ = (x * 2).sum().item()    # eager work between replays
+    for o in outs:
+        assert np.array_equal(o, outs[0])
+    check_against_oracle(bf, outs[0], status.cpu().numpy(), 1e-9)
+    plan.close()
+
+
+def test_graph_recaptures_when_pointers_change():
+    plan = lf.Plan(3, 2)
+    for seed in (10, 11):
+        bf = W.random_batch([500, 600, 700], [2, 2, 1], seed=seed)
+        coef, status = run_batched(bf, 2, plan=plan)
+        check_against_oracle(bf, coef, status, 1e-9)
+    plan.close()
+
+
+# --- adjoint -------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_adjoint_against_oracle(dtype):
+    announce(f"adjoint {np.dtype(dtype).name}")
+    bf = W.random_batch([4096, 1000, 257, 33], [2, 3, 1, 2], seed=12, dtype=dtype, with_target=True)
+    x = to_dev(bf.x).requires_grad_(True)
+    y = to_dev(bf.y).requires_grad_(True)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    target = torch.from_numpy(bf.target).to(x.device)
+    coef = lf.lsefit(x, y, off, dg, 3, center=0.0, scale=1.0)
+    mask = torch.zeros_like(coef)
+    for f in range(bf.batch):
+        mask[f, : int(bf.degrees[f]) + 1] = 1.0
+    loss = (((coef - target) * mask) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    gx, gy = x.grad.cpu().numpy(), y.grad.cpu().numpy()
+    tol = 1e-5 if dtype == np.float32 else 1e-10
+    a_all = coef.detach().cpu().numpy()
+    for f in range(bf.batch):
+        lo, hi = bf.offsets[f], bf.offsets[f + 1]
+        m = int(bf.degrees[f])
+        gbar = 2.0 * (a_all[f, : m + 1] - bf.target[f, : m + 1])
+        ref = adjoint.gradients(bf.x[lo:hi], bf.y[lo:hi], m, gbar)
+        # the float32 gradients are rounded on store; compare against the rounded oracle too
+        assert normwise(gx[lo:hi], ref["dx"]) <= tol, f
+        assert normwise(gy[lo:hi], ref["dy"]) <= tol, f
+
+
+def test_adjoint_against_finite_differences():
+    bf = W.random_batch([300], [2], seed=13, dtype=np.float64, with_target=True)
+    x = to_dev(bf.x).requires_grad_(True)
+    y = to_dev(bf.y).requires_grad_(True)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    target = bf.target[0, :3]
+    coef = lf.lsefit(x, y, off, dg, 2)
+    loss = ((coef[0] - torch.from_numpy(target).to(x.device)) ** 2).sum()
+    loss.backward()
+    fd = adjoint.fd_gradients(bf.x, bf.y, 2, lambda a: float(np.sum((a - target) ** 2)), h=1e-6)
+    assert normwise(x.grad.cpu().numpy(), fd["dx"]) <= 1e-4
+    assert normwise(y.grad.cpu().numpy(), fd["dy"]) <= 1e-4
+
+
+def test_adjoint_nan_for_failed_fits():
+    bf = W.random_batch([100, 2, 100], [2, 2, 2], seed=14)
+    x = to_dev(bf.x).requires_grad_(True)
+    y = to_dev(bf.y).requires_grad_(True)
+    coef = lf.lsefit(x, y, to_dev(bf.offsets), to_dev(bf.degrees), 2)
+    torch.nan_to_num(coef).sum().backward()
+    g = x.grad.cpu().numpy()
+    assert np.isfinite(g[:100]).all() and np.isnan(g[100:102]).all() and np.isfinite(g[102:]).all()

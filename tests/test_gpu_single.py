@@ -1,0 +1,222 @@
+"""GPU parity of the single-fit path (fit_moments + fit_solve) against the oracle.
+
+Sizes span several tiles and a ragged tail; both the float64 and the
+compensated-float32 forms, both range modes, every degree up to the maximum,
+odd alignments and the degenerate cases.  Gates: float64 form <= 1e-9 and
+compensated float32 form with one refinement <= 1e-6, normwise relative to
+the oracle's coefficients; power sums <= 1e-12 relative per sum.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from gpu_common import announce, normwise, to_dev, torch
+from oracle import adjoint, c_oracle, fp64
+from paper_1512_08017_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+lf = pytest.importorskip("paper_1512_08017_amd")
+
+
+def run_fit(fit, degree, precision="f64", **kw):
+    x, y = to_dev(fit.x), to_dev(fit.y)
+    res = lf.fit(x, y, degree, precision=precision, **kw)
+    torch.cuda.synchronize()
+    return res
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 63, 64, 65, 255, 257, 1000, 4097, 65_537, 1_000_003])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_f64_form_sizes(n, dtype):
+    m = 1 if n < 4 else 3
+    announce(f"f64 form n={n} dtype={np.dtype(dtype).name} m={m}")
+    fit = W.random_small(n, m, seed=n, dtype=dtype)
+    res = run_fit(fit, m)
+    ref = c_oracle.fit(fit.x, fit.y, m)
+    assert int(res.status.cpu()[0]) == 0
+    assert normwise(res.coef.cpu().numpy(), ref["a"]) <= 1e-9
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_every_degree_given_range(m):
+    """Given (c, s): compare power sums and t-basis solution in the same basis."""
+    announce(f"degree {m} given range")
+    fit = W.random_small(200_001, m, seed=100 + m, lo=2.0, hi=4.0, dtype=np.float32)
+    c, s = 3.0, 1.0
+    res = run_fit(fit, m, center=c, scale=s)
+    ref = c_oracle.fit(fit.x, fit.y, m, center=c, scale=s)
+    mom = res.moments.cpu().numpy()
+    assert mom[0] == c and mom[1] == s
+    S, T = mom[2:3 + 2 * m], mom[3 + 2 * m:]
+    assert S[0] == fit.n
+    assert np.max(np.abs(S - ref["S"]) / np.abs(ref["S"]).max()) <= 1e-12
+    assert np.max(np.abs(T - ref["T"]) / np.abs(ref["T"]).max()) <= 1e-12
+    assert int(res.status.cpu()[0]) == 0
+    # cond of the monomial Hankel matrix grows quickly with m: the gate follows it
+    tol = 1e-9 if m <= 5 else 1e-7
+    assert normwise(res.coef_t.cpu().numpy(), ref["b"]) <= tol
+    # a = M b amplifies a relative error of b by kappa = max|M||b| / max|a|
+    Mx = adjoint.basis_map(m, c, s)
+    kappa = np.max(np.abs(Mx) @ np.abs(ref["b"])) / np.max(np.abs(ref["a"]))
+    assert normwise(res.coef.cpu().numpy(), ref["a"]) <= tol * max(1.0, kappa)
+
+
+@pytest.mark.parametrize("m", [1, 3, 5])
+def test_auto_range_matches_plain_minimiser(m):
+    announce(f"auto range m={m}")
+    fit = W.random_small(300_007, m, seed=200 + m, lo=-3.0, hi=7.0, dtype=np.float32)
+    res = run_fit(fit, m)
+    mom = res.moments.cpu().numpy()
+    # the auto range is a power-of-two scale and a float32 centre
+    assert np.log2(mom[1]) == np.round(np.log2(mom[1]))
+    assert float(np.float32(mom[0])) == mom[0]
+    ref = c_oracle.fit(fit.x, fit.y, m, center=2.0, scale=4.0)
+    assert normwise(res.coef.cpu().numpy(), ref["a"]) <= 1e-9
+
+
+@pytest.mark.parametrize("n", [5, 1000, 65_536, 1_000_001])
+@pytest.mark.parametrize("m", [1, 3, 5])
+def test_f32c_form_with_refinement(n, m):
+    if n < m + 1:
+        pytest.skip("too few points")
+    announce(f"f32c n={n} m={m}")
+    fit = W.random_small(n, m, seed=300 + n + m, lo=-1.0, hi=1.0, noise_sd=0.01, dtype=np.float32)
+    res = run_fit(fit, m, precision="f32c", refine=1)
+    ref = c_oracle.fit(fit.x, fit.y, m)
+    assert int(res.status.cpu()[0]) == 0
+    assert normwise(res.coef.cpu().numpy(), ref["a"]) <= 1e-6
+
+
+def test_f32c_without_refinement_is_close():
+    fit = W.random_small(1_000_000, 3, seed=41, dtype=np.float32)
+    res = run_fit(fit, 3, precision="f32c", refine=0)
+    ref = c_oracle.fit(fit.x, fit.y, 3)
+    assert normwise(res.coef.cpu().numpy(), ref["a"]) <= 1e-4
+
+
+def test_bitwise_deterministic():
+    fit = W.random_small(3_000_017, 3, seed=42, dtype=np.float32)
+    x, y = to_dev(fit.x), to_dev(fit.y)
+    for prec in ("f64", "f32c"):
+        outs = []
+        for _ in range(3):
+            r = lf.fit(x, y, 3, precision=prec)
+            torch.cuda.synchronize()
+            outs.append((r.coef.cpu().numpy().tobytes(), r.moments.cpu().numpy().tobytes()))
+        assert outs[0] == outs[1] == outs[2], prec
+
+
+@pytest.mark.parametrize("shift_x,shift_y", [(1, 1), (2, 2), (3, 3), (1, 2), (0, 3)])
+def test_misaligned_pointers(shift_x, shift_y):
+    """Slices that start off the 16-byte grid (same or different offsets for x and y)."""
+    announce(f"misaligned {shift_x} {shift_y}")
+    fit = W.random_small(100_003, 3, seed=43, dtype=np.float32)
+    xf = np.concatenate([np.zeros(4, np.float32), fit.x])
+    yf = np.concatenate([np.zeros(4, np.float32), fit.y])
+    n = fit.n - 4
+    xh, yh = xf[shift_x:shift_x + n], yf[shift_y:shift_y + n]
+    x = to_dev(xf)[shift_x:shift_x + n]
+    y = to_dev(yf)[shift_y:shift_y + n]
+    assert x.is_contiguous() and y.is_contiguous()
+    res = lf.fit(x, y, 3)
+    torch.cuda.synchronize()
+    ref = c_oracle.fit(xh, yh, 3)
+    assert normwise(res.coef.cpu().numpy(), ref["a"]) <= 1e-9
+
+
+def test_duplicate_x_is_singular():
+    x = np.repeat(np.array([1.0, 2.0, 3.0], np.float32), 1000)
+    y = np.random.default_rng(0).standard_normal(3000).astype(np.float32)
+    for m, expect in ((2, 0), (3, 2), (4, 2)):
+        res = lf.fit(to_dev(x), to_dev(y), m)
+        torch.cuda.synchronize()
+        assert int(res.status.cpu()[0]) == expect, m
+        assert fp64.fit(x, y, m)["status"] == ("ok" if expect == 0 else "singular")
+        if expect:
+            assert torch.isnan(res.coef).all()
+
+
+@pytest.mark.parametrize("where", ["x", "y"])
+@pytest.mark.parametrize("value", [np.nan, np.inf])
+def test_nonfinite_input(where, value):
+    fit = W.random_small(10_000, 2, seed=44, dtype=np.float32)
+    getattr(fit, where)[1234] = value
+    for prec in ("f64", "f32c"):
+        res = run_fit(fit, 2, precision=prec, center=0.0, scale=1.0)
+        assert int(res.status.cpu()[0]) == 3
+        assert torch.isnan(res.coef).all()
+
+
+def test_constant_x_auto_range():
+    x = np.full(1000, 5.0, np.float32)
+    y = np.arange(1000, dtype=np.float32)
+    res = run_fit(W.SingleFit("c", x, y, 1, np.zeros(2)), 1)
+    assert int(res.status.cpu()[0]) == 2
+
+
+def test_minimum_points_interpolates():
+    """n = m + 1 distinct points: zero residual (interpolation)."""
+    x = np.array([-1.0, -0.25, 0.5, 1.0], np.float64)
+    y = np.array([2.0, -1.0, 0.5, 3.0], np.float64)
+    res = run_fit(W.SingleFit("i", x, y, 3, np.zeros(4)), 3)
+    a = res.coef.cpu().numpy()
+    assert np.max(np.abs(fp64.polyval(a, x) - y)) <= 1e-12
+
+
+def test_host_errors_raise():
+    x = to_dev(np.zeros(3, np.float32))
+    with pytest.raises(lf.LsefitError):
+        lf.fit(x, x, 3)                       # n < m + 1
+    with pytest.raises(lf.LsefitError):
+        lf.fit(x.double(), x.double(), 1, precision="f32c")   # unsupported
+    with pytest.raises((lf.LsefitError, ValueError)):
+        lf.fit(to_dev(np.zeros(100, np.float32)), to_dev(np.zeros(100, np.float32)), 9)
+
+
+def test_c_abi_workspace_check_on_device():
+    from paper_1512_08017_amd import _lib, api
+    L = _lib.load()
+    x = to_dev(np.zeros(100, np.float32))
+    ws = torch.empty(64, dtype=torch.uint8, device=x.device)
+    mom = torch.empty(13, dtype=torch.float64, device=x.device)
+    o = api.options(3)
+    rc = L.fit_moments(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr()), 100, _lib.F32,
+                       ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), 64, ctypes.c_void_p(mom.data_ptr()), None)
+    assert rc == _lib.WORKSPACE
+
+
+def test_linear_f64_workload():
+    """The m = 1, n = 1e6 float64 workload (x ~ U[0,10], y = 2 + 3x + noise)."""
+    fit = W.linear_f64()
+    res = run_fit(fit, 1)
+    ref = c_oracle.fit(fit.x, fit.y, 1)
+    assert normwise(res.coef.cpu().numpy(), ref["a"]) <= 1e-9
+    assert abs(res.coef.cpu().numpy()[1] - 3.0) < 1e-2
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32c"])
+def test_split_calls_match_fused_call(precision):
+    """fit_moments + fit_solve and the fused fit_single give the same numbers."""
+    fit = W.random_small(500_009, 3, seed=45, dtype=np.float32)
+    x, y = to_dev(fit.x), to_dev(fit.y)
+    fused = lf.fit(x, y, 3, precision=precision)
+    split = lf.fit_split(x, y, 3, precision=precision)
+    torch.cuda.synchronize()
+    assert np.array_equal(fused.moments.cpu().numpy(), split.moments.cpu().numpy())
+    assert normwise(fused.coef.cpu().numpy(), split.coef.cpu().numpy()) <= 1e-13
+    assert int(fused.status.cpu()[0]) == int(split.status.cpu()[0]) == 0
+
+
+def test_ticket_reuse_across_calls_and_workspaces():
+    """The single-fit ticket resets itself: many calls on one workspace, and a
+    fresh workspace holding stale bytes, give identical results."""
+    fit = W.random_small(2_000_003, 2, seed=46, dtype=np.float32)
+    x, y = to_dev(fit.x), to_dev(fit.y)
+    ws = torch.full((lf.workspace_bytes(1, 2),), 0x5A, dtype=torch.uint8, device=x.device)
+    first = lf.fit(x, y, 2, ws=ws).coef.cpu().numpy()
+    for _ in range(5):
+        assert np.array_equal(lf.fit(x, y, 2, ws=ws).coef.cpu().numpy(), first)
+    ref = c_oracle.fit(fit.x, fit.y, 2)
+    assert normwise(first, ref["a"]) <= 1e-9

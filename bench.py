@@ -59,6 +59,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--schedule", type=str, default=None, help="JSON schedule for the streaming kernels")
+    ap.add_argument("--workload", choices=("cubic_f32", "ragged_batch", "grad_batch", "shifted_quintic",
+                                           "linear_f64"), default="cubic_f32",
+                    help="cubic_f32 is the benchmark; the others are extra measurements (see their docstrings)")
+    ap.add_argument("--per-fit-limit", type=int, default=4096,
+                    help="batched workloads: fits timed one launch sequence at a time for the per-fit baseline")
+    ap.add_argument("--read-probe", action="store_true", help="sweep the read-bandwidth probe instead")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="a few steps of each form plus one plain device copy of known size (for --pmc runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -151,7 +157,7 @@ class SingleFitRunner:
         self.x, self.y, self.m, self.precision = x, y, degree, precision
         self.opt = api.options(degree, precision, 1)
         nbytes = api.workspace_bytes(1, degree)
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
         self.mom = torch.empty(3 * degree + 4, dtype=torch.float64, device=x.device)
         self.coef = torch.empty(2 * (degree + 1), dtype=torch.float64, device=x.device)
         self.status = torch.empty(1, dtype=torch.int32, device=x.device)
@@ -219,6 +225,220 @@ def cpu_baseline(x_np, y_np, degree, target_s):
                       f"(compensated sums + partial-pivoting elimination), {el:.1f} s on {used} host threads"}, res
 
 
+# ---------------------------------------------------------------------------
+# extra workloads (not the benchmark line): batched, differentiable, shifted
+# ---------------------------------------------------------------------------
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    a, b = _events()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def _kernel_avgs():
+    from paper_1512_08017_amd import _lib
+    L = _lib.load()
+    out = {}
+    for kind, name in ((0, "moments"), (1, "refine"), (2, "adjoint"), (3, "combine")):
+        tot, cnt = ctypes.c_double(0.0), ctypes.c_int64(0)
+        _lib.check(L.lsefit_timing_read(kind, ctypes.byref(tot), ctypes.byref(cnt)), "lsefit_timing_read")
+        if cnt.value:
+            out[name] = {"avg_ms": tot.value / cnt.value, "launches": int(cnt.value)}
+    return out
+
+
+def _instrumented(fn, steps):
+    from paper_1512_08017_amd import _lib
+    L = _lib.load()
+    L.lsefit_timing_reset()
+    L.lsefit_timing_enable(1)
+    _time(fn, steps, 0)
+    L.lsefit_timing_enable(0)
+    return _kernel_avgs()
+
+
+def bench_ragged(args):
+    """65,536 ragged fits (log-uniform lengths in [16, 65536], degree 1..3): one
+    persistent batched launch sequence (tuned plan, graph replay) against a
+    sequence of single-fit calls, one per fit, on the same GPU."""
+    import numpy as np
+    import torch
+    import paper_1512_08017_amd as lf
+    from paper_1512_08017_amd import _lib, api, workloads as W
+    dev = torch.device("cuda:0")
+    bf = W.ragged_batch()
+    x, y = torch.from_numpy(bf.x).to(dev), torch.from_numpy(bf.y).to(dev)
+    off, dg = torch.from_numpy(bf.offsets).to(dev), torch.from_numpy(bf.degrees).to(dev)
+    P = bf.total_points
+    out = {"workload": f"ragged_batch: {bf.batch} fits, {P} float32 points", "points": P}
+    for prec in ("f64", "f32c"):
+        coef = torch.zeros(bf.batch, 4, dtype=torch.float64, device=dev)
+        status = torch.zeros(bf.batch, dtype=torch.int32, device=dev)
+        eager_ms = _time(lambda: lf.fit_batched(x, y, off, dg, 3, precision=prec, out=(coef, status)),
+                         args.steps, args.warmup)
+        plan = lf.Plan(bf.batch, 3, precision=prec)
+        tuned_ms = plan.tune(x, y, off, dg, precision=prec, reps=3)
+        graph_ms = _time(lambda: lf.fit_batched(x, y, off, dg, 3, precision=prec, plan=plan, out=(coef, status)),
+                         args.steps, args.warmup)
+        plan.set_graph(False)
+        kern = _instrumented(lambda: lf.fit_batched(x, y, off, dg, 3, precision=prec, plan=plan,
+                                                    out=(coef, status)), args.steps)
+        ok = bool((status.cpu().numpy() == 0).all())
+        passes = 2 if prec == "f32c" else 1
+        out[prec] = {"eager_default_ms": eager_ms, "tuned_graph_ms": graph_ms, "tuned_schedule": plan.schedule,
+                     "points_per_s": P / (graph_ms * 1e-3), "step_gbps": 8.0 * P * passes / (graph_ms * 1e-3) / 1e9,
+                     "kernels": kern, "all_ok": ok,
+                     "moments_gbps": 8.0 * P / (kern["moments"]["avg_ms"] * 1e-3) / 1e9}
+        plan.close()
+        log(f"ragged {prec}: {out[prec]}")
+    # per-fit baseline: one fit_single call per fit on the same stream
+    L = _lib.load()
+    nfit = min(args.per_fit_limit, bf.batch)
+    ws = torch.zeros(api.workspace_bytes(1, 3), dtype=torch.uint8, device=dev)
+    cbuf = torch.zeros(nfit, 8, dtype=torch.float64, device=dev)
+    sbuf = torch.zeros(nfit, dtype=torch.int32, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    opts = [api.options(int(m)) for m in range(1, 4)]
+    calls = []
+    pts = 0
+    for f in range(nfit):
+        lo, hi = int(bf.offsets[f]), int(bf.offsets[f + 1])
+        m = int(bf.degrees[f])
+        pts += hi - lo
+        calls.append((ctypes.c_void_p(x.data_ptr() + 4 * lo), ctypes.c_void_p(y.data_ptr() + 4 * lo), hi - lo, _lib.F32,
+                      ctypes.byref(opts[m - 1]), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                      ctypes.c_void_p(cbuf.data_ptr() + 64 * f), ctypes.c_void_p(sbuf.data_ptr() + 4 * f), None,
+                      stream))
+
+    def per_fit():
+        for c in calls:
+            L.fit_single(*c)
+
+    per_ms = _time(per_fit, 1, 1)
+    out["per_fit_launches"] = {"fits": nfit, "points": pts, "ms": per_ms, "points_per_s": pts / (per_ms * 1e-3),
+                               "ms_per_fit": per_ms / nfit}
+    best = out["f64"]
+    out["speedup_vs_per_fit"] = best["points_per_s"] / out["per_fit_launches"]["points_per_s"]
+    return out
+
+
+def bench_grad(args):
+    """4,096 fits x 4,096 float32 points, m = 2: batched forward + hand-written
+    adjoint against per-fit forward + backward calls on the same GPU."""
+    import torch
+    import paper_1512_08017_amd as lf
+    from paper_1512_08017_amd import workloads as W
+    dev = torch.device("cuda:0")
+    bf = W.grad_batch()
+    x, y = torch.from_numpy(bf.x).to(dev), torch.from_numpy(bf.y).to(dev)
+    off, dg = torch.from_numpy(bf.offsets).to(dev), torch.from_numpy(bf.degrees).to(dev)
+    target = torch.from_numpy(bf.target).to(dev)
+    P = bf.total_points
+    state = {}
+
+    def fwd_bwd():
+        coef, status, ws = lf.fit_batched(x, y, off, dg, 2, ws=state.get("ws"))
+        state["ws"] = ws
+        g = 2.0 * (coef - target)
+        lf.fit_backward(x, y, off, dg, 2, g, ws=ws)
+
+    ms = _time(fwd_bwd, args.steps, args.warmup)
+    kern = _instrumented(fwd_bwd, args.steps)
+    # per fit: fit_batched and fit_backward on a one-fit batch, fit by fit
+    nfit = min(args.per_fit_limit, bf.batch)
+    off1 = torch.tensor([0, 4096], dtype=torch.int64, device=dev)
+    dg1 = torch.tensor([2], dtype=torch.int32, device=dev)
+    ws1 = {}
+
+    def per_fit():
+        for f in range(nfit):
+            xs, ys = x[f * 4096:(f + 1) * 4096], y[f * 4096:(f + 1) * 4096]
+            coef, status, ws = lf.fit_batched(xs, ys, off1, dg1, 2, ws=ws1.get("ws"))
+            ws1["ws"] = ws
+            lf.fit_backward(xs, ys, off1, dg1, 2, 2.0 * (coef - target[f:f + 1]), ws=ws)
+
+    per_ms = _time(per_fit, 1, 1)
+    fwd_bytes = 8.0 * P
+    bwd_bytes = 16.0 * P
+    return {"workload": f"grad_batch: {bf.batch} fits x 4096 float32 points, m=2, forward + adjoint",
+            "points": P, "ms_per_step": ms, "points_per_s": P / (ms * 1e-3),
+            "step_gbps": (fwd_bytes + bwd_bytes) / (ms * 1e-3) / 1e9, "kernels": kern,
+            "moments_gbps": fwd_bytes / (kern["moments"]["avg_ms"] * 1e-3) / 1e9,
+            "adjoint_gbps": bwd_bytes / (kern["adjoint"]["avg_ms"] * 1e-3) / 1e9,
+            "per_fit": {"fits": nfit, "ms": per_ms, "points_per_s": nfit * 4096 / (per_ms * 1e-3)},
+            "speedup_vs_per_fit": (P / (ms * 1e-3)) / (nfit * 4096 / (per_ms * 1e-3))}
+
+
+def bench_single_workload(args, name):
+    """Single fits other than the benchmark: shifted_quintic (n = 1e7, m = 5,
+    x in [1000, 1001]) and linear_f64 (n = 1e6 float64, m = 1)."""
+    import torch
+    from paper_1512_08017_amd import workloads as W
+    dev = torch.device("cuda:0")
+    wl = W.shifted_quintic() if name == "shifted_quintic" else W.linear_f64()
+    x, y = torch.from_numpy(wl.x).to(dev), torch.from_numpy(wl.y).to(dev)
+    esize = wl.x.dtype.itemsize
+    out = {"workload": f"{name}: n={wl.n}, m={wl.degree}, {wl.x.dtype}", "n": wl.n}
+    for prec in (("f64", "f32c") if esize == 4 else ("f64",)):
+        r = SingleFitRunner(x, y, wl.degree, prec)
+        ms, wall, ms_inst, kern = time_steps(r, args.steps, args.warmup)
+        out[prec] = {"ms_per_step": ms, "points_per_s": wl.n / (ms * 1e-3), "kernels": kern,
+                     "moments_gbps": 2 * esize * wl.n / (kern["moments"]["avg_ms"] * 1e-3) / 1e9,
+                     "status": int(r.status.cpu()[0])}
+    return out
+
+
+def probe_sweep(args):
+    """Read-bandwidth probe over the benchmark's 800 MB of x and y, per schedule,
+    load pattern and load kind (the attainable ceiling for the power-sum pass)."""
+    import torch
+    import paper_1512_08017_amd as lf
+    from paper_1512_08017_amd import _lib
+    L = _lib.load()
+    dev = torch.device("cuda:0")
+    n = args.n
+    x = torch.rand(n, device=dev)
+    y = torch.rand(n, device=dev)
+    out = torch.zeros(1 << 16, dtype=torch.float32, device=dev)
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    cus = lf.device_cus()
+    rows = []
+    for wpc in (4, 8, 16, 32):
+        for wpb in (2, 4):
+            for unroll in (1, 2, 4):
+                sch = _lib.Schedule(cus * wpc, wpb, 256, unroll)
+                for pattern in (0, 1):
+                    for nt in (0, 1):
+                        args_ = (ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), n, ctypes.byref(sch),
+                                 pattern, nt, ctypes.c_void_p(out.data_ptr()), out.numel(), st)
+                        fn = lambda: _lib.check(L.lsefit_read_probe(*args_), "lsefit_read_probe")
+                        _time(fn, 3, 2)
+                        L.lsefit_timing_reset()
+                        L.lsefit_timing_enable(1)
+                        _time(fn, args.steps, 0)
+                        L.lsefit_timing_enable(0)
+                        tot, cnt = ctypes.c_double(0.0), ctypes.c_int64(0)
+                        L.lsefit_timing_read(4, ctypes.byref(tot), ctypes.byref(cnt))
+                        ms = tot.value / cnt.value
+                        rows.append({"waves_per_cu": wpc, "wpb": wpb, "unroll": unroll, "pattern": pattern, "nt": nt,
+                                     "ms": ms, "gbps": 8.0 * n / (ms * 1e-3) / 1e9})
+                        log(json.dumps(rows[-1]))
+    best = max(rows, key=lambda r: r["gbps"])
+    return {"probe": "read ceiling, two float32 arrays of n elements", "n": n, "best": best, "rows": rows}
+
+
 def main():
     args = parse()
     if args.summarize_pmc:
@@ -239,6 +459,14 @@ def main():
     dev = torch.device("cuda:0")
     if args.schedule:
         lf.set_default_schedule(json.loads(args.schedule))
+    if args.read_probe:
+        print(json.dumps(probe_sweep(args)), flush=True)
+        return 0
+    if args.workload != "cubic_f32":
+        fn = {"ragged_batch": bench_ragged, "grad_batch": bench_grad}.get(args.workload)
+        res = fn(args) if fn else bench_single_workload(args, args.workload)
+        print(json.dumps(res), flush=True)
+        return 0
     log(f"generating cubic_f32 workload n={args.n:,}")
     t0 = time.perf_counter()
     wl = W.cubic_f32(n=args.n)

@@ -102,11 +102,11 @@ typedef struct lsefit_options {
  * same numbers up to the summation order it implies.
  *  waves:          total wavefronts of the persistent streaming grid; each owns
  *                  an equal share of the tiles (balanced by tile count)
- *  waves_per_block: 1, 2, 4, 8 or 16
+ *  waves_per_block: 1, 2 or 4
  *  tile:           balancing granularity in points (>= 64); a tile never spans
  *                  two fits, a wave streams the consecutive tiles of one fit
  *                  as one segment
- *  unroll:         vector loads in flight per lane and array: 1, 2, 4 or 8 */
+ *  unroll:         vector loads in flight per lane and array: 1, 2 or 4 */
 typedef struct lsefit_schedule {
     int32_t waves;
     int32_t waves_per_block;
@@ -218,13 +218,24 @@ void fit_plan_destroy(lsefit_plan* plan);
 
 const char* lsefit_status_string(lsefit_status s);
 
+/* Read-bandwidth probe, for measurement only (no part of the fit): streams two
+ * float32 arrays of n elements (n rounded down to a multiple of 4; both
+ * 16-byte aligned) with the schedule's grid and 16-byte loads and writes one
+ * float per block into out[out_count >= number of blocks].  pattern 0: each
+ * wave reads one contiguous share (the layout of the power-sum pass);
+ * pattern 1: the grid strides over 16-byte vectors.  nontemporal: 1 uses
+ * non-temporal loads.  Timed as kind 4 by lsefit_timing_read.  Serves to
+ * measure the read bandwidth the device attains with each load pattern. */
+lsefit_status lsefit_read_probe(const float* x, const float* y, int64_t n, const lsefit_schedule* schedule,
+                                int32_t pattern, int32_t nontemporal, float* out, size_t out_count, void* stream);
+
 /* Kernel timing for profiling.  While enabled, every launch of a streaming
  * kernel made by the calls above (outside graph capture) is bracketed by a
  * pair of HIP events recorded on the call's stream.  lsefit_timing_read waits
  * for the recorded events of one kernel kind and returns the summed duration
  * in milliseconds and the number of launches since the last reset.
  *  kind: 0 = power-sum pass, 1 = refinement pass, 2 = adjoint pass,
- *        3 = per-fit combine and solve.
+ *        3 = per-fit combine and solve, 4 = read-bandwidth probe.
  * Not synchronised with calls on other host threads. */
 lsefit_status lsefit_timing_enable(int32_t enable);
 lsefit_status lsefit_timing_reset(void);

@@ -22,7 +22,7 @@ EXPORTS = (
     "fit_moments", "fit_solve", "fit_single", "fit_batched", "fit_backward",
     "fit_plan_create", "fit_plan_tune", "fit_plan_set_schedule", "fit_plan_get_schedule",
     "fit_plan_set_graph", "fit_plan_destroy", "lsefit_status_string", "lsefit_device_cus",
-    "lsefit_timing_enable", "lsefit_timing_reset", "lsefit_timing_read",
+    "lsefit_timing_enable", "lsefit_timing_reset", "lsefit_timing_read", "lsefit_read_probe",
 )
 
 
@@ -81,11 +81,12 @@ def load():
     L.lsefit_status_string.restype = ctypes.c_char_p
     L.lsefit_device_cus.restype = i32
     L.lsefit_timing_enable.argtypes = [i32]
+    L.lsefit_read_probe.argtypes = [vp, vp, i64, SchP, i32, i32, vp, sz, vp]
     L.lsefit_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     for name in ("lsefit_default_schedule", "lsefit_set_default_schedule", "fit_moments", "fit_solve", "fit_single",
                  "fit_batched", "fit_backward", "fit_plan_create", "fit_plan_tune", "fit_plan_set_schedule",
                  "fit_plan_get_schedule", "fit_plan_set_graph", "lsefit_timing_enable", "lsefit_timing_reset",
-                 "lsefit_timing_read"):
+                 "lsefit_timing_read", "lsefit_read_probe"):
         getattr(L, name).restype = i32
     _lib = L
     return L

@@ -22,12 +22,12 @@ using namespace lsefit;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kDefaultWavesPerCU = 16;
+constexpr int kDefaultWavesPerCU = 8;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t tile_start, pstatus, rec, part, total;
+    size_t tile_start, pstatus, rec, part, block_tot, total;
 };
 
 Layout layout(int64_t B, int maxM, int64_t W) {
@@ -41,6 +41,8 @@ Layout layout(int64_t B, int maxM, int64_t W) {
     off = align_up(off + sizeof(double) * (size_t)B * rec_len(maxM));
     L.part = off;
     off = align_up(off + sizeof(double) * (size_t)(W + B) * nacc(maxM));
+    L.block_tot = off;
+    off = align_up(off + sizeof(int64_t) * (size_t)((B + 1023) / 1024));
     L.total = off + kAlign;   // slack for aligning the caller's base pointer
     return L;
 }
@@ -52,6 +54,7 @@ Work carve(void* ws, const Layout& L) {
     w.pstatus = (int32_t*)(base + L.pstatus);
     w.rec = (double*)(base + L.rec);
     w.part = (double*)(base + L.part);
+    w.block_tot = (int64_t*)(base + L.block_tot);
     return w;
 }
 
@@ -68,7 +71,7 @@ lsefit_schedule initial_schedule() {
     lsefit_schedule s;
     s.waves = cus * kDefaultWavesPerCU;
     s.waves_per_block = 4;
-    s.tile = 256;
+    s.tile = 2048;
     s.unroll = 2;
     return s;
 }
@@ -141,15 +144,15 @@ bool refining(const lsefit_options* o) { return o->precision == LSEFIT_PREC_F32C
 // ---------------------------------------------------------------------------
 // optional kernel timing: event pairs around streaming launches
 // ---------------------------------------------------------------------------
-enum TimedKind { kTimeMoments = 0, kTimeRefine = 1, kTimeAdjoint = 2, kTimeCombine = 3, kTimeKinds = 4 };
+enum TimedKind { kTimeMoments = 0, kTimeRefine = 1, kTimeAdjoint = 2, kTimeCombine = 3, kTimeProbe = 4, kTimeKinds = 5 };
 
 struct Timing {
     std::mutex mu;
     bool enabled = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kTimeKinds];
     std::vector<hipEvent_t> pool;
-    double total_ms[kTimeKinds] = {0, 0, 0, 0};
-    int64_t launches[kTimeKinds] = {0, 0, 0, 0};
+    double total_ms[kTimeKinds] = {0, 0, 0, 0, 0};
+    int64_t launches[kTimeKinds] = {0, 0, 0, 0, 0};
 };
 Timing g_timing;
 
@@ -208,10 +211,10 @@ lsefit_status enqueue_batched(const FitDesc& d, const Work& w, const lsefit_opti
     const bool by_block = L.waves >= 64 * d.batch;
     const Finish solve{kSolve, coef, coef_stride, 0, status, nullptr};
     const Finish refine{kRefine, coef, coef_stride, 0, status, nullptr};
-    LSEFIT_TRY(launch_plan(d, w, maxM, L.tile, given, o->center, o->scale, st));
-    if (!given) LSEFIT_TRY(launch_range(d, w, maxM, dt, x, st));
+    LSEFIT_TRY(launch_plan(d, w, maxM, L.tile, given, o->center, o->scale, dt, x, w.block_tot, st));
     const RangeArg ra{LSEFIT_RANGE_GIVEN, 0.0, 1.0};   // per-fit (c, s) are in the records
-    LSEFIT_TRY(timed(kTimeMoments, st, [&] { return launch_moments(d, w, maxM, o->precision, dt, x, y, L, mis, ra, st); }));
+    LSEFIT_TRY(timed(kTimeMoments, st,
+                     [&] { return launch_moments(d, w, maxM, o->precision, dt, x, y, L, mis, ra, st); }));
     LSEFIT_TRY(timed(kTimeCombine, st, [&] { return launch_combine(d, w, maxM, L, by_block, solve, st); }));
     if (refining(o)) {
         LSEFIT_TRY(timed(kTimeRefine, st, [&] { return launch_refine(d, w, maxM, dt, x, y, L, mis, st); }));
@@ -325,6 +328,22 @@ size_t lsefit_workspace_bytes(int64_t batch, int32_t max_degree, const lsefit_sc
 
 int64_t grid_blocks(const Launch& L) { return L.waves / L.wpb; }
 
+// one streaming pass of a single fit (power sums or refinement), then the
+// one-block kernel that sums the block partials and finishes the fit
+lsefit_status single_pass(bool refine_pass, const FitDesc& d, const Work& w, const lsefit_options* opt, int dt,
+                          const void* x, const void* y, const Launch& L, int mis, const Finish& fz, hipStream_t st) {
+    const RangeArg ra{opt->range_mode, opt->center, opt->scale};
+    if (refine_pass)
+        LSEFIT_TRY(timed(kTimeRefine, st, [&] { return launch_refine(d, w, opt->degree, dt, x, y, L, mis, st); }));
+    else
+        LSEFIT_TRY(timed(kTimeMoments, st, [&] {
+            return launch_moments(d, w, opt->degree, opt->precision, dt, x, y, L, mis, ra, st);
+        }));
+    LSEFIT_TRY(timed(kTimeCombine, st,
+                     [&] { return launch_finish_single(d, w, opt->degree, grid_blocks(L), fz, st); }));
+    return LSEFIT_OK;
+}
+
 lsefit_status fit_moments(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
                           void* ws, size_t ws_bytes, double* moments, void* stream) {
     if (!moments) return LSEFIT_ERR_INVALID_ARG;
@@ -332,17 +351,10 @@ lsefit_status fit_moments(const void* x, const void* y, int64_t n, lsefit_dtype 
     lsefit_schedule sched;
     const lsefit_status v = check_single(x, y, n, dt, opt, ws, ws_bytes, &lay, &sched);
     if (v != LSEFIT_OK) return v;
-    hipStream_t st = (hipStream_t)stream;
     const FitDesc d{nullptr, nullptr, n, 1, opt->degree};
-    const Work w = carve(ws, lay);
-    const Launch L = to_launch(sched);
-    const int mis = common_mis(dt, {x, y});
-    const RangeArg ra{opt->range_mode, opt->center, opt->scale};
     const Finish fz{kMomentsOnly, nullptr, 0, 0, nullptr, moments};
-    LSEFIT_TRY(timed(kTimeMoments, st,
-                     [&] { return launch_moments(d, w, opt->degree, opt->precision, dt, x, y, L, mis, ra, st); }));
-    LSEFIT_TRY(timed(kTimeCombine, st, [&] { return launch_finish_single(d, w, opt->degree, grid_blocks(L), fz, st); }));
-    return LSEFIT_OK;
+    return single_pass(false, d, carve(ws, lay), opt, dt, x, y, to_launch(sched), common_mis(dt, {x, y}), fz,
+                       (hipStream_t)stream);
 }
 
 lsefit_status fit_solve(const double* moments, const lsefit_options* opt, const void* x, const void* y, int64_t n,
@@ -359,16 +371,10 @@ lsefit_status fit_solve(const double* moments, const lsefit_options* opt, const 
     hipStream_t st = (hipStream_t)stream;
     const FitDesc d{nullptr, nullptr, refine ? n : 0, 1, opt->degree};
     const Work w = carve(ws, lay);
-    const Launch L = to_launch(sched);
     LSEFIT_TRY(launch_solve_moments(moments, w, opt->degree, opt->degree, coef, status, st));
-    if (refine) {
-        const int mis = common_mis(dt, {x, y});
-        const Finish fz{kRefine, coef, 2 * (opt->degree + 1), 1, status, nullptr};
-        LSEFIT_TRY(timed(kTimeRefine, st, [&] { return launch_refine(d, w, opt->degree, dt, x, y, L, mis, st); }));
-        LSEFIT_TRY(timed(kTimeCombine, st,
-                         [&] { return launch_finish_single(d, w, opt->degree, grid_blocks(L), fz, st); }));
-    }
-    return LSEFIT_OK;
+    if (!refine) return LSEFIT_OK;
+    const Finish fz{kRefine, coef, 2 * (opt->degree + 1), 1, status, nullptr};
+    return single_pass(true, d, w, opt, dt, x, y, to_launch(sched), common_mis(dt, {x, y}), fz, st);
 }
 
 lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
@@ -384,19 +390,11 @@ lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype d
     const Launch L = to_launch(sched);
     const int mis = common_mis(dt, {x, y});
     const int stride = 2 * (opt->degree + 1);
-    const RangeArg ra{opt->range_mode, opt->center, opt->scale};
     const Finish solve{kSolve, coef, stride, 1, status, moments};
-    LSEFIT_TRY(timed(kTimeMoments, st,
-                     [&] { return launch_moments(d, w, opt->degree, opt->precision, dt, x, y, L, mis, ra, st); }));
-    LSEFIT_TRY(timed(kTimeCombine, st,
-                     [&] { return launch_finish_single(d, w, opt->degree, grid_blocks(L), solve, st); }));
-    if (refining(opt)) {
-        const Finish fz{kRefine, coef, stride, 1, status, nullptr};
-        LSEFIT_TRY(timed(kTimeRefine, st, [&] { return launch_refine(d, w, opt->degree, dt, x, y, L, mis, st); }));
-        LSEFIT_TRY(timed(kTimeCombine, st,
-                         [&] { return launch_finish_single(d, w, opt->degree, grid_blocks(L), fz, st); }));
-    }
-    return LSEFIT_OK;
+    lsefit_status r = single_pass(false, d, w, opt, dt, x, y, L, mis, solve, st);
+    if (r != LSEFIT_OK || !refining(opt)) return r;
+    const Finish fz{kRefine, coef, stride, 1, status, nullptr};
+    return single_pass(true, d, w, opt, dt, x, y, L, mis, fz, st);
 }
 
 lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
@@ -571,6 +569,20 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
     plan->sched = best_s;
     plan->drop_graph();
     if (best_ms_out) *best_ms_out = best;
+    return LSEFIT_OK;
+}
+
+lsefit_status lsefit_read_probe(const float* x, const float* y, int64_t n, const lsefit_schedule* schedule,
+                                int32_t pattern, int32_t nontemporal, float* out, size_t out_count, void* stream) {
+    if (!x || !y || !out || n < 4 || (pattern != 0 && pattern != 1)) return LSEFIT_ERR_INVALID_ARG;
+    if (((uintptr_t)x | (uintptr_t)y) % 16) return LSEFIT_ERR_INVALID_ARG;
+    const lsefit_schedule s = schedule ? *schedule : current_default();
+    if (!schedule_ok(s)) return LSEFIT_ERR_INVALID_ARG;
+    const Launch L = to_launch(s);
+    if (out_count < (size_t)(L.waves / L.wpb)) return LSEFIT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    LSEFIT_TRY(timed(kTimeProbe, st,
+                     [&] { return launch_read_probe(x, y, n / 4, L, pattern, nontemporal != 0, out, st); }));
     return LSEFIT_OK;
 }
 

@@ -52,17 +52,36 @@ struct Work {
     double* rec;          // [B * rec_len(M)]
     double* part;         // [(W + B) * nacc(M)] per-(wave, fit) partial sums (batched) or
                           // per-block partial sums (single fit)
+    int64_t* block_tot;   // [ceil(B / 1024)] tile totals of the tile-table blocks
 };
 
 // ---------------------------------------------------------------------------
-// wave-level reductions (fixed butterfly: every lane ends with the same bits,
-// since each step adds the same two operands in either order)
+// wave-level reductions.  The float64 sum runs on DPP lane moves (CDNA keeps the
+// GFX9 row broadcasts): pairs, quads, half rows and rows combine by mirrored
+// moves, so every lane of a row holds the same row sum; two masked row
+// broadcasts then fold rows 0..3 into lane 63, which is read back for all lanes.
+// The pattern is fixed, so the result is the same bits on every run.  Every
+// lane of the wave must be active.
 // ---------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
 }
+
+__device__ inline double wave_sum(double v) {
+    v += dpp_f64<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xf>(v);   // row_half_mirror
+    v += dpp_f64<0x140, 0xf>(v);   // row_mirror
+    v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ inline double wave_min(double v) {
 #pragma unroll
     for (int off = kWave / 2; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));

@@ -8,29 +8,58 @@
 namespace lsefit {
 
 // ---------------------------------------------------------------------------
-// tile table: fit f gets ceil(L_f / tile) tiles; one block scans all fits.
-// Also writes the plan status of each fit and, for a given range, (c, s).
+// tile table of a batch, in two launches.  Pass A: one thread per fit counts
+// its tiles (ceil(L / tile), every point of every fit is in exactly one tile),
+// sets its plan status (bad degree or segment -> INVALID_ARG, fewer than m+1
+// points -> SINGULAR), writes (c, s) (given, or from up to 16 evenly strided
+// samples of its x, first and last included, all loaded in one round), and
+// scans the tile counts of its block.  Pass B adds the tile totals of the
+// blocks before it.  Integer sums: the result does not depend on the order.
 // ---------------------------------------------------------------------------
 constexpr int kPlanThreads = 1024;
+constexpr int kRangeBatchSamples = 16;
 
-__device__ inline int64_t plan_tiles(const FitDesc& d, int64_t f, int64_t tile) {
-    const int64_t L = fit_hi(d, f) - fit_lo(d, f);
-    return L <= 0 ? 0 : (L + tile - 1) / tile;
-}
-
+template <typename In>
 __global__ void __launch_bounds__(kPlanThreads)
-    k_plan(FitDesc d, Work w, int maxM, int64_t tile, int range_given, double c, double s) {
+    k_plan_count(FitDesc d, Work w, int maxM, int64_t tile, int range_given, double c, double s,
+                 const In* __restrict__ x, int64_t* __restrict__ block_tot) {
     __shared__ int64_t sh[kPlanThreads];
     const int tid = threadIdx.x;
-    const int64_t B = d.batch;
-    const int64_t per = (B + kPlanThreads - 1) / kPlanThreads;
-    int64_t f0 = (int64_t)tid * per;
-    if (f0 > B) f0 = B;
-    int64_t f1 = f0 + per;
-    if (f1 > B) f1 = B;
-    int64_t cnt = 0;
-    for (int64_t f = f0; f < f1; ++f) cnt += plan_tiles(d, f, tile);
-    sh[tid] = cnt;
+    const int64_t f = (int64_t)blockIdx.x * kPlanThreads + tid;
+    const int rl = rec_len(maxM);
+    int64_t tiles = 0;
+    if (f < d.batch) {
+        const int64_t lo = fit_lo(d, f);
+        const int64_t L = fit_hi(d, f) - lo;
+        const int m = fit_deg(d, f);
+        tiles = L <= 0 ? 0 : (L + tile - 1) / tile;
+        int st = LSEFIT_OK;
+        if (m < 1 || m > maxM || L < 0) st = LSEFIT_ERR_INVALID_ARG;
+        else if (L < m + 1) st = LSEFIT_ERR_SINGULAR;
+        w.pstatus[f] = st;
+        double cc = c, ss = s;
+        if (!range_given) {
+            const int64_t K = L < kRangeBatchSamples ? L : kRangeBatchSamples;
+            double v[kRangeBatchSamples];
+#pragma unroll
+            for (int i = 0; i < kRangeBatchSamples; ++i) {
+                v[i] = NAN;
+                if (i < K) v[i] = (double)x[lo + (K == 1 ? 0 : (int64_t)i * (L - 1) / (K - 1))];
+            }
+            double mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < kRangeBatchSamples; ++i) {
+                if (isfinite(v[i])) {
+                    mn = fmin(mn, v[i]);
+                    mx = fmax(mx, v[i]);
+                }
+            }
+            snap_range(mn, mx, &cc, &ss);
+        }
+        w.rec[f * rl + 0] = cc;
+        w.rec[f * rl + 1] = ss;
+    }
+    sh[tid] = tiles;
     __syncthreads();
     for (int off = 1; off < kPlanThreads; off <<= 1) {
         const int64_t v = tid >= off ? sh[tid - off] : 0;
@@ -38,57 +67,94 @@ __global__ void __launch_bounds__(kPlanThreads)
         sh[tid] += v;
         __syncthreads();
     }
-    int64_t base = sh[tid] - cnt;
-    const int rl = rec_len(maxM);
-    for (int64_t f = f0; f < f1; ++f) {
-        w.tile_start[f] = base;
-        base += plan_tiles(d, f, tile);
-        const int64_t L = fit_hi(d, f) - fit_lo(d, f);
-        const int m = fit_deg(d, f);
-        int st = LSEFIT_OK;
-        if (m < 1 || m > maxM || L < 0) st = LSEFIT_ERR_INVALID_ARG;
-        else if (L < m + 1) st = LSEFIT_ERR_SINGULAR;
-        w.pstatus[f] = st;
-        if (range_given) {
-            w.rec[f * rl + 0] = c;
-            w.rec[f * rl + 1] = s;
-        }
+    if (f < d.batch) w.tile_start[f] = sh[tid] - tiles;
+    if (tid == kPlanThreads - 1) block_tot[blockIdx.x] = sh[tid];
+}
+
+__global__ void __launch_bounds__(kPlanThreads)
+    k_plan_offsets(FitDesc d, Work w, const int64_t* __restrict__ block_tot, int64_t nblocks) {
+    __shared__ int64_t sh[kPlanThreads];
+    const int tid = threadIdx.x;
+    int64_t part = 0;
+    for (int64_t b = tid; b < blockIdx.x; b += kPlanThreads) part += block_tot[b];
+    sh[tid] = part;
+    __syncthreads();
+    for (int off = kPlanThreads / 2; off >= 1; off >>= 1) {
+        if (tid < off) sh[tid] += sh[tid + off];
+        __syncthreads();
     }
-    if (tid == kPlanThreads - 1) w.tile_start[B] = sh[tid];
+    const int64_t base = sh[0];
+    const int64_t f = (int64_t)blockIdx.x * kPlanThreads + tid;
+    if (f < d.batch) w.tile_start[f] += base;
+    if (blockIdx.x == nblocks - 1 && tid == 0) w.tile_start[d.batch] = base + block_tot[blockIdx.x];
 }
 
 // ---------------------------------------------------------------------------
-// sampled range
+// read-bandwidth probe (measurement only; no fitting arithmetic): streams x and
+// y with 16-byte loads and folds them into one float per block so that the
+// loads stay live.  PATTERN 0: each wave reads one contiguous share, as the
+// power-sum kernel of a single fit does; PATTERN 1: the grid strides over the
+// 16-byte vectors.  NT: non-temporal loads.
 // ---------------------------------------------------------------------------
-constexpr int kRangeBatchSamples = 16;
+template <bool NT, typename V>
+__device__ inline V probe_load(const V* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
 
-template <typename In>
-__global__ void __launch_bounds__(256) k_range_batched(FitDesc d, Work w, int maxM, const In* __restrict__ x) {
-    const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
-    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+template <int U, int PATTERN, bool NT>
+__global__ void __launch_bounds__(256)
+    k_read_probe(const float* __restrict__ x, const float* __restrict__ y, int64_t nvec, int64_t W,
+                 float* __restrict__ out) {
+    typedef float V __attribute__((ext_vector_type(4)));
+    const V* xv = reinterpret_cast<const V*>(x);
+    const V* yv = reinterpret_cast<const V*>(y);
     const int lane = lane_id();
-    const int rl = rec_len(maxM);
-    for (int64_t f = wave0; f < d.batch; f += nw) {
-        const int64_t base = fit_lo(d, f);
-        const int64_t L = fit_hi(d, f) - base;
-        const int64_t K = L < kRangeBatchSamples ? L : kRangeBatchSamples;
-        double lo = INFINITY, hi = -INFINITY;
-        if (lane < K) {
-            const int64_t idx = K == 1 ? 0 : (int64_t)lane * (L - 1) / (K - 1);
-            const double v = (double)x[base + idx];
-            if (isfinite(v)) lo = hi = v;
-        }
-        lo = wave_min(lo);
-        hi = wave_max(hi);
-        if (lane == 0) {
-            double c, s;
-            snap_range(lo, hi, &c, &s);
-            w.rec[f * rl + 0] = c;
-            w.rec[f * rl + 1] = s;
-        }
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    float acc = 0.0f;
+    int64_t j, end, step;
+    if (PATTERN == 0) {
+        j = wave * nvec / W + lane;
+        end = (wave + 1) * nvec / W;
+        step = kWave;
+    } else {
+        j = wave * kWave + lane;
+        end = nvec;
+        step = W * kWave;
     }
+    for (; j + (int64_t)(U - 1) * step < end; j += (int64_t)U * step) {
+        V a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = probe_load<NT>(xv + j + u * step);
+            b[u] = probe_load<NT>(yv + j + u * step);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (a[u].x + a[u].y) + (a[u].z + a[u].w) + (b[u].x + b[u].y) + (b[u].z + b[u].w);
+    }
+    for (; j < end; j += step) {
+        const V a = probe_load<NT>(xv + j), b = probe_load<NT>(yv + j);
+        acc += (a.x + a.y) + (a.z + a.w) + (b.x + b.y) + (b.z + b.w);
+    }
+    acc = (float)wave_sum((double)acc);
+    if (threadIdx.x == 0) out[blockIdx.x] = acc;
 }
 
+hipError_t launch_read_probe(const float* x, const float* y, int64_t nvec, const Launch& L, int pattern, bool nt,
+                             float* out, hipStream_t st) {
+    const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
+#define LSEFIT_PROBE(UU, PP, NN)                                                                                  \
+    if (L.unroll == UU && pattern == PP && nt == NN) {                                                            \
+        hipLaunchKernelGGL((k_read_probe<UU, PP, NN>), grid, block, 0, st, x, y, nvec, L.waves, out);             \
+        return hipGetLastError();                                                                                 \
+    }
+    LSEFIT_PROBE(1, 0, false) LSEFIT_PROBE(2, 0, false) LSEFIT_PROBE(4, 0, false)
+    LSEFIT_PROBE(1, 0, true) LSEFIT_PROBE(2, 0, true) LSEFIT_PROBE(4, 0, true)
+    LSEFIT_PROBE(1, 1, false) LSEFIT_PROBE(2, 1, false) LSEFIT_PROBE(4, 1, false)
+    LSEFIT_PROBE(1, 1, true) LSEFIT_PROBE(2, 1, true) LSEFIT_PROBE(4, 1, true)
+#undef LSEFIT_PROBE
+    return hipErrorInvalidValue;
+}
 
 // ---------------------------------------------------------------------------
 // dispatch on the largest degree of the call
@@ -107,20 +173,20 @@ __global__ void __launch_bounds__(256) k_range_batched(FitDesc d, Work w, int ma
     }                                                    \
     return hipErrorInvalidValue;
 
-hipError_t launch_plan(const FitDesc& d, const Work& w, int maxM, int64_t tile, bool range_given, double c,
-                       double s, hipStream_t st) {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, d, w, maxM, tile, range_given ? 1 : 0, c, s);
-    return hipGetLastError();
-}
+int64_t plan_blocks(int64_t batch) { return (batch + kPlanThreads - 1) / kPlanThreads; }
 
-hipError_t launch_range(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, hipStream_t st) {
-    int64_t blocks = (d.batch + 3) / 4;
-    if (blocks > 65536) blocks = 65536;
-    if (blocks < 1) blocks = 1;
+hipError_t launch_plan(const FitDesc& d, const Work& w, int maxM, int64_t tile, bool range_given, double c,
+                       double s, int dtype, const void* x, int64_t* block_tot, hipStream_t st) {
+    const int64_t nb = plan_blocks(d.batch);
     if (dtype == LSEFIT_F32)
-        hipLaunchKernelGGL(k_range_batched<float>, dim3(blocks), dim3(256), 0, st, d, w, maxM, (const float*)x);
+        hipLaunchKernelGGL(k_plan_count<float>, dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile,
+                           range_given ? 1 : 0, c, s, (const float*)x, block_tot);
     else
-        hipLaunchKernelGGL(k_range_batched<double>, dim3(blocks), dim3(256), 0, st, d, w, maxM, (const double*)x);
+        hipLaunchKernelGGL(k_plan_count<double>, dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile,
+                           range_given ? 1 : 0, c, s, (const double*)x, block_tot);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_plan_offsets, dim3(nb), dim3(kPlanThreads), 0, st, d, w, block_tot, nb);
     return hipGetLastError();
 }
 

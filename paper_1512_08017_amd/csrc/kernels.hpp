@@ -35,12 +35,11 @@ struct RangeArg {
     double c, s;
 };
 
-// Tile table, plan status and (for a given range) c, s of every fit.
+// Batched: tile table, plan status and (c, s) of every fit (given, or from a
+// sample of the fit's x), in two launches; block_tot holds plan_blocks(B) int64.
+int64_t plan_blocks(int64_t batch);
 hipError_t launch_plan(const FitDesc& d, const Work& w, int maxM, int64_t tile, bool range_given, double c,
-                       double s, hipStream_t st);
-
-// Batched: sampled range -> (c, s) per fit (a wave per fit).
-hipError_t launch_range(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, hipStream_t st);
+                       double s, int dtype, const void* x, int64_t* block_tot, hipStream_t st);
 
 // The power-sum pass: per-(wave, fit) partial sums (batched) or per-block
 // partial sums (single fit) into w.part.
@@ -69,5 +68,10 @@ hipError_t launch_refine(const FitDesc& d, const Work& w, int maxM, int dtype, c
 hipError_t launch_adjoint(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, const void* y,
                           const double* grad_coef, int32_t coef_stride, void* gx, void* gy, const Launch& L,
                           int mis, hipStream_t st);
+
+// Read-bandwidth probe over two float32 arrays of nvec 16-byte vectors each;
+// one float per block into out.
+hipError_t launch_read_probe(const float* x, const float* y, int64_t nvec, const Launch& L, int pattern, bool nt,
+                             float* out, hipStream_t st);
 
 }  // namespace lsefit

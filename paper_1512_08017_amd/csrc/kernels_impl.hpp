@@ -235,6 +235,43 @@ __device__ inline void stream_segment(const In* __restrict__ x, const In* __rest
     }
 }
 
+// single fit: the whole grid strides over the 16-byte vectors of x and y (wave
+// g reads vectors g*64 + lane, then every W*64 further), so consecutive waves
+// read consecutive kilobytes and the grid sweeps the arrays front to back.
+// Wave 0 also takes the unaligned head and the ragged tail.
+template <int U, typename In, class Acc>
+__device__ inline void stream_strided(const In* __restrict__ x, const In* __restrict__ y, int64_t n, int mis,
+                                      int64_t gwave, int64_t W, Acc& acc) {
+    constexpr int VW = VecOf<In>::W;
+    using V = typename VecOf<In>::type;
+    const int lane = lane_id();
+    const int64_t step = W * kWave;
+    if (mis >= 0) {
+        int64_t a = (VW - mis) % VW;
+        if (a > n) a = n;
+        const int64_t nv = (n - a) / VW;
+        const int64_t b = a + nv * VW;
+        if (gwave == 0 && lane < a) acc.scalar(ld_scalar(x + lane), ld_scalar(y + lane));
+        const V* __restrict__ xv = reinterpret_cast<const V*>(x + a);
+        const V* __restrict__ yv = reinterpret_cast<const V*>(y + a);
+        int64_t j = gwave * kWave + lane;
+        for (; j + (int64_t)(U - 1) * step < nv; j += (int64_t)U * step) {
+            V xs[U], ys[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                xs[u] = ld_stream(xv + j + u * step);
+                ys[u] = ld_stream(yv + j + u * step);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc.template vec<V, VW>(xs[u], ys[u]);
+        }
+        for (; j < nv; j += step) acc.template vec<V, VW>(ld_stream(xv + j), ld_stream(yv + j));
+        if (gwave == 0 && lane < n - b) acc.scalar(ld_scalar(x + b + lane), ld_scalar(y + b + lane));
+    } else {
+        for (int64_t i = gwave * kWave + lane; i < n; i += step) acc.scalar(ld_scalar(x + i), ld_scalar(y + i));
+    }
+}
+
 // run body.template operator()<m>() for the runtime degree m (1 <= m <= MAXM)
 template <int MAXM, class Body>
 __device__ inline void dispatch_degree(int m, Body&& body) {
@@ -381,6 +418,58 @@ __device__ inline void block_combine_fit(const FitDesc& d, const Work& w, int64_
     dispatch_degree<MAXM>(fit_deg(d, f), body);
 }
 
+// single fit: the threads of one block sum the G block partials (thread t takes
+// blocks t, t + blockDim, ...; then waves in order) and thread 0 finishes the fit
+template <int MAXM>
+__device__ inline void finish_single_block(const FitDesc& d, const Work& w, int64_t G, const Finish& fz) {
+    constexpr int stride = nacc(MAXM);
+    __shared__ double sh[16][stride];
+    const int pst = w.pstatus[0];
+    if (pst != LSEFIT_OK) {
+        if (threadIdx.x == 0 && fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, 0, fz, pst);
+        return;
+    }
+    auto body = [&]<int M>() {
+        constexpr int K = nacc(M);
+        const int nk = fz.mode == kRefine ? M + 1 : K;
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = 0.0;
+#pragma unroll 4
+        for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
+            const double* p = w.part + g * stride;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k < nk) v[k] += p[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) sh[wave_id_in_block()][k] = v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int nw = blockDim.x / kWave;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                double acc = sh[0][k];
+                for (int i = 1; i < nw; ++i) acc += sh[i][k];
+                v[k] = acc;
+            }
+            finish_fit<M, MAXM>(d, w, 0, v, fz);
+        }
+    };
+    dispatch_degree<MAXM>(d.degree, body);
+}
+
+constexpr int kFinishThreads = 256;
+
+template <int MAXM>
+__global__ void __launch_bounds__(kFinishThreads) k_finish_single(FitDesc d, Work w, int64_t G, Finish fz) {
+    finish_single_block<MAXM>(d, w, G, fz);
+}
+
 // ---------------------------------------------------------------------------
 // single fit: every block of the streaming grid derives (c, s) itself, from the
 // same sample (kSingleRangeSamples evenly strided points, first and last
@@ -470,19 +559,12 @@ __global__ void __launch_bounds__(256)
         auto body = [&]<int M>() {
             using Acc = std::conditional_t<PREC == LSEFIT_PREC_F64, AccF64<M>, AccF32C<M>>;
             double v[nacc(M)];
+            Acc acc;
+            acc.init(c, inv_s);
+            stream_strided<U>(x, y, d.n_single, mis, wave, W, acc);
+            acc.out(v);
 #pragma unroll
-            for (int k = 0; k < nacc(M); ++k) v[k] = 0.0;
-            const int64_t NT = (d.n_single + tile - 1) / tile;
-            const int64_t t0 = wave * NT / W, t1 = (wave + 1) * NT / W;
-            if (t0 < t1) {
-                Acc acc;
-                acc.init(c, inv_s);
-                const int64_t hi = t1 * tile < d.n_single ? t1 * tile : d.n_single;
-                stream_segment<U>(x, y, t0 * tile, hi, mis, acc);
-                acc.out(v);
-#pragma unroll
-                for (int k = 0; k < nacc(M); ++k) v[k] = wave_sum(v[k]);
-            }
+            for (int k = 0; k < nacc(M); ++k) v[k] = wave_sum(v[k]);
             single_block_partial<nacc(M), stride>(w, v);
         };
         dispatch_degree<MAXM>(d.degree, body);
@@ -527,13 +609,10 @@ __global__ void __launch_bounds__(256)
             double v[M + 1];
 #pragma unroll
             for (int k = 0; k <= M; ++k) v[k] = 0.0;
-            const int64_t NT = (d.n_single + tile - 1) / tile;
-            const int64_t t0 = wave * NT / W, t1 = (wave + 1) * NT / W;
-            if (ok && t0 < t1) {
+            if (ok) {
                 AccRefine<M> acc;
                 acc.init(c, inv_s, r + rec_b(MAXM));
-                const int64_t hi = t1 * tile < d.n_single ? t1 * tile : d.n_single;
-                stream_segment<U>(x, y, t0 * tile, hi, mis, acc);
+                stream_strided<U>(x, y, d.n_single, mis, wave, W, acc);
 #pragma unroll
                 for (int k = 0; k <= M; ++k) v[k] = wave_sum(acc.R[k]);
             }
@@ -562,52 +641,6 @@ __global__ void __launch_bounds__(256)
         };
         dispatch_degree<MAXM>(fit_deg(d, f), body);
     });
-}
-
-// single fit: one block sums the G block partials (thread t takes blocks t,
-// t + blockDim, ...; then waves in order) and finishes the fit
-constexpr int kFinishThreads = 1024;
-
-template <int MAXM>
-__global__ void __launch_bounds__(kFinishThreads) k_finish_single(FitDesc d, Work w, int64_t G, Finish fz) {
-    constexpr int stride = nacc(MAXM);
-    __shared__ double sh[kFinishThreads / kWave][stride];
-    const int pst = w.pstatus[0];
-    if (pst != LSEFIT_OK) {
-        if (threadIdx.x == 0 && fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, 0, fz, pst);
-        return;
-    }
-    auto body = [&]<int M>() {
-        constexpr int K = nacc(M);
-        const int nk = fz.mode == kRefine ? M + 1 : K;
-        double v[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = 0.0;
-        for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
-            const double* p = w.part + g * stride;
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k < nk) v[k] += p[k];
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-        if (lane_id() == 0) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) sh[wave_id_in_block()][k] = v[k];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const int nw = blockDim.x / kWave;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                double acc = sh[0][k];
-                for (int i = 1; i < nw; ++i) acc += sh[i][k];
-                v[k] = acc;
-            }
-            finish_fit<M, MAXM>(d, w, 0, v, fz);
-        }
-    };
-    dispatch_degree<MAXM>(d.degree, body);
 }
 
 template <int MAXM>

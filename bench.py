@@ -51,8 +51,8 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=100_000_000)
     ap.add_argument("--degree", type=int, default=3)
     ap.add_argument("--form", choices=("auto", "f64", "f32c"), default="auto")
@@ -68,7 +68,8 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="a few steps of each form plus one plain device copy of known size (for --pmc runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="turn two rocprofv3 --pmc output folders into the traffic summary in profiles/")
+                    help="turn two rocprofv3 --pmc output folders into the traffic summary")
+    ap.add_argument("--out", type=str, default=None, help="where --summarize-pmc writes (default: profiles/)")
     return ap.parse_args()
 
 
@@ -91,7 +92,7 @@ def _read_counter_csv(folder, counter):
     return rows
 
 
-def summarize_pmc(fetch_dir, write_dir):
+def summarize_pmc(fetch_dir, write_dir, out_path=None):
     out = {}
     for counter, folder in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _read_counter_csv(folder, counter)
@@ -106,14 +107,16 @@ def summarize_pmc(fetch_dir, write_dir):
              "python3 bench.py --pmc-probe",
              "#   rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o run --output-format csv -- "
              "python3 bench.py --pmc-probe",
-             "#   python3 bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write",
+             "#   python3 bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write "
+             "--out profiles/moments_cubic_f32_traffic.txt",
              f"# {COPY_BYTES_NOTE}",
              f"kernel_hash {kernel_hash()}"]
     for counter, d in out.items():
         for key, vals in d.items():
             lines.append(f"{counter}.{key} " + " ".join(f"{v:.1f}" for v in vals))
-    os.makedirs(PROFILES, exist_ok=True)
-    with open(TRAFFIC_FILE, "w") as fh:
+    out_path = out_path or TRAFFIC_FILE
+    os.makedirs(os.path.dirname(os.path.abspath(out_path)), exist_ok=True)
+    with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -442,7 +445,7 @@ def probe_sweep(args):
 def main():
     args = parse()
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc)
+        summarize_pmc(*args.summarize_pmc, out_path=args.out)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

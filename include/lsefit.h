@@ -88,6 +88,15 @@ typedef enum { LSEFIT_PREC_F64 = 0, LSEFIT_PREC_F32C = 1 } lsefit_precision;
  *                      on this choice except through rounding. */
 typedef enum { LSEFIT_RANGE_GIVEN = 0, LSEFIT_RANGE_AUTO = 1 } lsefit_range_mode;
 
+/* How the (m+1)x(m+1) normal system A X = B is solved.
+ *  LSEFIT_SOLVER_GEPP:     Gaussian elimination with partial pivoting (the
+ *                          method of the end of Sec. II).
+ *  LSEFIT_SOLVER_CHOLESKY: A = L L^T (A is symmetric positive definite for a
+ *                          determined fit), one of the "methods other than
+ *                          Gaussian elimination" Sec. V names.  SINGULAR when a
+ *                          diagonal of the factorisation is at most 2^-40 max|A|. */
+typedef enum { LSEFIT_SOLVER_GEPP = 0, LSEFIT_SOLVER_CHOLESKY = 1 } lsefit_solver;
+
 typedef struct lsefit_options {
     int32_t degree;        /* single fit: m in 1..LSEFIT_MAX_DEGREE; batched: the
                               largest degree present (each degrees[f] must be <= it) */
@@ -96,6 +105,7 @@ typedef struct lsefit_options {
     int32_t range_mode;    /* lsefit_range_mode */
     double center;         /* c for LSEFIT_RANGE_GIVEN */
     double scale;          /* s for LSEFIT_RANGE_GIVEN, > 0 */
+    int32_t solver;        /* lsefit_solver */
 } lsefit_options;
 
 /* Launch schedule of the streaming kernels.  Any valid schedule gives the
@@ -199,6 +209,21 @@ lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets,
                            const double* grad_coef, int32_t coef_stride,
                            void* grad_x, void* grad_y, void* stream);
 
+/* Residuals of fitted polynomials: the fitted values and errors of Table V
+ * (Sec. III), e_i = y_i - f(x_i), and the sum of squared errors Pi = sum e_i^2
+ * of Sec. II, per fit.  Must follow a fit on the same workspace (or plan), with
+ * the same x, y and options: the per-fit (c, s) and t-basis coefficients are
+ * read from there, and e_i is formed in the t variable in float64.
+ *  offsets:    NULL -> one fit of n points (after fit_single or fit_solve;
+ *              degrees and batch ignored); else the batch of fit_batched
+ *  sse:        output, device float64 [batch] (or [1]); NaN for fits whose
+ *              status is not OK
+ *  residuals:  optional output (NULL to skip), device, dtype dt, one per point */
+lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
+                            int64_t batch, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
+                            lsefit_plan* plan, void* ws, size_t ws_bytes, double* sse, void* residuals,
+                            void* stream);
+
 /* Plans for repeated batched calls of one shape.  fit_plan_create allocates
  * the plan's workspace (device memory, freed by fit_plan_destroy) for up to
  * `batch` fits of degree <= max_degree.  fit_plan_tune times candidate
@@ -235,7 +260,8 @@ lsefit_status lsefit_read_probe(const float* x, const float* y, int64_t n, const
  * for the recorded events of one kernel kind and returns the summed duration
  * in milliseconds and the number of launches since the last reset.
  *  kind: 0 = power-sum pass, 1 = refinement pass, 2 = adjoint pass,
- *        3 = per-fit combine and solve, 4 = read-bandwidth probe.
+ *        3 = per-fit combine and solve, 4 = read-bandwidth probe,
+ *        5 = residual pass.
  * Not synchronised with calls on other host threads. */
 lsefit_status lsefit_timing_enable(int32_t enable);
 lsefit_status lsefit_timing_reset(void);

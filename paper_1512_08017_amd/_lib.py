@@ -11,6 +11,7 @@ LSEFIT_MAX_DEGREE = 8
 OK, INVALID_ARG, SINGULAR, NONFINITE, WORKSPACE, DEVICE, UNSUPPORTED = range(7)
 F32, F64 = 0, 1
 PREC_F64, PREC_F32C = 0, 1
+SOLVER_GEPP, SOLVER_CHOLESKY = 0, 1
 RANGE_GIVEN, RANGE_AUTO = 0, 1
 
 STATUS_NAMES = {OK: "ok", INVALID_ARG: "invalid_arg", SINGULAR: "singular", NONFINITE: "nonfinite",
@@ -19,7 +20,7 @@ STATUS_NAMES = {OK: "ok", INVALID_ARG: "invalid_arg", SINGULAR: "singular", NONF
 # C-ABI symbols the library must export (one per declaration in include/lsefit.h)
 EXPORTS = (
     "lsefit_workspace_bytes", "lsefit_default_schedule", "lsefit_set_default_schedule",
-    "fit_moments", "fit_solve", "fit_single", "fit_batched", "fit_backward",
+    "fit_moments", "fit_solve", "fit_single", "fit_batched", "fit_backward", "fit_residuals",
     "fit_plan_create", "fit_plan_tune", "fit_plan_set_schedule", "fit_plan_get_schedule",
     "fit_plan_set_graph", "fit_plan_destroy", "lsefit_status_string", "lsefit_device_cus",
     "lsefit_timing_enable", "lsefit_timing_reset", "lsefit_timing_read", "lsefit_read_probe",
@@ -28,7 +29,8 @@ EXPORTS = (
 
 class Options(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("range_mode", ctypes.c_int32), ("center", ctypes.c_double), ("scale", ctypes.c_double)]
+                ("range_mode", ctypes.c_int32), ("center", ctypes.c_double), ("scale", ctypes.c_double),
+                ("solver", ctypes.c_int32)]
 
 
 class Schedule(ctypes.Structure):
@@ -70,6 +72,7 @@ def load():
     L.fit_single.argtypes = [vp, vp, i64, i32, OptP, vp, sz, vp, vp, vp, vp]
     L.fit_batched.argtypes = [vp, vp, vp, vp, i64, i32, OptP, vp, vp, sz, vp, i32, vp, vp]
     L.fit_backward.argtypes = [vp, vp, vp, vp, i64, i32, OptP, vp, vp, sz, vp, i32, vp, vp, vp]
+    L.fit_residuals.argtypes = [vp, vp, vp, vp, i64, i64, i32, OptP, vp, vp, sz, vp, vp, vp]
     L.fit_plan_create.argtypes = [ctypes.POINTER(vp), i64, i32, i32, i32]
     L.fit_plan_tune.argtypes = [vp, vp, vp, vp, vp, i64, OptP, vp, i32, vp, vp, i32, ctypes.POINTER(ctypes.c_double)]
     L.fit_plan_set_schedule.argtypes = [vp, SchP]
@@ -84,6 +87,7 @@ def load():
     L.lsefit_read_probe.argtypes = [vp, vp, i64, SchP, i32, i32, vp, sz, vp]
     L.lsefit_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     for name in ("lsefit_default_schedule", "lsefit_set_default_schedule", "fit_moments", "fit_solve", "fit_single",
+                 "fit_residuals",
                  "fit_batched", "fit_backward", "fit_plan_create", "fit_plan_tune", "fit_plan_set_schedule",
                  "fit_plan_get_schedule", "fit_plan_set_graph", "lsefit_timing_enable", "lsefit_timing_reset",
                  "lsefit_timing_read", "lsefit_read_probe"):

@@ -17,6 +17,7 @@ from ._lib import Options, Schedule, check
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
 _PREC = {"f64": _lib.PREC_F64, "f32c": _lib.PREC_F32C}
+_SOLVER = {"gepp": _lib.SOLVER_GEPP, "cholesky": _lib.SOLVER_CHOLESKY}
 
 
 def _ptr(t):
@@ -27,10 +28,14 @@ def _stream(dev):
     return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
 
 
-def options(degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None) -> Options:
+def options(degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None,
+            solver: str = "gepp") -> Options:
     if precision not in _PREC:
         raise ValueError(f"precision must be one of {sorted(_PREC)}")
+    if solver not in _SOLVER:
+        raise ValueError(f"solver must be one of {sorted(_SOLVER)}")
     o = Options()
+    o.solver = _SOLVER[solver]
     o.degree = int(degree)
     o.precision = _PREC[precision]
     o.refine_steps = int(refine) if precision == "f32c" else 0
@@ -94,6 +99,8 @@ class FitResult:
     coef_t: torch.Tensor     # b_0..b_m, t-basis, float64 (device)
     status: torch.Tensor     # int32 [1] (device)
     moments: torch.Tensor    # [c, s, S_0..S_2m, T_0..T_m] (device)
+    ws: torch.Tensor | None = None   # the workspace the fit left its records in
+    options: Options | None = None
 
     @property
     def center(self):
@@ -104,11 +111,11 @@ class FitResult:
         return float(self.moments[1])
 
 
-def fit_moments(x, y, degree, precision="f64", center=None, scale=None, ws=None):
+def fit_moments(x, y, degree, precision="f64", center=None, scale=None, ws=None, solver="gepp"):
     """Power sums [c, s, S_0..S_2m, T_0..T_m] of t = (x - c)/s (one streaming pass)."""
     _check_points(x, y)
     L = _lib.load()
-    o = options(degree, precision, 0, center, scale)
+    o = options(degree, precision, 0, center, scale, solver)
     nbytes = workspace_bytes(1, degree)
     if ws is None or ws.numel() < nbytes:
         ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
@@ -118,10 +125,11 @@ def fit_moments(x, y, degree, precision="f64", center=None, scale=None, ws=None)
     return mom, ws
 
 
-def fit_solve(moments, degree, precision="f64", refine=1, x=None, y=None, ws=None, center=None, scale=None):
-    """Gaussian elimination on the Hankel system, optional refinement, x-basis coefficients."""
+def fit_solve(moments, degree, precision="f64", refine=1, x=None, y=None, ws=None, center=None, scale=None,
+              solver="gepp"):
+    """Elimination on the Hankel system, optional refinement, x-basis coefficients."""
     L = _lib.load()
-    o = options(degree, precision, refine, center, scale)
+    o = options(degree, precision, refine, center, scale, solver)
     dev = moments.device
     nbytes = workspace_bytes(1, degree)
     if ws is None or ws.numel() < nbytes:
@@ -136,11 +144,11 @@ def fit_solve(moments, degree, precision="f64", refine=1, x=None, y=None, ws=Non
 
 
 def fit(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None,
-        ws=None) -> FitResult:
+        ws=None, solver: str = "gepp") -> FitResult:
     """Least-squares polynomial fit of degree ``degree`` (coefficients a_0 first), one fused call."""
     _check_points(x, y)
     L = _lib.load()
-    o = options(degree, precision, refine, center, scale)
+    o = options(degree, precision, refine, center, scale, solver)
     nbytes = workspace_bytes(1, degree)
     if ws is None or ws.numel() < nbytes:
         ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
@@ -150,15 +158,45 @@ def fit(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None,
     mom = torch.empty(3 * degree + 4, dtype=torch.float64, device=x.device)
     check(L.fit_single(_ptr(x), _ptr(y), x.numel(), _DT[x.dtype], ctypes.byref(o), _ptr(ws), ws.numel(),
                        _ptr(coef), _ptr(status), _ptr(mom), _stream(x.device)), "fit_single")
-    return FitResult(coef[:m1], coef[m1:], status, mom)
+    return FitResult(coef[:m1], coef[m1:], status, mom, ws, o)
 
 
-def fit_split(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None) -> FitResult:
+def fit_split(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None,
+              solver: str = "gepp") -> FitResult:
     """The same fit through the two-call form (fit_moments, then fit_solve)."""
-    mom, ws = fit_moments(x, y, degree, precision, center, scale)
-    coef, status = fit_solve(mom, degree, precision, refine, x, y, ws, center, scale)
+    mom, ws = fit_moments(x, y, degree, precision, center, scale, solver=solver)
+    coef, status = fit_solve(mom, degree, precision, refine, x, y, ws, center, scale, solver=solver)
     m1 = degree + 1
-    return FitResult(coef[:m1], coef[m1:], status, mom)
+    return FitResult(coef[:m1], coef[m1:], status, mom, ws, options(degree, precision, refine, center, scale, solver))
+
+
+def residuals(x, y, result: FitResult, store: bool = False):
+    """Sum of squared residuals of a single fit (and, with store=True, every
+    residual e_i = y_i - f(x_i)); `result` is what fit() returned for x, y."""
+    _check_points(x, y)
+    L = _lib.load()
+    sse = torch.empty(1, dtype=torch.float64, device=x.device)
+    res = torch.empty_like(x) if store else None
+    check(L.fit_residuals(_ptr(x), _ptr(y), None, None, 1, x.numel(), _DT[x.dtype], ctypes.byref(result.options),
+                          None, _ptr(result.ws), result.ws.numel(), _ptr(sse), _ptr(res), _stream(x.device)),
+          "fit_residuals")
+    return sse, res
+
+
+def residuals_batched(x, y, offsets, degrees, max_degree: int, ws=None, plan=None, store: bool = False,
+                      precision: str = "f64", center=None, scale=None, solver: str = "gepp"):
+    """Per-fit sums of squared residuals after fit_batched on the same workspace or plan."""
+    _check_batch(x, y, offsets, degrees)
+    L = _lib.load()
+    B = degrees.numel()
+    o = options(max_degree, precision, 0, center, scale, solver)
+    sse = torch.empty(B, dtype=torch.float64, device=x.device)
+    res = torch.empty_like(x) if store else None
+    check(L.fit_residuals(_ptr(x), _ptr(y), _ptr(offsets), _ptr(degrees), B, x.numel(), _DT[x.dtype],
+                          ctypes.byref(o), plan.handle if plan is not None else None,
+                          _ptr(ws) if plan is None else None, ws.numel() if (plan is None and ws is not None) else 0,
+                          _ptr(sse), _ptr(res), _stream(x.device)), "fit_residuals")
+    return sse, res
 
 
 # ---------------------------------------------------------------------------
@@ -203,10 +241,10 @@ class Plan:
         check(self._L.fit_plan_set_graph(self.handle, 1 if enable else 0), "fit_plan_set_graph")
 
     def tune(self, x, y, offsets, degrees, max_degree=None, precision=None, refine=1, center=None, scale=None,
-             reps=3) -> float:
+             reps=3, solver="gepp") -> float:
         _check_batch(x, y, offsets, degrees)
         m = self.max_degree if max_degree is None else max_degree
-        o = options(m, precision or self.precision, refine, center, scale)
+        o = options(m, precision or self.precision, refine, center, scale, solver)
         B = degrees.numel()
         coef = torch.empty(B * (m + 1), dtype=torch.float64, device=x.device)
         status = torch.empty(B, dtype=torch.int32, device=x.device)
@@ -231,12 +269,12 @@ def _check_batch(x, y, offsets, degrees):
 
 def fit_batched(x, y, offsets, degrees, max_degree: int, precision: str = "f64", refine: int = 1,
                 center=None, scale=None, plan: Plan | None = None, coef_stride: int | None = None,
-                ws: torch.Tensor | None = None, out=None):
+                ws: torch.Tensor | None = None, out=None, solver: str = "gepp"):
     """Independent fits over CSR segments; returns (coef [B, stride], status [B], ws)."""
     _check_batch(x, y, offsets, degrees)
     L = _lib.load()
     B = degrees.numel()
-    o = options(max_degree, precision, refine, center, scale)
+    o = options(max_degree, precision, refine, center, scale, solver)
     stride = coef_stride or (max_degree + 1)
     if out is None:
         coef = torch.zeros((B, stride), dtype=torch.float64, device=x.device)
@@ -255,12 +293,12 @@ def fit_batched(x, y, offsets, degrees, max_degree: int, precision: str = "f64",
 
 
 def fit_backward(x, y, offsets, degrees, max_degree, grad_coef, ws=None, plan=None, precision="f64",
-                 center=None, scale=None):
+                 center=None, scale=None, solver="gepp"):
     """dL/dx, dL/dy from dL/da (grad_coef [B, stride] float64) after fit_batched."""
     _check_batch(x, y, offsets, degrees)
     L = _lib.load()
     B = degrees.numel()
-    o = options(max_degree, precision, 0, center, scale)
+    o = options(max_degree, precision, 0, center, scale, solver)
     grad_coef = grad_coef.to(torch.float64).contiguous()
     gx = torch.empty_like(x)
     gy = torch.empty_like(y)

@@ -42,7 +42,7 @@ Layout layout(int64_t B, int maxM, int64_t W) {
     L.part = off;
     off = align_up(off + sizeof(double) * (size_t)(W + B) * nacc(maxM));
     L.block_tot = off;
-    off = align_up(off + sizeof(int64_t) * (size_t)((B + 1023) / 1024));
+    off = align_up(off + sizeof(int64_t) * (size_t)((B + kPlanThreads - 1) / kPlanThreads));
     L.total = off + kAlign;   // slack for aligning the caller's base pointer
     return L;
 }
@@ -130,6 +130,7 @@ bool opts_ok(const lsefit_options* o, int dt, bool batched) {
     if (o->range_mode == LSEFIT_RANGE_GIVEN && !(std::isfinite(o->center) && std::isfinite(o->scale) && o->scale > 0))
         return false;
     if (dt != LSEFIT_F32 && dt != LSEFIT_F64) return false;
+    if (o->solver != LSEFIT_SOLVER_GEPP && o->solver != LSEFIT_SOLVER_CHOLESKY) return false;
     (void)batched;
     return true;
 }
@@ -144,15 +145,23 @@ bool refining(const lsefit_options* o) { return o->precision == LSEFIT_PREC_F32C
 // ---------------------------------------------------------------------------
 // optional kernel timing: event pairs around streaming launches
 // ---------------------------------------------------------------------------
-enum TimedKind { kTimeMoments = 0, kTimeRefine = 1, kTimeAdjoint = 2, kTimeCombine = 3, kTimeProbe = 4, kTimeKinds = 5 };
+enum TimedKind {
+    kTimeMoments = 0,
+    kTimeRefine = 1,
+    kTimeAdjoint = 2,
+    kTimeCombine = 3,
+    kTimeProbe = 4,
+    kTimeResidual = 5,
+    kTimeKinds = 6
+};
 
 struct Timing {
     std::mutex mu;
     bool enabled = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kTimeKinds];
     std::vector<hipEvent_t> pool;
-    double total_ms[kTimeKinds] = {0, 0, 0, 0, 0};
-    int64_t launches[kTimeKinds] = {0, 0, 0, 0, 0};
+    double total_ms[kTimeKinds] = {};
+    int64_t launches[kTimeKinds] = {};
 };
 Timing g_timing;
 
@@ -209,8 +218,8 @@ lsefit_status enqueue_batched(const FitDesc& d, const Work& w, const lsefit_opti
     const bool given = o->range_mode == LSEFIT_RANGE_GIVEN;
     const int mis = common_mis(dt, {x, y});
     const bool by_block = L.waves >= 64 * d.batch;
-    const Finish solve{kSolve, coef, coef_stride, 0, status, nullptr};
-    const Finish refine{kRefine, coef, coef_stride, 0, status, nullptr};
+    const Finish solve{kSolve, coef, coef_stride, 0, status, nullptr, o->solver};
+    const Finish refine{kRefine, coef, coef_stride, 0, status, nullptr, o->solver};
     LSEFIT_TRY(launch_plan(d, w, maxM, L.tile, given, o->center, o->scale, dt, x, w.block_tot, st));
     const RangeArg ra{LSEFIT_RANGE_GIVEN, 0.0, 1.0};   // per-fit (c, s) are in the records
     LSEFIT_TRY(timed(kTimeMoments, st,
@@ -352,7 +361,7 @@ lsefit_status fit_moments(const void* x, const void* y, int64_t n, lsefit_dtype 
     const lsefit_status v = check_single(x, y, n, dt, opt, ws, ws_bytes, &lay, &sched);
     if (v != LSEFIT_OK) return v;
     const FitDesc d{nullptr, nullptr, n, 1, opt->degree};
-    const Finish fz{kMomentsOnly, nullptr, 0, 0, nullptr, moments};
+    const Finish fz{kMomentsOnly, nullptr, 0, 0, nullptr, moments, opt->solver};
     return single_pass(false, d, carve(ws, lay), opt, dt, x, y, to_launch(sched), common_mis(dt, {x, y}), fz,
                        (hipStream_t)stream);
 }
@@ -371,9 +380,9 @@ lsefit_status fit_solve(const double* moments, const lsefit_options* opt, const 
     hipStream_t st = (hipStream_t)stream;
     const FitDesc d{nullptr, nullptr, refine ? n : 0, 1, opt->degree};
     const Work w = carve(ws, lay);
-    LSEFIT_TRY(launch_solve_moments(moments, w, opt->degree, opt->degree, coef, status, st));
+    LSEFIT_TRY(launch_solve_moments(moments, w, opt->degree, opt->degree, opt->solver, coef, status, st));
     if (!refine) return LSEFIT_OK;
-    const Finish fz{kRefine, coef, 2 * (opt->degree + 1), 1, status, nullptr};
+    const Finish fz{kRefine, coef, 2 * (opt->degree + 1), 1, status, nullptr, opt->solver};
     return single_pass(true, d, w, opt, dt, x, y, to_launch(sched), common_mis(dt, {x, y}), fz, st);
 }
 
@@ -390,10 +399,10 @@ lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype d
     const Launch L = to_launch(sched);
     const int mis = common_mis(dt, {x, y});
     const int stride = 2 * (opt->degree + 1);
-    const Finish solve{kSolve, coef, stride, 1, status, moments};
+    const Finish solve{kSolve, coef, stride, 1, status, moments, opt->solver};
     lsefit_status r = single_pass(false, d, w, opt, dt, x, y, L, mis, solve, st);
     if (r != LSEFIT_OK || !refining(opt)) return r;
-    const Finish fz{kRefine, coef, stride, 1, status, nullptr};
+    const Finish fz{kRefine, coef, stride, 1, status, nullptr, opt->solver};
     return single_pass(true, d, w, opt, dt, x, y, L, mis, fz, st);
 }
 
@@ -468,9 +477,53 @@ lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets,
     }
     const int mis = common_mis(dt, {x, y, grad_x, grad_y});
     LSEFIT_TRY(timed(kTimeAdjoint, st, [&] {
-        return launch_adjoint(d, w, opt->degree, dt, x, y, grad_coef, coef_stride, grad_x, grad_y, to_launch(sched),
+        return launch_adjoint(d, w, opt->degree, opt->solver, dt, x, y, grad_coef, coef_stride, grad_x, grad_y,
+                              to_launch(sched),
                               mis, st);
     }));
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
+                            int64_t batch, int64_t n, lsefit_dtype dt, const lsefit_options* opt, lsefit_plan* plan,
+                            void* ws, size_t ws_bytes, double* sse, void* residuals, void* stream) {
+    if (!x || !y || !sse || !opts_ok(opt, dt, offsets != nullptr)) return LSEFIT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const int mis = common_mis(dt, {x, y, residuals});
+    if (!offsets) {
+        if (n < (int64_t)opt->degree + 1 || !ws) return LSEFIT_ERR_INVALID_ARG;
+        const lsefit_schedule sched = current_default();
+        const Layout lay = layout(1, opt->degree, to_launch(sched).waves);
+        if (ws_bytes < lay.total) return LSEFIT_ERR_WORKSPACE;
+        const FitDesc d{nullptr, nullptr, n, 1, opt->degree};
+        const Work w = carve(ws, lay);
+        const Launch L = to_launch(sched);
+        const Finish fz{kSSE, sse, 1, 0, nullptr, nullptr, opt->solver};
+        LSEFIT_TRY(timed(kTimeResidual, st,
+                         [&] { return launch_residual(d, w, opt->degree, dt, x, y, residuals, L, mis, st); }));
+        LSEFIT_TRY(launch_finish_single(d, w, opt->degree, grid_blocks(L), fz, st));
+        return LSEFIT_OK;
+    }
+    if (batch < 0 || !degrees) return LSEFIT_ERR_INVALID_ARG;
+    if (batch == 0) return LSEFIT_OK;
+    const FitDesc d{offsets, degrees, 0, batch, opt->degree};
+    Work w;
+    lsefit_schedule sched;
+    if (plan) {
+        if (batch > plan->batch || opt->degree > plan->max_degree || dt != plan->dtype) return LSEFIT_ERR_INVALID_ARG;
+        w = carve(plan->ws, layout(plan->batch, plan->max_degree, plan->max_waves));
+        sched = plan->sched;
+    } else {
+        sched = current_default();
+        const Layout lay = layout(batch, opt->degree, to_launch(sched).waves);
+        if (!ws || ws_bytes < lay.total) return LSEFIT_ERR_WORKSPACE;
+        w = carve(ws, lay);
+    }
+    const Launch L = to_launch(sched);
+    const Finish fz{kSSE, sse, 1, 0, nullptr, nullptr, opt->solver};
+    LSEFIT_TRY(timed(kTimeResidual, st,
+                     [&] { return launch_residual(d, w, opt->degree, dt, x, y, residuals, L, mis, st); }));
+    LSEFIT_TRY(launch_combine(d, w, opt->degree, L, L.waves >= 64 * d.batch, fz, st));
     return LSEFIT_OK;
 }
 

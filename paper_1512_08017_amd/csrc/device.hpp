@@ -52,8 +52,12 @@ struct Work {
     double* rec;          // [B * rec_len(M)]
     double* part;         // [(W + B) * nacc(M)] per-(wave, fit) partial sums (batched) or
                           // per-block partial sums (single fit)
-    int64_t* block_tot;   // [ceil(B / 1024)] tile totals of the tile-table blocks
+    int64_t* block_tot;   // [ceil(B / kPlanThreads)] tile totals of the tile-table blocks
 };
+
+// threads per block of the tile-table kernels (one thread per fit); the
+// workspace holds one tile total per such block
+constexpr int kPlanThreads = 256;
 
 // ---------------------------------------------------------------------------
 // wave-level reductions.  The float64 sum runs on DPP lane moves (CDNA keeps the
@@ -242,6 +246,73 @@ __device__ inline int hankel_solve(const double* S, const double (&rhs)[R][N], d
         for (int i = 0; i < N; ++i)
             if (!isfinite(X[r][i])) return LSEFIT_ERR_NONFINITE;
     return LSEFIT_OK;
+}
+
+// Cholesky (L L^T) solve of the same normal system: A_jk = S_(j+k) is symmetric
+// positive definite when the fit is determined, so no pivoting is needed.
+// Singular when a diagonal of the Schur complement is at most 2^-40 max|A|.
+template <int N, int R>
+__device__ inline int hankel_cholesky(const double* S, const double (&rhs)[R][N], double (&X)[R][N]) {
+    double Lm[N][N];
+    double amax = 0.0;
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k <= 2 * (N - 1); ++k) {
+        finite = finite && isfinite(S[k]);
+        amax = fmax(amax, fabs(S[k]));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < N; ++j) finite = finite && isfinite(rhs[r][j]);
+    if (!finite) return LSEFIT_ERR_NONFINITE;
+    const double tiny = ldexp(amax, -40);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double dgl = S[2 * j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) dgl -= Lm[j][k] * Lm[j][k];
+        if (!(dgl > tiny)) return LSEFIT_ERR_SINGULAR;
+        const double ljj = sqrt(dgl);
+        Lm[j][j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < N; ++i) {
+            double acc = S[i + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) acc -= Lm[i][k] * Lm[j][k];
+            Lm[i][j] = acc / ljj;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double z[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double acc = rhs[r][i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) acc -= Lm[i][k] * z[k];
+            z[i] = acc / Lm[i][i];
+        }
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) {
+            double acc = z[i];
+#pragma unroll
+            for (int k = i + 1; k < N; ++k) acc -= Lm[k][i] * X[r][k];
+            X[r][i] = acc / Lm[i][i];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (!isfinite(X[r][i])) return LSEFIT_ERR_NONFINITE;
+    return LSEFIT_OK;
+}
+
+// the normal-system solve the options ask for
+template <int N, int R>
+__device__ inline int normal_solve(int solver, const double* S, const double (&rhs)[R][N], double (&X)[R][N]) {
+    return solver == LSEFIT_SOLVER_CHOLESKY ? hankel_cholesky<N, R>(S, rhs, X) : hankel_solve<N, R>(S, rhs, X);
 }
 
 // t-basis b (t = (x - c)/s) to x-basis a: a_k = sum_{j>=k} b_j C(j,k) (-c)^(j-k) s^-j

@@ -16,7 +16,6 @@ namespace lsefit {
 // scans the tile counts of its block.  Pass B adds the tile totals of the
 // blocks before it.  Integer sums: the result does not depend on the order.
 // ---------------------------------------------------------------------------
-constexpr int kPlanThreads = 1024;
 constexpr int kRangeBatchSamples = 16;
 
 template <typename In>
@@ -205,9 +204,9 @@ hipError_t launch_combine(const FitDesc& d, const Work& w, int maxM, const Launc
     LSEFIT_SWITCH_MAXM(maxM, return Launchers<MM>::combine(d, w, L, by_block, fz, st));
 }
 
-hipError_t launch_solve_moments(const double* moments, const Work& w, int m, int maxM, double* coef,
+hipError_t launch_solve_moments(const double* moments, const Work& w, int m, int maxM, int solver, double* coef,
                                 int32_t* status, hipStream_t st) {
-    LSEFIT_SWITCH_MAXM(maxM, return Launchers<MM>::solve_moments(moments, w, m, coef, status, st));
+    LSEFIT_SWITCH_MAXM(maxM, return Launchers<MM>::solve_moments(moments, w, m, solver, coef, status, st));
 }
 
 hipError_t launch_refine(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, const void* y,
@@ -215,11 +214,16 @@ hipError_t launch_refine(const FitDesc& d, const Work& w, int maxM, int dtype, c
     LSEFIT_SWITCH_MAXM(maxM, return Launchers<MM>::refine(d, w, dtype, x, y, L, mis, st));
 }
 
-hipError_t launch_adjoint(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, const void* y,
-                          const double* grad_coef, int32_t coef_stride, void* gx, void* gy, const Launch& L,
-                          int mis, hipStream_t st) {
-    LSEFIT_SWITCH_MAXM(maxM, return Launchers<MM>::adjoint(d, w, dtype, x, y, grad_coef, coef_stride, gx, gy, L,
-                                                           mis, st));
+hipError_t launch_adjoint(const FitDesc& d, const Work& w, int maxM, int solver, int dtype, const void* x,
+                          const void* y, const double* grad_coef, int32_t coef_stride, void* gx, void* gy,
+                          const Launch& L, int mis, hipStream_t st) {
+    LSEFIT_SWITCH_MAXM(maxM, return Launchers<MM>::adjoint(d, w, solver, dtype, x, y, grad_coef, coef_stride, gx, gy,
+                                                           L, mis, st));
+}
+
+hipError_t launch_residual(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, const void* y,
+                           void* resid, const Launch& L, int mis, hipStream_t st) {
+    LSEFIT_SWITCH_MAXM(maxM, return Launchers<MM>::residual(d, w, dtype, x, y, resid, L, mis, st));
 }
 
 }  // namespace lsefit

@@ -15,18 +15,20 @@ struct Launch {
     int32_t unroll;       // vector loads in flight per lane and array
 };
 
-enum CombineMode { kNoFinish = -1, kMomentsOnly = 0, kSolve = 1, kRefine = 2 };
+enum CombineMode { kNoFinish = -1, kMomentsOnly = 0, kSolve = 1, kRefine = 2, kSSE = 3 };
 
 // What happens once the partial sums of a fit are complete: write its power
-// sums (kMomentsOnly), solve (kSolve), or apply the refinement correction
-// (kRefine).  Passed to the combine and finish kernels.
+// sums (kMomentsOnly), solve (kSolve), apply the refinement correction
+// (kRefine), or store the sum of squared residuals (kSSE, into coef[f]).
+// Passed to the combine and finish kernels.
 struct Finish {
     int mode;
-    double* coef;          // [B * coef_stride] x-basis coefficients
+    double* coef;          // [B * coef_stride] x-basis coefficients (kSSE: [B] sums)
     int32_t coef_stride;
     int write_b;           // also write the t-basis solution after a_0..a_m
     int32_t* status;       // [B]
     double* moments_out;   // nullable: [3m+4] = c, s, S_0..S_2m, T_0..T_m
+    int solver;            // lsefit_solver
 };
 
 // Range of a single fit: given (c, s), or derived by the streaming kernel itself.
@@ -57,7 +59,7 @@ hipError_t launch_combine(const FitDesc& d, const Work& w, int maxM, const Launc
                           const Finish& fz, hipStream_t st);
 
 // Solve one fit from caller-provided power sums [c, s, S_0..S_2m, T_0..T_m].
-hipError_t launch_solve_moments(const double* moments, const Work& w, int m, int maxM, double* coef,
+hipError_t launch_solve_moments(const double* moments, const Work& w, int m, int maxM, int solver, double* coef,
                                 int32_t* status, hipStream_t st);
 
 // Refinement pass: per-(wave, fit) partial sums of t^j (y - f(t)) into w.part.
@@ -65,9 +67,14 @@ hipError_t launch_refine(const FitDesc& d, const Work& w, int maxM, int dtype, c
                          const Launch& L, int mis, hipStream_t st);
 
 // Adjoint: lambda per fit, then dL/dx, dL/dy per point.
-hipError_t launch_adjoint(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, const void* y,
-                          const double* grad_coef, int32_t coef_stride, void* gx, void* gy, const Launch& L,
-                          int mis, hipStream_t st);
+hipError_t launch_adjoint(const FitDesc& d, const Work& w, int maxM, int solver, int dtype, const void* x,
+                          const void* y, const double* grad_coef, int32_t coef_stride, void* gx, void* gy,
+                          const Launch& L, int mis, hipStream_t st);
+
+// Residual pass: e = y - f(t) per point (optionally stored) and partial sums of
+// e^2 (per block for a single fit, per wave and fit for a batch) into w.part.
+hipError_t launch_residual(const FitDesc& d, const Work& w, int maxM, int dtype, const void* x, const void* y,
+                           void* resid, const Launch& L, int mis, hipStream_t st);
 
 // Read-bandwidth probe over two float32 arrays of nvec 16-byte vectors each;
 // one float per block into out.

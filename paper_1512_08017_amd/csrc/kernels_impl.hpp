@@ -58,16 +58,17 @@ struct AccF64 {
         nc = -c * is;
     }
     __device__ inline void point(double xv, double yv) {
-        const double t = fma(xv, inv_s, nc);
-        double p = t;
-        T[0] += yv;
-        S[0] += p;
-        T[1] = fma(yv, p, T[1]);
+        // powers by a product tree, p_k = p_(k/2) p_(k - k/2): depth ceil(log2 2M)
+        // instead of a chain of 2M - 1 dependent multiplies
+        double p[2 * M + 1];
+        p[1] = fma(xv, inv_s, nc);
 #pragma unroll
-        for (int k = 2; k <= 2 * M; ++k) {
-            p *= t;
-            S[k - 1] += p;
-            if (k <= M) T[k] = fma(yv, p, T[k]);
+        for (int k = 2; k <= 2 * M; ++k) p[k] = p[k / 2] * p[k - k / 2];
+        T[0] += yv;
+#pragma unroll
+        for (int k = 1; k <= 2 * M; ++k) {
+            S[k - 1] += p[k];
+            if (k <= M) T[k] = fma(yv, p[k], T[k]);
         }
     }
     template <typename V, int VW>
@@ -118,12 +119,18 @@ struct AccF32C {
 #pragma unroll
         for (int e = 1; e < G; ++e) g += ys[e];
         kahan(T[0], cT[0], g);
+        // powers by a product tree per point (as in the float64 form)
+        float pw[2 * M + 1][G];
+#pragma unroll
+        for (int e = 0; e < G; ++e) {
+            pw[1][e] = t[e];
+#pragma unroll
+            for (int k = 2; k <= 2 * M; ++k) pw[k][e] = pw[k / 2][e] * pw[k - k / 2][e];
+        }
 #pragma unroll
         for (int k = 1; k <= 2 * M; ++k) {
-            if (k > 1) {
 #pragma unroll
-                for (int e = 0; e < G; ++e) p[e] *= t[e];
-            }
+            for (int e = 0; e < G; ++e) p[e] = pw[k][e];
             float gs = p[0];
 #pragma unroll
             for (int e = 1; e < G; ++e) gs += p[e];
@@ -296,6 +303,10 @@ __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, co
                                   const Finish& fz) {
     constexpr int N = M + 1;
     constexpr int rl = rec_len(MAXM);
+    if (fz.mode == kSSE) {
+        fz.coef[f] = v[0];
+        return;
+    }
     double* r = w.rec + f * rl;
     const double c = r[0], s = r[1];
     double* a_out = fz.coef + f * (int64_t)fz.coef_stride;
@@ -308,7 +319,7 @@ __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, co
         double R[1][N], delta[1][N];
 #pragma unroll
         for (int j = 0; j < N; ++j) R[0][j] = v[j];
-        st = hankel_solve<N, 1>(S, R, delta);
+        st = normal_solve<N, 1>(fz.solver, S, R, delta);
 #pragma unroll
         for (int j = 0; j < N; ++j) b[0][j] = r[rec_b(MAXM) + j] + delta[0][j];
     } else {
@@ -331,7 +342,7 @@ __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, co
             for (int j = 0; j < N; ++j) fz.moments_out[3 + 2 * M + j] = T[0][j];
         }
         if (fz.mode == kMomentsOnly) return;
-        st = hankel_solve<N, 1>(S, T, b);
+        st = normal_solve<N, 1>(fz.solver, S, T, b);
     }
     if (st == LSEFIT_OK) {
         to_x_basis<N>(b[0], c, s, a);
@@ -357,6 +368,10 @@ __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, co
 // them when the degree itself is out of range) and its status
 template <int MAXM>
 __device__ inline void fail_fit(const FitDesc& d, const Work& w, int64_t f, const Finish& fz, int st) {
+    if (fz.mode == kSSE) {
+        fz.coef[f] = NAN;
+        return;
+    }
     const int m = fit_deg(d, f);
     const bool valid = m >= 1 && m <= MAXM;
     const int n = valid ? m + 1 : fz.coef_stride;
@@ -385,7 +400,7 @@ __device__ inline void block_combine_fit(const FitDesc& d, const Work& w, int64_
     const int64_t w0 = wave_of_tile(ts, NT, W), w1 = wave_of_tile(te - 1, NT, W);
     auto body = [&]<int M>() {
         constexpr int K = nacc(M);
-        const int nk = fz.mode == kRefine ? M + 1 : K;
+        const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
         double v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = 0.0;
@@ -431,7 +446,7 @@ __device__ inline void finish_single_block(const FitDesc& d, const Work& w, int6
     }
     auto body = [&]<int M>() {
         constexpr int K = nacc(M);
-        const int nk = fz.mode == kRefine ? M + 1 : K;
+        const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
         double v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = 0.0;
@@ -658,7 +673,7 @@ __global__ void __launch_bounds__(256) k_combine_lane(FitDesc d, Work w, int64_t
     const int64_t w0 = wave_of_tile(ts, NT, W), w1 = wave_of_tile(te - 1, NT, W);
     auto body = [&]<int M>() {
         constexpr int K = nacc(M);
-        const int nk = fz.mode == kRefine ? M + 1 : K;
+        const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
         double v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = 0.0;
@@ -682,7 +697,7 @@ __global__ void __launch_bounds__(kCombineThreads) k_combine_block(FitDesc d, Wo
 }
 
 template <int M, int MAXM>
-__global__ void k_solve_moments(const double* __restrict__ mom, Work w, double* coef, int32_t* status) {
+__global__ void k_solve_moments(const double* __restrict__ mom, Work w, int solver, double* coef, int32_t* status) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     constexpr int N = M + 1;
     constexpr int rl = rec_len(MAXM);
@@ -699,7 +714,7 @@ __global__ void k_solve_moments(const double* __restrict__ mom, Work w, double* 
     for (int k = 0; k <= 2 * M; ++k) r[rec_S(MAXM) + k] = S[k];
 #pragma unroll
     for (int j = 0; j < N; ++j) r[rec_T(MAXM) + j] = T[0][j];
-    int st = (s > 0.0 && isfinite(c) && isfinite(s)) ? hankel_solve<N, 1>(S, T, b) : LSEFIT_ERR_NONFINITE;
+    int st = (s > 0.0 && isfinite(c) && isfinite(s)) ? normal_solve<N, 1>(solver, S, T, b) : LSEFIT_ERR_NONFINITE;
     if (st == LSEFIT_OK) {
         to_x_basis<N>(b[0], c, s, a);
 #pragma unroll
@@ -726,7 +741,7 @@ __global__ void k_solve_moments(const double* __restrict__ mom, Work w, double* 
 // ---------------------------------------------------------------------------
 template <int MAXM>
 __global__ void __launch_bounds__(256)
-    k_adjoint_solve(FitDesc d, Work w, const double* __restrict__ gcoef, int32_t coef_stride) {
+    k_adjoint_solve(FitDesc d, Work w, int solver, const double* __restrict__ gcoef, int32_t coef_stride) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.batch) return;
     if (w.pstatus[f] != LSEFIT_OK) return;
@@ -740,7 +755,7 @@ __global__ void __launch_bounds__(256)
         to_t_basis_adjoint<N>(g, r[0], r[1], gt[0]);
 #pragma unroll
         for (int k = 0; k <= 2 * M; ++k) S[k] = r[rec_S(MAXM) + k];
-        const int st = hankel_solve<N, 1>(S, gt, lam);
+        const int st = normal_solve<N, 1>(solver, S, gt, lam);
 #pragma unroll
         for (int k = 0; k < N; ++k) r[rec_lam(MAXM) + k] = st == LSEFIT_OK ? lam[0][k] : NAN;
     };
@@ -830,6 +845,114 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
+// residual pass (Table V of Sec. III): e = y - f(t), f = sum_j b_j t^j in
+// float64, optionally stored; partial sums of e^2 as in the power-sum pass
+// ---------------------------------------------------------------------------
+template <int M>
+struct ResidPoint {
+    double b[M + 1];
+    double inv_s, nc;
+    __device__ inline void init(const double* r, int MAXM_) {
+        inv_s = 1.0 / r[1];
+        nc = -r[0] * inv_s;
+#pragma unroll
+        for (int j = 0; j <= M; ++j) b[j] = r[rec_b(MAXM_) + j];
+    }
+    __device__ inline double err(double xv, double yv) const {
+        const double t = fma(xv, inv_s, nc);
+        double f = b[M];
+#pragma unroll
+        for (int j = M - 1; j >= 0; --j) f = fma(f, t, b[j]);
+        return yv - f;
+    }
+};
+
+// one wave: points [lo, hi) of one fit (or the whole grid-stride share of a
+// single fit when `strided`), e^2 summed per lane into acc, e stored if resid
+template <int M, typename In, bool STRIDED>
+__device__ inline void resid_points(const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ resid,
+                                    int64_t lo, int64_t hi, int mis, int64_t gwave, int64_t W,
+                                    const ResidPoint<M>& P, double& acc) {
+    constexpr int VW = VecOf<In>::W;
+    using V = typename VecOf<In>::type;
+    const int lane = lane_id();
+    const int64_t step = STRIDED ? W * kWave : kWave;
+    const int64_t first = STRIDED ? gwave * kWave + lane : lane;
+    const bool edge_wave = STRIDED ? gwave == 0 : true;
+    auto one = [&](int64_t i) {
+        const double e = P.err((double)x[i], (double)y[i]);
+        acc = fma(e, e, acc);
+        if (resid) resid[i] = (In)e;
+    };
+    if (mis >= 0) {
+        int64_t a = lo + (int64_t)((VW - (int)((lo + mis) % VW)) % VW);
+        if (a > hi) a = hi;
+        const int64_t nv = (hi - a) / VW;
+        const int64_t b = a + nv * VW;
+        if (edge_wave && lane < a - lo) one(lo + lane);
+        const V* xv = reinterpret_cast<const V*>(x + a);
+        const V* yv = reinterpret_cast<const V*>(y + a);
+        V* rv = resid ? reinterpret_cast<V*>(resid + a) : nullptr;
+        for (int64_t j = first; j < nv; j += step) {
+            const V xs = ld_stream(xv + j), ys = ld_stream(yv + j);
+            V os;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                const double er = P.err((double)xs[e], (double)ys[e]);
+                acc = fma(er, er, acc);
+                os[e] = (In)er;
+            }
+            if (rv) __builtin_nontemporal_store(os, rv + j);
+        }
+        if (edge_wave && lane < hi - b) one(b + lane);
+    } else {
+        for (int64_t i = lo + first; i < hi; i += step) one(i);
+    }
+}
+
+template <int MAXM, typename In>
+__global__ void __launch_bounds__(256)
+    k_residual(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ resid,
+               int64_t tile, int64_t W, int mis) {
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    constexpr int stride = nacc(MAXM);
+    constexpr int rl = rec_len(MAXM);
+    if (is_single(d)) {
+        const bool ok = w.pstatus[0] == LSEFIT_OK;
+        auto body = [&]<int M>() {
+            double acc = 0.0;
+            if (ok) {
+                ResidPoint<M> P;
+                P.init(w.rec, MAXM);
+                resid_points<M, In, true>(x, y, resid, 0, d.n_single, mis, wave, W, P, acc);
+            } else if (resid) {
+                for (int64_t i = wave * kWave + lane_id(); i < d.n_single; i += W * kWave) resid[i] = (In)NAN;
+            }
+            double v[1] = {wave_sum(acc)};
+            single_block_partial<1, stride>(w, v);
+        };
+        dispatch_degree<MAXM>(d.degree, body);
+        return;
+    }
+    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
+        if (w.pstatus[f] != LSEFIT_OK) {
+            if (resid)
+                for (int64_t i = lo + lane_id(); i < hi; i += kWave) resid[i] = (In)NAN;
+            return;
+        }
+        auto body = [&]<int M>() {
+            ResidPoint<M> P;
+            P.init(w.rec + f * rl, MAXM);
+            double acc = 0.0;
+            resid_points<M, In, false>(x, y, resid, lo, hi, mis, 0, W, P, acc);
+            acc = wave_sum(acc);
+            if (lane_id() == 0) w.part[slot * stride] = acc;
+        };
+        dispatch_degree<MAXM>(fit_deg(d, f), body);
+    });
+}
+
+// ---------------------------------------------------------------------------
 // per-degree launchers (explicitly instantiated once per largest degree)
 // ---------------------------------------------------------------------------
 inline int64_t blocks_for(const Launch& L) { return (L.waves + L.wpb - 1) / L.wpb; }
@@ -883,13 +1006,13 @@ hipError_t Launchers<MAXM>::finish_single(const FitDesc& d, const Work& w, int64
 }
 
 template <int MAXM>
-hipError_t Launchers<MAXM>::solve_moments(const double* moments, const Work& w, int m, double* coef,
+hipError_t Launchers<MAXM>::solve_moments(const double* moments, const Work& w, int m, int solver, double* coef,
                                           int32_t* status, hipStream_t st) {
     switch (m) {
 #define LSEFIT_SOLVE_CASE(MV)                                                                                   \
     case MV:                                                                                                    \
         if constexpr (MV <= MAXM) {                                                                             \
-            hipLaunchKernelGGL((k_solve_moments<MV, MAXM>), dim3(1), dim3(64), 0, st, moments, w, coef, status); \
+            hipLaunchKernelGGL((k_solve_moments<MV, MAXM>), dim3(1), dim3(64), 0, st, moments, w, solver, coef, status); \
             return hipGetLastError();                                                                           \
         }                                                                                                       \
         break;
@@ -930,12 +1053,12 @@ hipError_t Launchers<MAXM>::refine(const FitDesc& d, const Work& w, int dtype, c
 }
 
 template <int MAXM>
-hipError_t Launchers<MAXM>::adjoint(const FitDesc& d, const Work& w, int dtype, const void* x, const void* y,
-                                    const double* grad_coef, int32_t coef_stride, void* gx, void* gy,
+hipError_t Launchers<MAXM>::adjoint(const FitDesc& d, const Work& w, int solver, int dtype, const void* x,
+                                    const void* y, const double* grad_coef, int32_t coef_stride, void* gx, void* gy,
                                     const Launch& L, int mis, hipStream_t st) {
     const int64_t sblocks = (d.batch + 255) / 256;
-    hipLaunchKernelGGL(k_adjoint_solve<MAXM>, dim3(sblocks > 0 ? sblocks : 1), dim3(256), 0, st, d, w, grad_coef,
-                       coef_stride);
+    hipLaunchKernelGGL(k_adjoint_solve<MAXM>, dim3(sblocks > 0 ? sblocks : 1), dim3(256), 0, st, d, w, solver,
+                       grad_coef, coef_stride);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid(blocks_for(L)), block(L.wpb * kWave);
@@ -945,6 +1068,19 @@ hipError_t Launchers<MAXM>::adjoint(const FitDesc& d, const Work& w, int dtype, 
     else
         hipLaunchKernelGGL((k_adjoint_stream<MAXM, double>), grid, block, 0, st, d, w, (const double*)x,
                            (const double*)y, (double*)gx, (double*)gy, L.tile, L.waves, mis);
+    return hipGetLastError();
+}
+
+template <int MAXM>
+hipError_t Launchers<MAXM>::residual(const FitDesc& d, const Work& w, int dtype, const void* x, const void* y,
+                                     void* resid, const Launch& L, int mis, hipStream_t st) {
+    const dim3 grid(blocks_for(L)), block(L.wpb * kWave);
+    if (dtype == LSEFIT_F32)
+        hipLaunchKernelGGL((k_residual<MAXM, float>), grid, block, 0, st, d, w, (const float*)x, (const float*)y,
+                           (float*)resid, L.tile, L.waves, mis);
+    else
+        hipLaunchKernelGGL((k_residual<MAXM, double>), grid, block, 0, st, d, w, (const double*)x, (const double*)y,
+                           (double*)resid, L.tile, L.waves, mis);
     return hipGetLastError();
 }
 

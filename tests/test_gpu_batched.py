@@ -184,3 +184,33 @@ def test_adjoint_nan_for_failed_fits():
     torch.nan_to_num(coef).sum().backward()
     g = x.grad.cpu().numpy()
     assert np.isfinite(g[:100]).all() and np.isnan(g[100:102]).all() and np.isfinite(g[102:]).all()
+
+
+def test_batched_cholesky_and_residuals():
+    rng = np.random.default_rng(20)
+    L = W.ragged_lengths(300, 16, 40_000, rng)
+    deg = rng.integers(1, 4, 300)
+    L[5] = 2          # singular
+    bf = W.random_batch(L, deg, seed=21, lo=-5.0, hi=5.0)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    for solver in ("gepp", "cholesky"):
+        coef, status, ws = lf.fit_batched(x, y, off, dg, 3, solver=solver)
+        torch.cuda.synchronize()
+        check_against_oracle(bf, coef.cpu().numpy(), status.cpu().numpy(), 1e-9)
+    sse, e = lf.residuals_batched(x, y, off, dg, 3, ws=ws, store=True)
+    torch.cuda.synchronize()
+    sse = sse.cpu().numpy()
+    e = e.cpu().numpy()
+    ref, rst = c_oracle.fit_batched(bf.x, bf.y, bf.offsets, bf.degrees, stride=4)
+    from oracle import fp64
+    for f in range(bf.batch):
+        lo, hi = bf.offsets[f], bf.offsets[f + 1]
+        if rst[f] != 0:
+            assert np.isnan(sse[f]) and np.isnan(e[lo:hi]).all()
+            continue
+        m = int(bf.degrees[f])
+        s_ref = fp64.sse(bf.x[lo:hi], bf.y[lo:hi], ref[f, : m + 1])
+        assert abs(sse[f] - s_ref) <= 1e-9 * s_ref + 1e-300, f
+        e_ref = bf.y[lo:hi].astype(np.float64) - fp64.polyval(ref[f, : m + 1], bf.x[lo:hi])
+        assert np.max(np.abs(e[lo:hi] - e_ref)) <= 1e-5 * max(np.max(np.abs(e_ref)), 1e-30), f

@@ -220,3 +220,61 @@ def test_ticket_reuse_across_calls_and_workspaces():
         assert np.array_equal(lf.fit(x, y, 2, ws=ws).coef.cpu().numpy(), first)
     ref = c_oracle.fit(fit.x, fit.y, 2)
     assert normwise(first, ref["a"]) <= 1e-9
+
+
+# --- Cholesky solver and the residual pass -------------------------------------
+
+@pytest.mark.parametrize("m", [1, 3, 5, 8])
+@pytest.mark.parametrize("precision", ["f64", "f32c"])
+def test_cholesky_matches_oracle(m, precision):
+    fit = W.random_small(300_001, m, seed=500 + m, dtype=np.float32)
+    res = run_fit(fit, m, precision=precision, solver="cholesky", center=0.0, scale=1.0)
+    ref = c_oracle.fit(fit.x, fit.y, m)
+    assert int(res.status.cpu()[0]) == 0
+    tol = (1e-9 if m <= 5 else 1e-7) if precision == "f64" else 1e-6
+    assert normwise(res.coef_t.cpu().numpy(), ref["b"]) <= tol
+
+
+def test_cholesky_flags_singular():
+    x = np.repeat(np.array([1.0, 2.0, 3.0], np.float32), 100)
+    y = np.arange(300, dtype=np.float32)
+    assert int(lf.fit(to_dev(x), to_dev(y), 3, solver="cholesky").status.cpu()[0]) == 2
+    assert int(lf.fit(to_dev(x), to_dev(y), 2, solver="cholesky").status.cpu()[0]) == 0
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_residuals_single(dtype):
+    fit = W.random_small(1_000_003, 3, seed=510, dtype=dtype)
+    x, y = to_dev(fit.x), to_dev(fit.y)
+    res = lf.fit(x, y, 3)
+    sse, e = lf.residuals(x, y, res, store=True)
+    torch.cuda.synchronize()
+    a = c_oracle.fit(fit.x, fit.y, 3)["a"]
+    sse_ref = fp64.sse(fit.x, fit.y, a)
+    assert abs(float(sse.cpu()[0]) - sse_ref) <= 1e-10 * sse_ref
+    e_ref = fit.y.astype(np.float64) - fp64.polyval(a, fit.x)
+    assert np.max(np.abs(e.cpu().numpy().astype(np.float64) - e_ref)) <= 1e-6 * np.max(np.abs(e_ref)) + (
+        0 if dtype == np.float64 else 1e-7 * np.max(np.abs(e_ref)))
+
+
+def test_residuals_table_v():
+    """Table V (Sec. III): the sum of squared errors of the order-3 fit of Table I
+    is the exact minimum 128.19957537..., below the printed 128.199937."""
+    from conftest import read_golden
+    rows, notes = read_golden("table_i.txt")
+    x = np.array([float(r[0]) for r in rows])
+    y = np.array([float(r[1]) for r in rows])
+    xd, yd = to_dev(x), to_dev(y)
+    res = lf.fit(xd, yd, 3)
+    sse, e = lf.residuals(xd, yd, res, store=True)
+    torch.cuda.synchronize()
+    from oracle import exact
+    a_ex, _ = exact.fit_exact(x, y, 3)
+    sse_exact = float(exact.sse_exact(x, y, a_ex))
+    _, tv = read_golden("table_v.txt")
+    s = float(sse.cpu()[0])
+    assert abs(s - sse_exact) <= 1e-9 * sse_exact
+    assert s <= tv["sum_e_f2"] and s <= tv["sum_e_p2"]
+    # the residuals themselves (e = y - f(x)) against the exact fitted values
+    fe = np.array([float(exact.polyval_exact(a_ex, xv)) for xv in x])
+    assert np.max(np.abs(e.cpu().numpy() - (y - fe))) <= 1e-8

@@ -1,0 +1,62 @@
+"""Pins of the Chebyshev-basis oracle (CPU only)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import cheb, exact, fp64
+from paper_1512_08017_amd import workloads as W
+
+
+def test_cheb_values_closed_form():
+    """T_k(cos th) = cos(k th)."""
+    th = np.linspace(0.1, 3.0, 50)
+    T = cheb.cheb_values(np.cos(th), 12)
+    for k in range(13):
+        assert np.max(np.abs(T[k] - np.cos(k * th))) < 1e-13
+
+
+def test_cheb_to_monomial_known_polynomials():
+    """T_2 = 2t^2 - 1, T_3 = 4t^3 - 3t, T_4 = 8t^4 - 8t^2 + 1 (exact)."""
+    F = Fraction
+    assert cheb.cheb_to_monomial([F(0), F(0), F(1)]) == [-1, 0, 2]
+    assert cheb.cheb_to_monomial([F(0), F(0), F(0), F(1)]) == [0, -3, 0, 4]
+    assert cheb.cheb_to_monomial([F(0), F(0), F(0), F(0), F(1)]) == [1, 0, -8, 0, 8]
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5])
+def test_same_minimiser_as_monomial_route(m):
+    """The basis does not change the least-squares minimiser (exact arithmetic)."""
+    fit = W.random_small(40, m, seed=30 + m)
+    c = cheb.fit_cheb_exact(fit.x, fit.y, m, Fraction(1, 4), 2)
+    a_mono, _ = exact.fit_exact(fit.x, fit.y, m)
+    b = cheb.cheb_to_monomial(c)
+    assert exact.unscale_exact(b, Fraction(1, 4), 2) == a_mono
+
+
+@pytest.mark.parametrize("m", [4, 8, 12, 16])
+def test_fp64_vs_exact_and_numpy_chebfit(m):
+    fit = W.random_small(2000, m, seed=40 + m)
+    res = cheb.fit_cheb(fit.x, fit.y, m)
+    ce = cheb.fit_cheb_exact(fit.x[:300], fit.y[:300], m) if m <= 8 else None
+    if ce is not None:
+        r300 = cheb.fit_cheb(fit.x[:300], fit.y[:300], m)
+        assert np.max(np.abs(r300["c"] - np.array([float(v) for v in ce]))) < 1e-11 * np.max(np.abs(r300["c"]))
+    ref = np.polynomial.chebyshev.chebfit(fit.x, fit.y, m)   # LAPACK least squares on the Chebyshev matrix
+    assert np.max(np.abs(res["c"] - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_monomial_route_fails_where_chebyshev_holds():
+    """At degree 20 on [-1, 1] the monomial normal matrix is numerically
+    singular in float64 even with correctly rounded sums; the Chebyshev route
+    keeps full precision (against numpy's chebfit)."""
+    fit = W.random_small(20000, 20, seed=60)
+    ref = np.polynomial.chebyshev.chebfit(fit.x, fit.y, 20)
+    res = cheb.fit_cheb(fit.x, fit.y, 20)
+    assert np.max(np.abs(res["c"] - ref)) <= 1e-10 * np.max(np.abs(ref))
+    mono = fp64.fit(fit.x, fit.y, 20)
+    if mono["status"] == fp64.OK:
+        c_from_mono = np.polynomial.chebyshev.poly2cheb(mono["b"])
+        assert np.max(np.abs(c_from_mono - ref)) > 1e-6 * np.max(np.abs(ref))
+    else:
+        assert mono["status"] == fp64.SINGULAR

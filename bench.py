@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--schedule", type=str, default=None, help="JSON schedule for the streaming kernels")
     ap.add_argument("--workload", choices=("cubic_f32", "ragged_batch", "grad_batch", "shifted_quintic",
-                                           "linear_f64"), default="cubic_f32",
+                                           "linear_f64", "runge"), default="cubic_f32",
                     help="cubic_f32 is the benchmark; the others are extra measurements (see their docstrings)")
     ap.add_argument("--per-fit-limit", type=int, default=4096,
                     help="batched workloads: fits timed one launch sequence at a time for the per-fit baseline")
@@ -153,12 +153,12 @@ def traffic_bytes(kernel="moments"):
 class SingleFitRunner:
     """Pre-allocated buffers and one C-ABI step (fit_single: the fused single-fit call)."""
 
-    def __init__(self, x, y, degree, precision):
+    def __init__(self, x, y, degree, precision, **opts):
         import torch
         from paper_1512_08017_amd import _lib, api
         self.L = _lib.load()
         self.x, self.y, self.m, self.precision = x, y, degree, precision
-        self.opt = api.options(degree, precision, 1)
+        self.opt = api.options(degree, precision, 1, **opts)
         nbytes = api.workspace_bytes(1, degree)
         self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
         self.mom = torch.empty(3 * degree + 4, dtype=torch.float64, device=x.device)
@@ -202,7 +202,7 @@ def time_steps(runner, steps, warmup):
     ms_inst, _ = _region(runner, steps)
     L.lsefit_timing_enable(0)
     kern = {}
-    for kind, name in ((0, "moments"), (1, "refine"), (3, "combine")):
+    for kind, name in ((0, "moments"), (1, "refine"), (3, "combine"), (6, "range")):
         tot, cnt = ctypes.c_double(0.0), ctypes.c_int64(0)
         _lib.check(L.lsefit_timing_read(kind, ctypes.byref(tot), ctypes.byref(cnt)), "lsefit_timing_read")
         if cnt.value:
@@ -254,7 +254,7 @@ def _kernel_avgs():
     from paper_1512_08017_amd import _lib
     L = _lib.load()
     out = {}
-    for kind, name in ((0, "moments"), (1, "refine"), (2, "adjoint"), (3, "combine")):
+    for kind, name in ((0, "moments"), (1, "refine"), (2, "adjoint"), (3, "combine"), (6, "range")):
         tot, cnt = ctypes.c_double(0.0), ctypes.c_int64(0)
         _lib.check(L.lsefit_timing_read(kind, ctypes.byref(tot), ctypes.byref(cnt)), "lsefit_timing_read")
         if cnt.value:
@@ -403,6 +403,56 @@ def bench_single_workload(args, name):
     return out
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def cheb_flops_per_point(m: int) -> int:
+    """float64 flops of one point of the Chebyshev streaming pass (fma = 2):
+    t (fma), 2t, then T_2..T_2m by T_(k+1) = 2t T_k - T_(k-1) (2m-1 fma), the
+    2m sums of T_k and D_0 (adds), and D_1..D_m (fma)."""
+    fma = 1 + (2 * m - 1) + m
+    add = 1 + 2 * m + 1
+    return 2 * fma + add
+
+
+def bench_runge(args):
+    """Chebyshev basis, the higher degrees Sec. V leaves open: one fit of
+    n = 1e8 float32 points of the Runge function on [-1, 1], m = 12, with the
+    range given (one streaming pass) and automatic (an extra pass over x for
+    the exact extent).  Reports points/s, the moment kernel against both the
+    HBM and the float64 vector roofline, and the error against the C oracle."""
+    import numpy as np
+    import torch
+    from oracle import c_oracle, cheb
+    from paper_1512_08017_amd import workloads as W
+    dev = torch.device("cuda:0")
+    wl = W.runge()
+    m, n = wl.degree, wl.n
+    x, y = torch.from_numpy(wl.x).to(dev), torch.from_numpy(wl.y).to(dev)
+    out = {"workload": f"runge: one degree-{m} Chebyshev-basis fit of n={n} float32 points, x~U[-1,1], "
+                       "y=1/(1+25x^2)+N(0,1e-3^2)", "n": n, "degree": m,
+           "flops_per_point": cheb_flops_per_point(m), "bytes_per_point": 8}
+    for mode, kw in (("given", {"center": 0.0, "scale": 1.0}), ("auto", {})):
+        r = SingleFitRunner(x, y, m, "f64", basis="chebyshev", **kw)
+        ms, wall, ms_inst, kern = time_steps(r, args.steps, args.warmup)
+        c_gpu = r.coef[: m + 1].cpu().numpy()
+        c0, s0 = (0.0, 1.0) if mode == "given" else cheb.cheb_range(wl.x)
+        t0 = time.perf_counter()
+        ref = c_oracle.cheb_fit(wl.x, wl.y, m, c0, s0)
+        cpu_s = time.perf_counter() - t0
+        mk = kern["moments"]["avg_ms"] * 1e-3
+        gbps = 8.0 * n / mk / 1e9
+        tflops = cheb_flops_per_point(m) * n / mk / 1e12
+        out[mode] = {"ms_per_step": ms, "points_per_s": n / (ms * 1e-3), "kernels": kern,
+                     "moments_gbps": gbps, "moments_hbm_frac": gbps / HBM_PEAK_GBPS,
+                     "moments_fp64_tflops": tflops, "moments_fp64_frac": tflops / FP64_VECTOR_PEAK_TFLOPS,
+                     "status": int(r.status.cpu()[0]),
+                     "max_rel_coef_err": float(np.max(np.abs(c_gpu - ref["c"])) / np.max(np.abs(ref["c"]))),
+                     "cpu_oracle_points_per_s": n / cpu_s, "cpu_oracle_threads": c_oracle.max_threads()}
+        log(f"runge {mode}: {json.dumps(out[mode])}")
+    return out
+
+
 def probe_sweep(args):
     """Read-bandwidth probe over the benchmark's 800 MB of x and y, per schedule,
     load pattern and load kind (the attainable ceiling for the power-sum pass)."""
@@ -466,7 +516,7 @@ def main():
         print(json.dumps(probe_sweep(args)), flush=True)
         return 0
     if args.workload != "cubic_f32":
-        fn = {"ragged_batch": bench_ragged, "grad_batch": bench_grad}.get(args.workload)
+        fn = {"ragged_batch": bench_ragged, "grad_batch": bench_grad, "runge": bench_runge}.get(args.workload)
         res = fn(args) if fn else bench_single_workload(args, args.workload)
         print(json.dumps(res), flush=True)
         return 0

@@ -51,6 +51,7 @@ extern "C" {
 #endif
 
 #define LSEFIT_MAX_DEGREE 8
+#define LSEFIT_MAX_DEGREE_CHEBYSHEV 16
 
 typedef enum {
     LSEFIT_OK = 0,
@@ -79,13 +80,19 @@ typedef enum { LSEFIT_PREC_F64 = 0, LSEFIT_PREC_F32C = 1 } lsefit_precision;
 /* Where (c, s) come from.
  *  LSEFIT_RANGE_GIVEN: c = center, s = scale for every fit (s > 0; a power
  *                      of two keeps t exact).
- *  LSEFIT_RANGE_AUTO:  from a sample of x (single fit: up to 65,536 evenly
- *                      strided points; batched: up to 16 per fit, first and
- *                      last included): s = 2^ceil(log2(half-range)) and c =
- *                      the mid-range rounded to a multiple of s/8, replaced
- *                      by 0 when it is below 2^-6 times the half-range; c is
- *                      then rounded to float32.  The result does not depend
- *                      on this choice except through rounding. */
+ *  LSEFIT_RANGE_AUTO:  monomial basis: from a sample of x (single fit: up to
+ *                      256 evenly strided points; batched: up to 16 per fit,
+ *                      first and last included): s = 2^ceil(log2(half-range))
+ *                      and c = the mid-range rounded to a multiple of s/8,
+ *                      replaced by 0 when it is below 2^-6 times the
+ *                      half-range; c is then rounded to float32.  The result
+ *                      does not depend on this choice except through rounding.
+ *                      Chebyshev basis: from the exact extent [lo, hi] of the
+ *                      finite x of each fit (one extra pass over x):
+ *                      c = hi/2 + lo/2, s = hi/2 - lo/2 (1 when zero), so
+ *                      that t covers [-1, 1], where the T_k are orthogonal;
+ *                      on a sub-interval their Gram matrix loses its
+ *                      conditioning quickly with the degree. */
 typedef enum { LSEFIT_RANGE_GIVEN = 0, LSEFIT_RANGE_AUTO = 1 } lsefit_range_mode;
 
 /* How the (m+1)x(m+1) normal system A X = B is solved.
@@ -97,8 +104,24 @@ typedef enum { LSEFIT_RANGE_GIVEN = 0, LSEFIT_RANGE_AUTO = 1 } lsefit_range_mode
  *                          diagonal of the factorisation is at most 2^-40 max|A|. */
 typedef enum { LSEFIT_SOLVER_GEPP = 0, LSEFIT_SOLVER_CHOLESKY = 1 } lsefit_solver;
 
+/* The basis the normal equations are written in.
+ *  LSEFIT_BASIS_MONOMIAL:  powers of t, the method of Sec. II (degree <= 8).
+ *  LSEFIT_BASIS_CHEBYSHEV: Chebyshev polynomials T_k(t) (degree <= 16), for the
+ *      higher orders Sec. V leaves open: the pass sums C_k = sum T_k(t_i) and
+ *      D_j = sum y_i T_j(t_i) by the recurrence T_(k+1) = 2t T_k - T_(k-1), and
+ *      the Gram matrix is G_jk = (C_(j+k) + C_|j-k|) / 2 (C_0 = n), which stays
+ *      well conditioned where the power-sum matrix does not.  float64 sums only
+ *      (LSEFIT_PREC_F64).  Results: single fits write c_0..c_m (Chebyshev
+ *      coefficients in t) followed by a_0..a_m (x-basis); batched fits write
+ *      c_0..c_m and, when coef_stride >= m + 3, the fit's center and scale.
+ *      fit_moments writes [c, s, C_0..C_2m, D_0..D_m] (same length 3m+4) and
+ *      fit_solve reads that layout.  fit_backward and fit_residuals do not
+ *      take this basis (UNSUPPORTED). */
+typedef enum { LSEFIT_BASIS_MONOMIAL = 0, LSEFIT_BASIS_CHEBYSHEV = 1 } lsefit_basis;
+
 typedef struct lsefit_options {
-    int32_t degree;        /* single fit: m in 1..LSEFIT_MAX_DEGREE; batched: the
+    int32_t degree;        /* single fit: m in 1..LSEFIT_MAX_DEGREE (Chebyshev basis:
+                              1..LSEFIT_MAX_DEGREE_CHEBYSHEV); batched: the
                               largest degree present (each degrees[f] must be <= it) */
     int32_t precision;     /* lsefit_precision */
     int32_t refine_steps;  /* LSEFIT_PREC_F32C: 0 or 1 refinement passes; ignored otherwise */
@@ -106,6 +129,7 @@ typedef struct lsefit_options {
     double center;         /* c for LSEFIT_RANGE_GIVEN */
     double scale;          /* s for LSEFIT_RANGE_GIVEN, > 0 */
     int32_t solver;        /* lsefit_solver */
+    int32_t basis;         /* lsefit_basis */
 } lsefit_options;
 
 /* Launch schedule of the streaming kernels.  Any valid schedule gives the
@@ -131,6 +155,7 @@ typedef struct lsefit_plan lsefit_plan;   /* opaque: schedule, workspace, captur
  * schedule).  The workspace holds per-wave partial sums, the tile table and one
  * record per fit (c, s, power sums, t-basis solution) that fit_backward reads. */
 size_t lsefit_workspace_bytes(int64_t batch, int32_t max_degree, const lsefit_schedule* schedule);
+/* (max_degree up to LSEFIT_MAX_DEGREE_CHEBYSHEV for Chebyshev-basis calls) */
 
 /* The schedule used when no plan is given (initially sized to this device's
  * compute units).  lsefit_set_default_schedule replaces it for the whole
@@ -261,7 +286,8 @@ lsefit_status lsefit_read_probe(const float* x, const float* y, int64_t n, const
  * in milliseconds and the number of launches since the last reset.
  *  kind: 0 = power-sum pass, 1 = refinement pass, 2 = adjoint pass,
  *        3 = per-fit combine and solve, 4 = read-bandwidth probe,
- *        5 = residual pass.
+ *        5 = residual pass, 6 = range pass (Chebyshev basis, automatic
+ *        range; with its per-fit fold).
  * Not synchronised with calls on other host threads. */
 lsefit_status lsefit_timing_enable(int32_t enable);
 lsefit_status lsefit_timing_reset(void);

@@ -28,6 +28,10 @@ def lib():
         L.lse_oracle_fit_batched.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int, _dbl_p, ctypes.c_void_p, ctypes.c_int]
+        L.lse_oracle_cheb_fit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                          _dbl_p, _dbl_p, _dbl_p, ctypes.c_int]
+        L.lse_oracle_cheb_fit_batched.argtypes = L.lse_oracle_fit_batched.argtypes
         L.lse_oracle_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -89,6 +93,41 @@ def fit_batched(x, y, offsets, degrees, centers=None, scales=None, stride=None, 
     if st != 0:
         raise ValueError(STATUS[st])
     return a.reshape(B, stride), status
+
+
+def cheb_fit(x, y, m, center=0.0, scale=1.0, threads=0) -> dict:
+    """Chebyshev coefficients c of one fit, with the Gram matrix G and D (entrywise sums)."""
+    x = np.ascontiguousarray(x)
+    y = np.ascontiguousarray(y, dtype=x.dtype)
+    c = np.zeros(m + 1)
+    G = np.zeros((m + 1, m + 1))
+    D = np.zeros(m + 1)
+    st = lib().lse_oracle_cheb_fit(_ptr(x), _ptr(y), x.shape[0], _dtype_code(x), m, center, scale,
+                                   c.ctypes.data_as(_dbl_p), G.ctypes.data_as(_dbl_p), D.ctypes.data_as(_dbl_p),
+                                   threads)
+    if st == 1:
+        raise ValueError("invalid arguments")
+    return {"c": c, "G": G, "D": D, "status": STATUS[st], "center": center, "scale": scale}
+
+
+def cheb_fit_batched(x, y, offsets, degrees, centers=None, scales=None, stride=None, threads=0):
+    x = np.ascontiguousarray(x)
+    y = np.ascontiguousarray(y, dtype=x.dtype)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    degrees = np.ascontiguousarray(degrees, dtype=np.int32)
+    B = degrees.shape[0]
+    if stride is None:
+        stride = int(degrees.max()) + 1 if B else 1
+    out = np.full(B * stride, np.nan)
+    status = np.zeros(B, dtype=np.int32)
+    c = None if centers is None else np.ascontiguousarray(centers, dtype=np.float64)
+    s = None if scales is None else np.ascontiguousarray(scales, dtype=np.float64)
+    st = lib().lse_oracle_cheb_fit_batched(_ptr(x), _ptr(y), _ptr(offsets), _ptr(degrees), B, _dtype_code(x),
+                                           _ptr(c), _ptr(s), stride, out.ctypes.data_as(_dbl_p), _ptr(status),
+                                           threads)
+    if st != 0:
+        raise ValueError(STATUS[st])
+    return out.reshape(B, stride), status
 
 
 def max_threads() -> int:

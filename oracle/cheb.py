@@ -16,6 +16,7 @@ V_ij = T_j(t_i) the normal equations read G c = V^T y, G = V^T V.
 * ``fit_cheb_exact``: the same in exact rational arithmetic.
 * ``cheb_to_monomial``: c -> b with sum_j c_j T_j(t) = sum_k b_k t^k, from the
   recurrence applied to coefficient vectors.
+* ``cheb_range``: the (c, s) that put the data's extent on [-1, 1].
 """
 from __future__ import annotations
 
@@ -25,6 +26,20 @@ from fractions import Fraction
 import numpy as np
 
 from . import exact, fp64
+
+
+def cheb_range(x) -> tuple[float, float]:
+    """(c, s) that map the extent [lo, hi] of the finite x onto [-1, 1]:
+    c = hi/2 + lo/2, s = hi/2 - lo/2 (s = 1 when the extent is a point, and
+    (0, 1) when no x is finite).  The T_k are orthogonal on [-1, 1]; the
+    Chebyshev route takes this range when none is given."""
+    v = np.asarray(x, dtype=np.float64)
+    v = v[np.isfinite(v)]
+    if v.size == 0:
+        return 0.0, 1.0
+    lo, hi = float(v.min()), float(v.max())
+    half = 0.5 * hi - 0.5 * lo
+    return 0.5 * hi + 0.5 * lo, (half if half > 0.0 else 1.0)
 
 
 def cheb_values(t, m: int) -> list:

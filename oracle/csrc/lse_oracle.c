@@ -219,6 +219,112 @@ int lse_oracle_fit_batched(const void *x, const void *y, const int64_t *offsets,
     return ST_OK;
 }
 
+/* ---------------------------------------------------------------------------
+ * Chebyshev basis (higher orders, which Sec. V leaves open): the same
+ * least-squares problem with f(x) = sum_j c_j T_j(t), T_0 = 1, T_1 = t,
+ * T_(k+1) = 2t T_k - T_(k-1).  Normal equations G c = D with the plain
+ * definitions G_jk = sum_i T_j(t_i) T_k(t_i) and D_j = sum_i T_j(t_i) y_i,
+ * every entry its own compensated sum (no product identity), then GEPP.
+ * ------------------------------------------------------------------------- */
+#define CHEB_NG(m) (((m) + 1) * ((m) + 2) / 2) /* upper triangle of G */
+
+static void cheb_range_sums(const void *x, const void *y, int dtype, int64_t lo, int64_t hi, int m, double c,
+                            double s, double *sum, double *comp) {
+    int ng = CHEB_NG(m), nacc = ng + m + 1;
+    double T[ORACLE_MAXDEG + 1];
+    for (int k = 0; k < nacc; ++k) sum[k] = comp[k] = 0.0;
+    for (int64_t i = lo; i < hi; ++i) {
+        double t = (load(x, dtype, i) - c) / s;
+        double yv = load(y, dtype, i);
+        T[0] = 1.0;
+        if (m >= 1) T[1] = t;
+        for (int k = 1; k < m; ++k) T[k + 1] = 2.0 * t * T[k] - T[k - 1];
+        int e = 0;
+        for (int j = 0; j <= m; ++j)
+            for (int k = j; k <= m; ++k, ++e) nadd(&sum[e], &comp[e], T[j] * T[k]);
+        for (int j = 0; j <= m; ++j) nadd(&sum[ng + j], &comp[ng + j], T[j] * yv);
+    }
+}
+
+static int cheb_solve(int m, const double *g, const double *D, double *cout) {
+    double G[(ORACLE_MAXDEG + 1) * (ORACLE_MAXDEG + 1)], X[ORACLE_MAXDEG + 1], R[ORACLE_MAXDEG + 1];
+    int n = m + 1, e = 0;
+    for (int j = 0; j <= m; ++j)
+        for (int k = j; k <= m; ++k, ++e) G[j * n + k] = G[k * n + j] = g[e];
+    memcpy(R, D, sizeof(double) * n);
+    int st = gepp(n, G, R, X);
+    for (int k = 0; k < n; ++k) cout[k] = st == ST_OK ? X[k] : NAN;
+    return st;
+}
+
+/* One fit: Chebyshev coefficients cout[m+1]; G_out[(m+1)^2] and D_out[m+1] nullable. */
+int lse_oracle_cheb_fit(const void *x, const void *y, int64_t n, int dtype, int m, double c, double s,
+                        double *cout, double *G_out, double *D_out, int nthreads) {
+    if (m < 0 || m > ORACLE_MAXDEG || n < 0 || (dtype != 0 && dtype != 1) || !(s != 0.0)) return ST_INVALID;
+    int ng = CHEB_NG(m), nacc = ng + m + 1;
+    int64_t nchunk = (n + ORACLE_CHUNK - 1) / ORACLE_CHUNK;
+    double *part = (double *)calloc((size_t)(nchunk > 0 ? nchunk : 1) * 2 * nacc, sizeof(double));
+    double tot[CHEB_NG(ORACLE_MAXDEG) + ORACLE_MAXDEG + 1];
+    if (!part) return ST_INVALID;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t ch = 0; ch < nchunk; ++ch) {
+        int64_t lo = ch * ORACLE_CHUNK, hi = lo + ORACLE_CHUNK < n ? lo + ORACLE_CHUNK : n;
+        cheb_range_sums(x, y, dtype, lo, hi, m, c, s, part + ch * 2 * nacc, part + ch * 2 * nacc + nacc);
+    }
+    for (int k = 0; k < nacc; ++k) {
+        double acc = 0.0, comp = 0.0;
+        for (int64_t ch = 0; ch < nchunk; ++ch) {
+            nadd(&acc, &comp, part[ch * 2 * nacc + k]);
+            comp += part[ch * 2 * nacc + nacc + k];
+        }
+        tot[k] = acc + comp;
+    }
+    free(part);
+    if (G_out) {
+        int e = 0;
+        for (int j = 0; j <= m; ++j)
+            for (int k = j; k <= m; ++k, ++e) G_out[j * (m + 1) + k] = G_out[k * (m + 1) + j] = tot[e];
+    }
+    if (D_out) memcpy(D_out, tot + ng, sizeof(double) * (m + 1));
+    if (n < m + 1) {
+        for (int k = 0; k <= m; ++k) cout[k] = NAN;
+        return ST_SINGULAR;
+    }
+    return cheb_solve(m, tot, tot + ng, cout);
+}
+
+/* Independent Chebyshev fits over CSR segments (layout as lse_oracle_fit_batched). */
+int lse_oracle_cheb_fit_batched(const void *x, const void *y, const int64_t *offsets, const int32_t *degrees,
+                                int64_t B, int dtype, const double *centers, const double *scales, int stride,
+                                double *cout, int32_t *status, int nthreads) {
+    if (B < 0 || (dtype != 0 && dtype != 1)) return ST_INVALID;
+    for (int64_t f = 0; f < B; ++f)
+        if (degrees[f] < 0 || degrees[f] > ORACLE_MAXDEG || degrees[f] + 1 > stride) return ST_INVALID;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (int64_t f = 0; f < B; ++f) {
+        int m = degrees[f];
+        int64_t lo = offsets[f], hi = offsets[f + 1];
+        double c = centers ? centers[f] : 0.0, s = scales ? scales[f] : 1.0;
+        double sum[CHEB_NG(ORACLE_MAXDEG) + ORACLE_MAXDEG + 1], comp[CHEB_NG(ORACLE_MAXDEG) + ORACLE_MAXDEG + 1];
+        if (hi - lo < m + 1) {
+            for (int k = 0; k <= m; ++k) cout[f * stride + k] = NAN;
+            status[f] = ST_SINGULAR;
+            continue;
+        }
+        cheb_range_sums(x, y, dtype, lo, hi, m, c, s, sum, comp);
+        int ng = CHEB_NG(m);
+        for (int k = 0; k < ng + m + 1; ++k) sum[k] += comp[k];
+        status[f] = cheb_solve(m, sum, sum + ng, cout + f * stride);
+    }
+    return ST_OK;
+}
+
 int lse_oracle_max_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

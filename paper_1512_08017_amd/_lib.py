@@ -12,6 +12,8 @@ OK, INVALID_ARG, SINGULAR, NONFINITE, WORKSPACE, DEVICE, UNSUPPORTED = range(7)
 F32, F64 = 0, 1
 PREC_F64, PREC_F32C = 0, 1
 SOLVER_GEPP, SOLVER_CHOLESKY = 0, 1
+BASIS_MONOMIAL, BASIS_CHEBYSHEV = 0, 1
+LSEFIT_MAX_DEGREE_CHEBYSHEV = 16
 RANGE_GIVEN, RANGE_AUTO = 0, 1
 
 STATUS_NAMES = {OK: "ok", INVALID_ARG: "invalid_arg", SINGULAR: "singular", NONFINITE: "nonfinite",
@@ -30,7 +32,7 @@ EXPORTS = (
 class Options(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
                 ("range_mode", ctypes.c_int32), ("center", ctypes.c_double), ("scale", ctypes.c_double),
-                ("solver", ctypes.c_int32)]
+                ("solver", ctypes.c_int32), ("basis", ctypes.c_int32)]
 
 
 class Schedule(ctypes.Structure):

@@ -18,6 +18,7 @@ from ._lib import Options, Schedule, check
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
 _PREC = {"f64": _lib.PREC_F64, "f32c": _lib.PREC_F32C}
 _SOLVER = {"gepp": _lib.SOLVER_GEPP, "cholesky": _lib.SOLVER_CHOLESKY}
+_BASIS = {"monomial": _lib.BASIS_MONOMIAL, "chebyshev": _lib.BASIS_CHEBYSHEV}
 
 
 def _ptr(t):
@@ -29,13 +30,16 @@ def _stream(dev):
 
 
 def options(degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None,
-            solver: str = "gepp") -> Options:
+            solver: str = "gepp", basis: str = "monomial") -> Options:
     if precision not in _PREC:
         raise ValueError(f"precision must be one of {sorted(_PREC)}")
     if solver not in _SOLVER:
         raise ValueError(f"solver must be one of {sorted(_SOLVER)}")
+    if basis not in _BASIS:
+        raise ValueError(f"basis must be one of {sorted(_BASIS)}")
     o = Options()
     o.solver = _SOLVER[solver]
+    o.basis = _BASIS[basis]
     o.degree = int(degree)
     o.precision = _PREC[precision]
     o.refine_steps = int(refine) if precision == "f32c" else 0
@@ -96,11 +100,12 @@ def device_cus() -> int:
 @dataclass
 class FitResult:
     coef: torch.Tensor       # a_0..a_m, x-basis, float64 (device)
-    coef_t: torch.Tensor     # b_0..b_m, t-basis, float64 (device)
+    coef_t: torch.Tensor | None   # b_0..b_m, t-basis (monomial basis only)
     status: torch.Tensor     # int32 [1] (device)
-    moments: torch.Tensor    # [c, s, S_0..S_2m, T_0..T_m] (device)
+    moments: torch.Tensor    # [c, s, S_0..S_2m, T_0..T_m] (Chebyshev: C_k, D_j in their place)
     ws: torch.Tensor | None = None   # the workspace the fit left its records in
     options: Options | None = None
+    coef_cheb: torch.Tensor | None = None   # c_0..c_m of sum_j c_j T_j(t) (Chebyshev basis)
 
     @property
     def center(self):
@@ -111,11 +116,13 @@ class FitResult:
         return float(self.moments[1])
 
 
-def fit_moments(x, y, degree, precision="f64", center=None, scale=None, ws=None, solver="gepp"):
-    """Power sums [c, s, S_0..S_2m, T_0..T_m] of t = (x - c)/s (one streaming pass)."""
+def fit_moments(x, y, degree, precision="f64", center=None, scale=None, ws=None, solver="gepp",
+                basis="monomial"):
+    """Power sums [c, s, S_0..S_2m, T_0..T_m] of t = (x - c)/s (one streaming
+    pass); for basis="chebyshev" the sums C_k of T_k(t) and D_j of y T_j(t)."""
     _check_points(x, y)
     L = _lib.load()
-    o = options(degree, precision, 0, center, scale, solver)
+    o = options(degree, precision, 0, center, scale, solver, basis)
     nbytes = workspace_bytes(1, degree)
     if ws is None or ws.numel() < nbytes:
         ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
@@ -126,10 +133,11 @@ def fit_moments(x, y, degree, precision="f64", center=None, scale=None, ws=None,
 
 
 def fit_solve(moments, degree, precision="f64", refine=1, x=None, y=None, ws=None, center=None, scale=None,
-              solver="gepp"):
-    """Elimination on the Hankel system, optional refinement, x-basis coefficients."""
+              solver="gepp", basis="monomial"):
+    """Elimination on the Hankel system, optional refinement, x-basis
+    coefficients; returns ([a | b], status) ([c | a] for basis="chebyshev")."""
     L = _lib.load()
-    o = options(degree, precision, refine, center, scale, solver)
+    o = options(degree, precision, refine, center, scale, solver, basis)
     dev = moments.device
     nbytes = workspace_bytes(1, degree)
     if ws is None or ws.numel() < nbytes:
@@ -144,11 +152,15 @@ def fit_solve(moments, degree, precision="f64", refine=1, x=None, y=None, ws=Non
 
 
 def fit(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None,
-        ws=None, solver: str = "gepp") -> FitResult:
-    """Least-squares polynomial fit of degree ``degree`` (coefficients a_0 first), one fused call."""
+        ws=None, solver: str = "gepp", basis: str = "monomial") -> FitResult:
+    """Least-squares polynomial fit of degree ``degree`` (coefficients a_0 first), one fused call.
+
+    basis="chebyshev" (degree up to 16): the normal equations are written in
+    Chebyshev polynomials of t = (x - center)/scale; ``coef_cheb`` holds their
+    coefficients c, ``coef`` the x-basis a, and ``coef_t`` is None."""
     _check_points(x, y)
     L = _lib.load()
-    o = options(degree, precision, refine, center, scale, solver)
+    o = options(degree, precision, refine, center, scale, solver, basis)
     nbytes = workspace_bytes(1, degree)
     if ws is None or ws.numel() < nbytes:
         ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
@@ -158,16 +170,21 @@ def fit(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None,
     mom = torch.empty(3 * degree + 4, dtype=torch.float64, device=x.device)
     check(L.fit_single(_ptr(x), _ptr(y), x.numel(), _DT[x.dtype], ctypes.byref(o), _ptr(ws), ws.numel(),
                        _ptr(coef), _ptr(status), _ptr(mom), _stream(x.device)), "fit_single")
+    if basis == "chebyshev":
+        return FitResult(coef[m1:], None, status, mom, ws, o, coef_cheb=coef[:m1])
     return FitResult(coef[:m1], coef[m1:], status, mom, ws, o)
 
 
 def fit_split(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None,
-              solver: str = "gepp") -> FitResult:
+              solver: str = "gepp", basis: str = "monomial") -> FitResult:
     """The same fit through the two-call form (fit_moments, then fit_solve)."""
-    mom, ws = fit_moments(x, y, degree, precision, center, scale, solver=solver)
-    coef, status = fit_solve(mom, degree, precision, refine, x, y, ws, center, scale, solver=solver)
+    mom, ws = fit_moments(x, y, degree, precision, center, scale, solver=solver, basis=basis)
+    coef, status = fit_solve(mom, degree, precision, refine, x, y, ws, center, scale, solver=solver, basis=basis)
     m1 = degree + 1
-    return FitResult(coef[:m1], coef[m1:], status, mom, ws, options(degree, precision, refine, center, scale, solver))
+    o = options(degree, precision, refine, center, scale, solver, basis)
+    if basis == "chebyshev":
+        return FitResult(coef[m1:], None, status, mom, ws, o, coef_cheb=coef[:m1])
+    return FitResult(coef[:m1], coef[m1:], status, mom, ws, o)
 
 
 def residuals(x, y, result: FitResult, store: bool = False):
@@ -241,10 +258,10 @@ class Plan:
         check(self._L.fit_plan_set_graph(self.handle, 1 if enable else 0), "fit_plan_set_graph")
 
     def tune(self, x, y, offsets, degrees, max_degree=None, precision=None, refine=1, center=None, scale=None,
-             reps=3, solver="gepp") -> float:
+             reps=3, solver="gepp", basis="monomial") -> float:
         _check_batch(x, y, offsets, degrees)
         m = self.max_degree if max_degree is None else max_degree
-        o = options(m, precision or self.precision, refine, center, scale, solver)
+        o = options(m, precision or self.precision, refine, center, scale, solver, basis)
         B = degrees.numel()
         coef = torch.empty(B * (m + 1), dtype=torch.float64, device=x.device)
         status = torch.empty(B, dtype=torch.int32, device=x.device)
@@ -269,12 +286,12 @@ def _check_batch(x, y, offsets, degrees):
 
 def fit_batched(x, y, offsets, degrees, max_degree: int, precision: str = "f64", refine: int = 1,
                 center=None, scale=None, plan: Plan | None = None, coef_stride: int | None = None,
-                ws: torch.Tensor | None = None, out=None, solver: str = "gepp"):
+                ws: torch.Tensor | None = None, out=None, solver: str = "gepp", basis: str = "monomial"):
     """Independent fits over CSR segments; returns (coef [B, stride], status [B], ws)."""
     _check_batch(x, y, offsets, degrees)
     L = _lib.load()
     B = degrees.numel()
-    o = options(max_degree, precision, refine, center, scale, solver)
+    o = options(max_degree, precision, refine, center, scale, solver, basis)
     stride = coef_stride or (max_degree + 1)
     if out is None:
         coef = torch.zeros((B, stride), dtype=torch.float64, device=x.device)

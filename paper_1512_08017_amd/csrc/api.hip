@@ -121,9 +121,12 @@ int common_mis(int dt, std::initializer_list<const void*> ptrs) {
     return mis;
 }
 
+bool chebyshev(const lsefit_options* o) { return o->basis == LSEFIT_BASIS_CHEBYSHEV; }
+
 bool opts_ok(const lsefit_options* o, int dt, bool batched) {
     if (!o) return false;
-    if (o->degree < 1 || o->degree > LSEFIT_MAX_DEGREE) return false;
+    if (o->basis != LSEFIT_BASIS_MONOMIAL && o->basis != LSEFIT_BASIS_CHEBYSHEV) return false;
+    if (o->degree < 1 || o->degree > (chebyshev(o) ? LSEFIT_MAX_DEGREE_CHEBYSHEV : LSEFIT_MAX_DEGREE)) return false;
     if (o->precision != LSEFIT_PREC_F64 && o->precision != LSEFIT_PREC_F32C) return false;
     if (o->refine_steps < 0 || o->refine_steps > 1) return false;
     if (o->range_mode != LSEFIT_RANGE_GIVEN && o->range_mode != LSEFIT_RANGE_AUTO) return false;
@@ -135,7 +138,16 @@ bool opts_ok(const lsefit_options* o, int dt, bool batched) {
     return true;
 }
 
-bool refining(const lsefit_options* o) { return o->precision == LSEFIT_PREC_F32C && o->refine_steps > 0; }
+bool refining(const lsefit_options* o) {
+    return o->precision == LSEFIT_PREC_F32C && o->refine_steps > 0 && !chebyshev(o);
+}
+
+// combinations the kernels do not implement
+bool unsupported(const lsefit_options* o, int dt) {
+    if (o->precision == LSEFIT_PREC_F32C && dt != LSEFIT_F32) return true;
+    if (chebyshev(o) && o->precision != LSEFIT_PREC_F64) return true;
+    return false;
+}
 
 #define LSEFIT_TRY(expr)                                   \
     do {                                                   \
@@ -152,7 +164,8 @@ enum TimedKind {
     kTimeCombine = 3,
     kTimeProbe = 4,
     kTimeResidual = 5,
-    kTimeKinds = 6
+    kTimeRange = 6,
+    kTimeKinds = 7
 };
 
 struct Timing {
@@ -220,6 +233,18 @@ lsefit_status enqueue_batched(const FitDesc& d, const Work& w, const lsefit_opti
     const bool by_block = L.waves >= 64 * d.batch;
     const Finish solve{kSolve, coef, coef_stride, 0, status, nullptr, o->solver};
     const Finish refine{kRefine, coef, coef_stride, 0, status, nullptr, o->solver};
+    if (chebyshev(o)) {
+        // the plan takes the given (c, s), or a placeholder the range pass replaces
+        LSEFIT_TRY(launch_plan(d, w, maxM, L.tile, true, given ? o->center : 0.0, given ? o->scale : 1.0, dt, x,
+                               w.block_tot, st));
+        if (!given)
+            LSEFIT_TRY(timed(kTimeRange, st, [&] { return launch_range_cheb(d, w, maxM, dt, x, L, mis, st); }));
+        const RangeArg ra{LSEFIT_RANGE_GIVEN, 0.0, 1.0};
+        LSEFIT_TRY(timed(kTimeMoments, st,
+                         [&] { return launch_moments_cheb(d, w, maxM, dt, x, y, L, mis, ra, st); }));
+        LSEFIT_TRY(timed(kTimeCombine, st, [&] { return launch_finish_cheb(d, w, maxM, L.waves, solve, st); }));
+        return LSEFIT_OK;
+    }
     LSEFIT_TRY(launch_plan(d, w, maxM, L.tile, given, o->center, o->scale, dt, x, w.block_tot, st));
     const RangeArg ra{LSEFIT_RANGE_GIVEN, 0.0, 1.0};   // per-fit (c, s) are in the records
     LSEFIT_TRY(timed(kTimeMoments, st,
@@ -237,7 +262,7 @@ lsefit_status check_single(const void* x, const void* y, int64_t n, int dt, cons
                            size_t ws_bytes, Layout* lay, lsefit_schedule* sched) {
     if (!x || !y || !ws || !opts_ok(opt, dt, false)) return LSEFIT_ERR_INVALID_ARG;
     if (n < (int64_t)opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
-    if (opt->precision == LSEFIT_PREC_F32C && dt != LSEFIT_F32) return LSEFIT_ERR_UNSUPPORTED;
+    if (unsupported(opt, dt)) return LSEFIT_ERR_UNSUPPORTED;
     *sched = current_default();
     *lay = layout(1, opt->degree, to_launch(*sched).waves);
     if (ws_bytes < lay->total) return LSEFIT_ERR_WORKSPACE;
@@ -329,7 +354,7 @@ lsefit_status lsefit_set_default_schedule(const lsefit_schedule* s) {
 }
 
 size_t lsefit_workspace_bytes(int64_t batch, int32_t max_degree, const lsefit_schedule* schedule) {
-    if (batch < 1 || max_degree < 1 || max_degree > LSEFIT_MAX_DEGREE) return 0;
+    if (batch < 1 || max_degree < 1 || max_degree > LSEFIT_MAX_DEGREE_CHEBYSHEV) return 0;
     const lsefit_schedule s = schedule ? *schedule : current_default();
     if (!schedule_ok(s)) return 0;
     return layout(batch, max_degree, to_launch(s).waves).total;
@@ -342,6 +367,19 @@ int64_t grid_blocks(const Launch& L) { return L.waves / L.wpb; }
 lsefit_status single_pass(bool refine_pass, const FitDesc& d, const Work& w, const lsefit_options* opt, int dt,
                           const void* x, const void* y, const Launch& L, int mis, const Finish& fz, hipStream_t st) {
     const RangeArg ra{opt->range_mode, opt->center, opt->scale};
+    if (chebyshev(opt)) {
+        RangeArg rc = ra;
+        if (opt->range_mode == LSEFIT_RANGE_AUTO) {
+            LSEFIT_TRY(timed(kTimeRange, st,
+                             [&] { return launch_range_cheb(d, w, opt->degree, dt, x, L, mis, st); }));
+            rc.mode = kRangeFromRecord;
+        }
+        LSEFIT_TRY(timed(kTimeMoments, st,
+                         [&] { return launch_moments_cheb(d, w, opt->degree, dt, x, y, L, mis, rc, st); }));
+        LSEFIT_TRY(timed(kTimeCombine, st,
+                         [&] { return launch_finish_cheb(d, w, opt->degree, grid_blocks(L), fz, st); }));
+        return LSEFIT_OK;
+    }
     if (refine_pass)
         LSEFIT_TRY(timed(kTimeRefine, st, [&] { return launch_refine(d, w, opt->degree, dt, x, y, L, mis, st); }));
     else
@@ -369,6 +407,7 @@ lsefit_status fit_moments(const void* x, const void* y, int64_t n, lsefit_dtype 
 lsefit_status fit_solve(const double* moments, const lsefit_options* opt, const void* x, const void* y, int64_t n,
                         lsefit_dtype dt, void* ws, size_t ws_bytes, double* coef, int32_t* status, void* stream) {
     if (!moments || !ws || !coef || !status || !opts_ok(opt, dt, false)) return LSEFIT_ERR_INVALID_ARG;
+    if (chebyshev(opt) && opt->precision != LSEFIT_PREC_F64) return LSEFIT_ERR_UNSUPPORTED;
     const bool refine = refining(opt);
     if (refine) {
         if (!x || !y || n < (int64_t)opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
@@ -380,6 +419,11 @@ lsefit_status fit_solve(const double* moments, const lsefit_options* opt, const 
     hipStream_t st = (hipStream_t)stream;
     const FitDesc d{nullptr, nullptr, refine ? n : 0, 1, opt->degree};
     const Work w = carve(ws, lay);
+    if (chebyshev(opt)) {
+        const Finish fz{kSolve, coef, 2 * (opt->degree + 1), 1, status, nullptr, opt->solver};
+        LSEFIT_TRY(launch_solve_cheb_moments(moments, w, opt->degree, fz, st));
+        return LSEFIT_OK;
+    }
     LSEFIT_TRY(launch_solve_moments(moments, w, opt->degree, opt->degree, opt->solver, coef, status, st));
     if (!refine) return LSEFIT_OK;
     const Finish fz{kRefine, coef, 2 * (opt->degree + 1), 1, status, nullptr, opt->solver};
@@ -413,7 +457,7 @@ lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, 
     if (batch == 0) return LSEFIT_OK;
     if (!x || !y || !offsets || !degrees || !coef || !status) return LSEFIT_ERR_INVALID_ARG;
     if (coef_stride < opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
-    if (opt->precision == LSEFIT_PREC_F32C && dt != LSEFIT_F32) return LSEFIT_ERR_UNSUPPORTED;
+    if (unsupported(opt, dt)) return LSEFIT_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     const FitDesc d{offsets, degrees, 0, batch, opt->degree};
     if (!plan) {
@@ -461,6 +505,7 @@ lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets,
     if (batch == 0) return LSEFIT_OK;
     if (!x || !y || !offsets || !degrees || !grad_coef || !grad_x || !grad_y) return LSEFIT_ERR_INVALID_ARG;
     if (coef_stride < opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
+    if (chebyshev(opt)) return LSEFIT_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     const FitDesc d{offsets, degrees, 0, batch, opt->degree};
     Work w;
@@ -488,6 +533,7 @@ lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets
                             int64_t batch, int64_t n, lsefit_dtype dt, const lsefit_options* opt, lsefit_plan* plan,
                             void* ws, size_t ws_bytes, double* sse, void* residuals, void* stream) {
     if (!x || !y || !sse || !opts_ok(opt, dt, offsets != nullptr)) return LSEFIT_ERR_INVALID_ARG;
+    if (chebyshev(opt)) return LSEFIT_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     const int mis = common_mis(dt, {x, y, residuals});
     if (!offsets) {
@@ -529,7 +575,7 @@ lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets
 
 lsefit_status fit_plan_create(lsefit_plan** out, int64_t batch, int32_t max_degree, lsefit_dtype dt,
                               int32_t precision) {
-    if (!out || batch < 1 || max_degree < 1 || max_degree > LSEFIT_MAX_DEGREE) return LSEFIT_ERR_INVALID_ARG;
+    if (!out || batch < 1 || max_degree < 1 || max_degree > LSEFIT_MAX_DEGREE_CHEBYSHEV) return LSEFIT_ERR_INVALID_ARG;
     if (dt != LSEFIT_F32 && dt != LSEFIT_F64) return LSEFIT_ERR_INVALID_ARG;
     if (precision != LSEFIT_PREC_F64 && precision != LSEFIT_PREC_F32C) return LSEFIT_ERR_INVALID_ARG;
     lsefit_plan* p = new (std::nothrow) lsefit_plan();

@@ -39,7 +39,7 @@ struct FitDesc {
     int32_t degree;   // uniform degree, or the largest degree allowed
 };
 
-__device__ inline bool is_single(const FitDesc& d) { return d.offsets == nullptr; }
+__host__ __device__ inline bool is_single(const FitDesc& d) { return d.offsets == nullptr; }
 
 __device__ inline int64_t fit_lo(const FitDesc& d, int64_t f) { return d.offsets ? d.offsets[f] : 0; }
 __device__ inline int64_t fit_hi(const FitDesc& d, int64_t f) { return d.offsets ? d.offsets[f + 1] : d.n_single; }

@@ -33,9 +33,11 @@ struct Finish {
 
 // Range of a single fit: given (c, s), or derived by the streaming kernel itself.
 struct RangeArg {
-    int mode;   // lsefit_range_mode
+    int mode;   // lsefit_range_mode, or kRangeFromRecord
     double c, s;
 };
+// (c, s) already in the fit's record (written by an earlier range pass)
+constexpr int kRangeFromRecord = 2;
 
 // Batched: tile table, plan status and (c, s) of every fit (given, or from a
 // sample of the fit's x), in two launches; block_tot holds plan_blocks(B) int64.
@@ -80,5 +82,20 @@ hipError_t launch_residual(const FitDesc& d, const Work& w, int maxM, int dtype,
 // one float per block into out.
 hipError_t launch_read_probe(const float* x, const float* y, int64_t nvec, const Launch& L, int pattern, bool nt,
                              float* out, hipStream_t st);
+
+// Chebyshev basis (degree up to LSEFIT_MAX_DEGREE_CHEBYSHEV, float64 sums):
+// streaming pass, per-fit finish (single fit: W = number of block partials),
+// and a solve from caller-provided sums.
+// exact extent of the finite x of every fit -> (c, s) of the Chebyshev basis in
+// its record (a streaming pass over x with per-block / per-slot min and max,
+// then a per-fit fold)
+hipError_t launch_range_cheb(const FitDesc& d, const Work& w, int maxm, int dtype, const void* x, const Launch& L,
+                             int mis, hipStream_t st);
+hipError_t launch_moments_cheb(const FitDesc& d, const Work& w, int maxm, int dtype, const void* x, const void* y,
+                               const Launch& L, int mis, const RangeArg& ra, hipStream_t st);
+hipError_t launch_finish_cheb(const FitDesc& d, const Work& w, int maxm, int64_t W, const Finish& fz,
+                              hipStream_t st);
+hipError_t launch_solve_cheb_moments(const double* moments, const Work& w, int m, const Finish& fz,
+                                    hipStream_t st);
 
 }  // namespace lsefit

@@ -281,7 +281,7 @@ __device__ inline void stream_strided(const In* __restrict__ x, const In* __rest
 
 // run body.template operator()<m>() for the runtime degree m (1 <= m <= MAXM)
 template <int MAXM, class Body>
-__device__ inline void dispatch_degree(int m, Body&& body) {
+__host__ __device__ inline void dispatch_degree(int m, Body&& body) {
     switch (m) {
         case 1: if constexpr (MAXM >= 1) body.template operator()<1>(); break;
         case 2: if constexpr (MAXM >= 2) body.template operator()<2>(); break;
@@ -291,6 +291,14 @@ __device__ inline void dispatch_degree(int m, Body&& body) {
         case 6: if constexpr (MAXM >= 6) body.template operator()<6>(); break;
         case 7: if constexpr (MAXM >= 7) body.template operator()<7>(); break;
         case 8: if constexpr (MAXM >= 8) body.template operator()<8>(); break;
+        case 9: if constexpr (MAXM >= 9) body.template operator()<9>(); break;
+        case 10: if constexpr (MAXM >= 10) body.template operator()<10>(); break;
+        case 11: if constexpr (MAXM >= 11) body.template operator()<11>(); break;
+        case 12: if constexpr (MAXM >= 12) body.template operator()<12>(); break;
+        case 13: if constexpr (MAXM >= 13) body.template operator()<13>(); break;
+        case 14: if constexpr (MAXM >= 14) body.template operator()<14>(); break;
+        case 15: if constexpr (MAXM >= 15) body.template operator()<15>(); break;
+        case 16: if constexpr (MAXM >= 16) body.template operator()<16>(); break;
         default: break;
     }
 }

@@ -24,6 +24,12 @@ of low degree fitted to many points, Sec. I and Sec. II of the paper):
                       noise N(0, 0.05^2), targets a_target ~ N(0,1) (FP64)
 * ``shifted_quintic`` n = 1e7 FP32, x ~ U[1000,1001], y = poly of degree 5 in
                       (x - 1000.5) with coefficients N(0,1), noise N(0, 1e-4^2)
+
+and one for the higher degrees the Chebyshev basis serves (beyond Sec. II's
+low orders):
+
+* ``runge``           n = 1e8 FP32, x ~ U[-1,1], y = 1/(1 + 25x^2) + N(0, 1e-3^2),
+                      m = 12
 """
 from __future__ import annotations
 
@@ -117,6 +123,25 @@ def shifted_quintic(n: int = 10_000_000, seed: int = 5000) -> SingleFit:
     """m = 5, FP32 storage, x ~ U[1000, 1001], polynomial in (x - 1000.5), noise N(0, 1e-4^2)."""
     return _single("shifted_quintic", n, seed, 1000.0, 1001.0, np.float32,
                    lambda r: r.standard_normal(6), 1e-4, 5, center=1000.5)
+
+
+def runge(n: int = 100_000_000, seed: int = 6000, degree: int = 12, lo: float = -1.0, hi: float = 1.0,
+          dtype=np.float32, noise_sd: float = 1e-3) -> SingleFit:
+    """Higher-degree workload: y = 1 / (1 + 25 u^2) + N(0, noise_sd^2), u the
+    position of x in [lo, hi] mapped to [-1, 1], x ~ U[lo, hi]; fitted with
+    degree ``degree`` (no polynomial generates it: true_coef is empty)."""
+    _, r_x, r_noise = _streams(seed)
+    x_out = np.empty(n, dtype=dtype)
+    y_out = np.empty(n, dtype=dtype)
+    mid, half = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    for s in range(0, n, CHUNK):
+        e = min(n, s + CHUNK)
+        xs = r_x.uniform(lo, hi, e - s)
+        u = (xs - mid) / half
+        x_out[s:e] = xs
+        y_out[s:e] = 1.0 / (1.0 + 25.0 * u * u) + r_noise.normal(0.0, noise_sd, e - s)
+    return SingleFit("runge", x_out, y_out, degree, np.zeros(0), 0.0, seed,
+                     {"lo": lo, "hi": hi, "noise_sd": noise_sd})
 
 
 def ragged_lengths(batch: int, lo: int, hi: int, rng) -> np.ndarray:

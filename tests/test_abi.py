@@ -53,7 +53,8 @@ def test_workspace_bytes_grows_with_batch_and_degree():
     c = L.lsefit_workspace_bytes(1000, 8, ctypes.byref(s))
     assert 0 < a < b < c
     assert L.lsefit_workspace_bytes(0, 3, ctypes.byref(s)) == 0
-    assert L.lsefit_workspace_bytes(1, 9, ctypes.byref(s)) == 0
+    assert L.lsefit_workspace_bytes(1, 16, ctypes.byref(s)) > c      # Chebyshev-basis fits go to 16
+    assert L.lsefit_workspace_bytes(1, 17, ctypes.byref(s)) == 0
     bad = _lib.Schedule(4096, 3, 256, 2)
     assert L.lsefit_workspace_bytes(1, 3, ctypes.byref(bad)) == 0
 
@@ -70,6 +71,10 @@ FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails va
     ({"range_mode": 0, "scale": float("nan")}, 100, _lib.F32, _lib.INVALID_ARG),
     ({"refine_steps": 2}, 100, _lib.F32, _lib.INVALID_ARG),
     ({}, 100, 7, _lib.INVALID_ARG),
+    ({"basis": 2}, 100, _lib.F32, _lib.INVALID_ARG),
+    ({"basis": 1, "degree": 17}, 100, _lib.F32, _lib.INVALID_ARG),
+    ({"basis": 1, "degree": 16}, 16, _lib.F32, _lib.INVALID_ARG),    # n < m + 1
+    ({"basis": 1, "precision": 1}, 100, _lib.F32, _lib.UNSUPPORTED),  # Chebyshev sums are float64 only
 ])
 def test_fit_moments_host_validation(kw, n, dt, expect):
     L = _lib.load()
@@ -100,8 +105,13 @@ def test_null_pointers_rejected():
     assert L.fit_backward(FAKE, FAKE, FAKE, FAKE, 10, _lib.F32, ctypes.byref(o), None, FAKE, 1 << 30, None, 4,
                           FAKE, FAKE, None) == _lib.INVALID_ARG
     assert L.fit_plan_create(None, 10, 3, _lib.F32, 0) == _lib.INVALID_ARG
+    cheb = _opt(basis=1)
+    assert L.fit_backward(FAKE, FAKE, FAKE, FAKE, 10, _lib.F32, ctypes.byref(cheb), None, FAKE, 1 << 30, FAKE, 4,
+                          FAKE, FAKE, None) == _lib.UNSUPPORTED     # no adjoint for the Chebyshev basis
+    assert L.fit_residuals(FAKE, FAKE, None, None, 1, 100, _lib.F32, ctypes.byref(cheb), None, FAKE, 1 << 30,
+                           FAKE, None, None) == _lib.UNSUPPORTED
     h = ctypes.c_void_p()
-    assert L.fit_plan_create(ctypes.byref(h), 10, 9, _lib.F32, 0) == _lib.INVALID_ARG
+    assert L.fit_plan_create(ctypes.byref(h), 10, 17, _lib.F32, 0) == _lib.INVALID_ARG
     L.fit_plan_destroy(None)
 
 

@@ -60,3 +60,45 @@ def test_monomial_route_fails_where_chebyshev_holds():
         assert np.max(np.abs(c_from_mono - ref)) > 1e-6 * np.max(np.abs(ref))
     else:
         assert mono["status"] == fp64.SINGULAR
+
+
+@pytest.mark.parametrize("m", [1, 4, 9, 16])
+def test_c_oracle_matches_python_oracle(m):
+    """The plain-C Chebyshev route (entrywise compensated sums, chunked) agrees
+    with the fsum route, and its Gram matrix is the definition's."""
+    from oracle import c_oracle
+    wl = W.runge(n=3000, seed=40 + m, dtype=np.float64, lo=-2.0, hi=3.0)
+    r = c_oracle.cheb_fit(wl.x, wl.y, m, 0.5, 2.5)
+    p = cheb.fit_cheb(wl.x, wl.y, m, 0.5, 2.5)
+    assert r["status"] == "ok"
+    assert np.max(np.abs(r["c"] - p["c"])) <= 1e-12 * np.max(np.abs(p["c"]))
+    t = (wl.x - 0.5) / 2.5
+    V = np.polynomial.chebyshev.chebvander(t, m)
+    assert np.allclose(r["G"], V.T @ V, rtol=1e-12, atol=1e-12 * wl.x.size)
+    assert r["G"][0, 0] == wl.x.size
+
+
+def test_c_oracle_batched_matches_single():
+    from oracle import c_oracle
+    lengths = [0, 3, 17, 500, 2000]
+    degrees = [2, 3, 16, 9, 12]
+    bf = W.random_batch(lengths, degrees, seed=9, dtype=np.float64)
+    out, st = c_oracle.cheb_fit_batched(bf.x, bf.y, bf.offsets, bf.degrees, stride=17)
+    assert list(st) == [2, 2, 0, 0, 0]
+    assert np.isnan(out[0, :3]).all() and np.isnan(out[1, :4]).all()
+    for f in (2, 3, 4):
+        lo, hi = bf.offsets[f], bf.offsets[f + 1]
+        r = c_oracle.cheb_fit(bf.x[lo:hi], bf.y[lo:hi], int(degrees[f]))
+        assert np.array_equal(out[f, : degrees[f] + 1], r["c"])
+
+
+def test_cheb_range_maps_extent_onto_unit_interval():
+    rng = np.random.default_rng(5)
+    for lo, hi in [(-1.0, 1.0), (1000.0, 1001.0), (-7.25, 3.5), (0.0, 1e-3)]:
+        x = rng.uniform(lo, hi, 1000).astype(np.float32)
+        x[[3, 17]] = [np.nan, np.inf]                 # skipped
+        c, s = cheb.cheb_range(x)
+        f = x[np.isfinite(x)].astype(np.float64)
+        assert (f.min() - c) / s == -1.0 and (f.max() - c) / s == 1.0
+    assert cheb.cheb_range(np.full(5, 2.5)) == (2.5, 1.0)
+    assert cheb.cheb_range(np.array([np.nan, np.inf])) == (0.0, 1.0)

@@ -421,10 +421,12 @@ lsefit_status fit_solve(const double* moments, const lsefit_options* opt, const 
     const Work w = carve(ws, lay);
     if (chebyshev(opt)) {
         const Finish fz{kSolve, coef, 2 * (opt->degree + 1), 1, status, nullptr, opt->solver};
-        LSEFIT_TRY(launch_solve_cheb_moments(moments, w, opt->degree, fz, st));
+        LSEFIT_TRY(timed(kTimeCombine, st, [&] { return launch_solve_cheb_moments(moments, w, opt->degree, fz, st); }));
         return LSEFIT_OK;
     }
-    LSEFIT_TRY(launch_solve_moments(moments, w, opt->degree, opt->degree, opt->solver, coef, status, st));
+    LSEFIT_TRY(timed(kTimeCombine, st, [&] {
+        return launch_solve_moments(moments, w, opt->degree, opt->degree, opt->solver, coef, status, st);
+    }));
     if (!refine) return LSEFIT_OK;
     const Finish fz{kRefine, coef, 2 * (opt->degree + 1), 1, status, nullptr, opt->solver};
     return single_pass(true, d, w, opt, dt, x, y, to_launch(sched), common_mis(dt, {x, y}), fz, st);

@@ -3,25 +3,32 @@
 // The least-squares problem of Sec. II written in the basis T_0..T_m of
 // Chebyshev polynomials of t = (x - c)/s instead of powers of x (Sec. V leaves
 // higher-order polynomials as further work; the monomial normal matrix loses
-// all precision there).  The streaming pass sums C_k = sum_i T_k(t_i)
-// (k = 1..2m, by the three-term recurrence T_(k+1) = 2 t T_k - T_(k-1)) and
-// D_j = sum_i y_i T_j(t_i); since T_j T_k = (T_(j+k) + T_|j-k|) / 2, the Gram
-// matrix is G_jk = (C_(j+k) + C_|j-k|) / 2 with C_0 = n, and G c = D gives the
-// Chebyshev coefficients c.  Float64 accumulation only.
+// all precision there).  Since T_j T_k = (T_(j+k) + T_|j-k|) / 2, the Gram
+// matrix is G_jk = (C_(j+k) + C_|j-k|) / 2 with C_k = sum_i T_k(t_i), C_0 = n,
+// and the right side is D_j = sum_i y_i T_j(t_i); G c = D gives the Chebyshev
+// coefficients c.  Float64 accumulation only.
+//
+// Per point the pass forms T_2..T_m by the three-term recurrence
+// T_(k+1) = 2 t T_k - T_(k-1) and accumulates C_1..C_m, D_0..D_m and
+// E_j = sum_i T_m(t_i) T_j(t_i) (j = 1..m); the upper sums follow from the same
+// identity, C_(m+j) = 2 E_j - C_(m-j).  That is 4m+2 float64 operations per
+// point instead of the 5m+2 of running the recurrence up to T_2m.
 #include "kernels_impl.hpp"
 
 namespace lsefit {
 
 constexpr int kChebMax = LSEFIT_MAX_DEGREE_CHEBYSHEV;
 
+// partial sums of one lane: [C_1..C_M, E_1..E_M, D_0..D_M] (nacc(M) values)
 template <int M>
 struct AccCheb {
-    double C[2 * M];   // C_1..C_2M
+    double C[M];       // C_1..C_M
+    double E[M];       // E_1..E_M
     double D[M + 1];   // D_0..D_M
     double inv_s, nc;
     __device__ inline void init(double c, double is) {
 #pragma unroll
-        for (int k = 0; k < 2 * M; ++k) C[k] = 0.0;
+        for (int k = 0; k < M; ++k) C[k] = E[k] = 0.0;
 #pragma unroll
         for (int j = 0; j <= M; ++j) D[j] = 0.0;
         inv_s = is;
@@ -30,17 +37,17 @@ struct AccCheb {
     __device__ inline void point(double xv, double yv) {
         const double t = fma(xv, inv_s, nc);
         const double t2 = t + t;
-        double tp = 1.0, tc = t;
-        D[0] += yv;
-        C[0] += tc;
-        D[1] = fma(yv, tc, D[1]);
+        double T[M + 1];
+        T[0] = 1.0;
+        T[1] = t;
 #pragma unroll
-        for (int k = 2; k <= 2 * M; ++k) {
-            const double tn = fma(t2, tc, -tp);
-            C[k - 1] += tn;
-            if (k <= M) D[k] = fma(yv, tn, D[k]);
-            tp = tc;
-            tc = tn;
+        for (int k = 2; k <= M; ++k) T[k] = fma(t2, T[k - 1], -T[k - 2]);
+        D[0] += yv;
+#pragma unroll
+        for (int k = 1; k <= M; ++k) {
+            C[k - 1] += T[k];
+            D[k] = fma(yv, T[k], D[k]);
+            E[k - 1] = fma(T[M], T[k], E[k - 1]);
         }
     }
     template <typename V, int VW>
@@ -220,9 +227,10 @@ __global__ void __launch_bounds__(256) k_range_fold_batch(FitDesc d, Work w, int
     cheb_range(lo, hi, &r[0], &r[1]);
 }
 
-// the waves of a block add their sums in order; one partial per block
+// the waves of a block add their sums in order; one partial per block, stored
+// sum-major (sum k of block g at part[k G + g], G blocks)
 template <int K>
-__device__ inline void cheb_block_partial(const Work& w, const double (&v)[K], int stride) {
+__device__ inline void cheb_block_partial(const Work& w, const double (&v)[K]) {
     __shared__ double sh[4][K];
     if (lane_id() == 0) {
 #pragma unroll
@@ -233,14 +241,17 @@ __device__ inline void cheb_block_partial(const Work& w, const double (&v)[K], i
         const int nw = blockDim.x / kWave;
         double acc = sh[0][threadIdx.x];
         for (int i = 1; i < nw; ++i) acc += sh[i][threadIdx.x];
-        w.part[(int64_t)blockIdx.x * stride + threadIdx.x] = acc;
+        w.part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = acc;
     }
 }
 
 template <int M>
 __device__ inline void cheb_wave_sums(const AccCheb<M>& acc, double (&v)[nacc(M)]) {
 #pragma unroll
-    for (int k = 0; k < 2 * M; ++k) v[k] = wave_sum(acc.C[k]);
+    for (int k = 0; k < M; ++k) {
+        v[k] = wave_sum(acc.C[k]);
+        v[M + k] = wave_sum(acc.E[k]);
+    }
 #pragma unroll
     for (int j = 0; j <= M; ++j) v[2 * M + j] = wave_sum(acc.D[j]);
 }
@@ -263,7 +274,7 @@ __global__ void __launch_bounds__(256)
     stream_strided<U>(x, y, d.n_single, mis, wave, W, acc);
     double v[nacc(M)];
     cheb_wave_sums(acc, v);
-    cheb_block_partial<nacc(M)>(w, v, nacc(M));
+    cheb_block_partial<nacc(M)>(w, v);
 }
 
 // batch, degrees up to MAXC <= maxm: each wave walks its tiles, one partial
@@ -295,156 +306,213 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// finishing a Chebyshev fit: one thread, matrices in LDS (up to 17 x 18)
+// finishing a Chebyshev fit: one wave per fit.  The sums go to a per-wave LDS
+// row [C_0..C_2m, D_0..D_m]; lane r < m+1 then holds row r of [G | D] in
+// registers for the elimination, and the lanes share pivot rows and solved
+// unknowns through readlane.
 // ---------------------------------------------------------------------------
-constexpr int kChebN = kChebMax + 1;
+__device__ inline double bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
 
-struct ChebShared {
-    double A[kChebN][kChebN + 1];
-    double L[kChebN][kChebN];
-    double X[kChebN];
-    double Tp[kChebN], Tc[kChebN], Tn[kChebN], b[kChebN];
-};
+// orders this wave's LDS writes before its later LDS reads
+__device__ inline void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-// partial pivoting on the augmented N x (N+1) matrix A
-__device__ inline int lds_gepp(ChebShared& sm, int N) {
+// max |G| over the N x N part held by lanes 0..N-1
+template <int M>
+__device__ inline double wave_amax(const double (&row)[M + 2]) {
+    constexpr int N = M + 1;
+    double la = 0.0;
+    if (lane_id() < N) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) la = fmax(la, fabs(row[c]));
+    }
     double amax = 0.0;
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) amax = fmax(amax, fabs(sm.A[i][j]));
-    const double tiny = ldexp(amax, -40);
+#pragma unroll
+    for (int r = 0; r < N; ++r) amax = fmax(amax, bcast(la, r));
+    return amax;
+}
+
+// Partial pivoting (first row of largest magnitude), singular when a pivot is
+// at most 2^-40 max|G|; the same operations, in the same order per entry, as an
+// elimination by one thread.  On success lane i < N holds x_i in xl.
+template <int M>
+__device__ __forceinline__ int wave_gepp(double (&row)[M + 2], double& xl) {
+    constexpr int N = M + 1;
+    const int lane = lane_id();
+    const double tiny = ldexp(wave_amax<M>(row), -40);
+#pragma unroll
     for (int k = 0; k < N; ++k) {
         int p = k;
-        for (int r = k + 1; r < N; ++r)
-            if (fabs(sm.A[r][k]) > fabs(sm.A[p][k])) p = r;
-        if (!(fabs(sm.A[p][k]) > tiny)) return LSEFIT_ERR_SINGULAR;
-        if (p != k)
-            for (int c = 0; c <= N; ++c) {
-                const double tmp = sm.A[k][c];
-                sm.A[k][c] = sm.A[p][c];
-                sm.A[p][c] = tmp;
-            }
+        double pv = fabs(bcast(row[k], k));
+#pragma unroll
         for (int r = k + 1; r < N; ++r) {
-            const double l = sm.A[r][k] / sm.A[k][k];
-            for (int c = k; c <= N; ++c) sm.A[r][c] -= l * sm.A[k][c];
+            const double v = fabs(bcast(row[k], r));
+            if (v > pv) {
+                pv = v;
+                p = r;
+            }
+        }
+        if (!(pv > tiny)) return LSEFIT_ERR_SINGULAR;
+        p = __builtin_amdgcn_readfirstlane(p);
+        if (p != k) {
+#pragma unroll
+            for (int c = k; c <= N; ++c) {
+                const double a = bcast(row[c], p), b = bcast(row[c], k);
+                if (lane == k) row[c] = a;
+                else if (lane == p) row[c] = b;
+            }
+        }
+        const double pk = bcast(row[k], k);
+        if (lane > k && lane < N) {
+            const double l = row[k] / pk;
+#pragma unroll
+            for (int c = k; c <= N; ++c) row[c] -= l * bcast(row[c], k);
         }
     }
+    xl = 0.0;
+#pragma unroll
     for (int i = N - 1; i >= 0; --i) {
-        double acc = sm.A[i][N];
-        for (int c = i + 1; c < N; ++c) acc -= sm.A[i][c] * sm.X[c];
-        sm.X[i] = acc / sm.A[i][i];
+        double acc = row[N];
+#pragma unroll
+        for (int c = i + 1; c < N; ++c) acc -= row[c] * bcast(xl, c);
+        const double xi = bcast(acc / row[i], i);
+        if (lane == i) xl = xi;
     }
     return LSEFIT_OK;
 }
 
-// A = L L^T on the N x N part, then the two triangular solves
-__device__ inline int lds_cholesky(ChebShared& sm, int N) {
-    double amax = 0.0;
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) amax = fmax(amax, fabs(sm.A[i][j]));
-    const double tiny = ldexp(amax, -40);
+// G = L L^T (lane r holds row r of L), then L z = D and L^T x = z; lane i < N
+// holds x_i in xl
+template <int M>
+__device__ __forceinline__ int wave_cholesky(const double (&row)[M + 2], double& xl) {
+    constexpr int N = M + 1;
+    const int lane = lane_id();
+    const double tiny = ldexp(wave_amax<M>(row), -40);
+    double L[M + 1];
+#pragma unroll
+    for (int c = 0; c < N; ++c) L[c] = 0.0;
+#pragma unroll
     for (int j = 0; j < N; ++j) {
-        double dg = sm.A[j][j];
-        for (int k = 0; k < j; ++k) dg -= sm.L[j][k] * sm.L[j][k];
+        double dg = bcast(row[j], j);
+#pragma unroll
+        for (int k = 0; k < j; ++k) {
+            const double ljk = bcast(L[k], j);
+            dg -= ljk * ljk;
+        }
         if (!(dg > tiny)) return LSEFIT_ERR_SINGULAR;
-        sm.L[j][j] = sqrt(dg);
-        for (int i = j + 1; i < N; ++i) {
-            double acc = sm.A[i][j];
-            for (int k = 0; k < j; ++k) acc -= sm.L[i][k] * sm.L[j][k];
-            sm.L[i][j] = acc / sm.L[j][j];
+        const double ljj = sqrt(dg);
+        if (lane == j) {
+            L[j] = ljj;
+        } else if (lane > j && lane < N) {
+            double acc = row[j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) acc -= L[k] * bcast(L[k], j);
+            L[j] = acc / ljj;
         }
     }
+    double zl = 0.0;
+#pragma unroll
     for (int i = 0; i < N; ++i) {
-        double acc = sm.A[i][N];
-        for (int k = 0; k < i; ++k) acc -= sm.L[i][k] * sm.X[k];
-        sm.X[i] = acc / sm.L[i][i];
+        double acc = row[N];
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc -= L[k] * bcast(zl, k);
+        const double zi = bcast(acc / L[i], i);
+        if (lane == i) zl = zi;
     }
+    xl = 0.0;
+#pragma unroll
     for (int i = N - 1; i >= 0; --i) {
-        double acc = sm.X[i];
-        for (int k = i + 1; k < N; ++k) acc -= sm.L[k][i] * sm.X[k];
-        sm.X[i] = acc / sm.L[i][i];
+        double acc = bcast(zl, i);
+#pragma unroll
+        for (int k = i + 1; k < N; ++k) acc -= bcast(L[i], k) * bcast(xl, k);
+        const double xi = acc / bcast(L[i], i);
+        if (lane == i) xl = xi;
     }
     return LSEFIT_OK;
 }
 
-// v = [C_1..C_2m, D_0..D_m] of fit f: assemble G, solve, write the Chebyshev
-// coefficients (then, for a single fit, the x-basis coefficients after them;
-// for a batch, c and s after them when the stride leaves room)
-__device__ inline void cheb_finish(const Work& w, int64_t f, int m, int maxm, double n, const double* v,
-                                   const Finish& fz, ChebShared& sm) {
-    const int N = m + 1;
-    const int rl = rec_len(maxm);
-    double* r = w.rec + f * rl;
-    const double c0 = r[0], s0 = r[1];
-    auto Cs = [&](int k) { return k == 0 ? n : v[k - 1]; };
-    for (int k = 0; k <= 2 * m; ++k) r[rec_S(maxm) + k] = Cs(k);
-    for (int j = 0; j < N; ++j) r[rec_T(maxm) + j] = v[2 * m + j];
-    if (fz.moments_out) {
-        fz.moments_out[0] = c0;
-        fz.moments_out[1] = s0;
-        for (int k = 0; k <= 2 * m; ++k) fz.moments_out[2 + k] = Cs(k);
-        for (int j = 0; j < N; ++j) fz.moments_out[3 + 2 * m + j] = v[2 * m + j];
-    }
-    if (fz.mode == kMomentsOnly) return;
+// S = this wave's LDS row [C_0..C_2m, D_0..D_m] of fit f (written and fenced by
+// the caller): assemble, solve, write the Chebyshev coefficients (then, with
+// write_b, the x-basis coefficients after them; else c and s after them when
+// the stride leaves room), the record's b and the status
+template <int M>
+__device__ __forceinline__ void cheb_solve_wave(const Work& w, int64_t f, int maxm, double c0, double s0, const double* S,
+                                       const Finish& fz) {
+    constexpr int N = M + 1;
+    const int lane = lane_id();
+    const bool mine = lane < N;
+    double row[M + 2];
     bool finite = true;
-    for (int j = 0; j < N; ++j) {
-        for (int k = 0; k < N; ++k) {
-            const int dk = j > k ? j - k : k - j;
-            sm.A[j][k] = 0.5 * (Cs(j + k) + Cs(dk));
-            finite = finite && isfinite(sm.A[j][k]);
+#pragma unroll
+    for (int c = 0; c <= N; ++c) row[c] = 0.0;
+    if (mine) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            const int dk = lane > c ? lane - c : c - lane;
+            row[c] = 0.5 * (S[lane + c] + S[dk]);
+            finite = finite && isfinite(row[c]);
         }
-        sm.A[j][N] = v[2 * m + j];
-        finite = finite && isfinite(sm.A[j][N]);
+        row[N] = S[2 * M + 1 + lane];
+        finite = finite && isfinite(row[N]);
     }
-    int st = !finite ? LSEFIT_ERR_NONFINITE
-                     : (fz.solver == LSEFIT_SOLVER_CHOLESKY ? lds_cholesky(sm, N) : lds_gepp(sm, N));
-    for (int j = 0; j < N && st == LSEFIT_OK; ++j)
-        if (!isfinite(sm.X[j])) st = LSEFIT_ERR_NONFINITE;
+    double x = 0.0;
+    int st = __ballot(!finite) ? LSEFIT_ERR_NONFINITE
+                               : (fz.solver == LSEFIT_SOLVER_CHOLESKY ? wave_cholesky<M>(row, x)
+                                                                      : wave_gepp<M>(row, x));
+    if (st == LSEFIT_OK && __ballot(mine && !isfinite(x))) st = LSEFIT_ERR_NONFINITE;
+    double* r = w.rec + f * rec_len(maxm);
     double* out = fz.coef + f * (int64_t)fz.coef_stride;
     if (st != LSEFIT_OK) {
-        for (int j = 0; j < N; ++j) {
-            out[j] = NAN;
-            r[rec_b(maxm) + j] = NAN;
-            if (fz.write_b) out[N + j] = NAN;
+        if (mine) {
+            out[lane] = NAN;
+            r[rec_b(maxm) + lane] = NAN;
+            if (fz.write_b) out[N + lane] = NAN;
         }
     } else {
-        for (int j = 0; j < N; ++j) {
-            out[j] = sm.X[j];
-            r[rec_b(maxm) + j] = sm.X[j];
+        if (mine) {
+            out[lane] = x;
+            r[rec_b(maxm) + lane] = x;
         }
         if (fz.write_b) {
-            // Chebyshev -> powers of t (b), then -> powers of x (a)
-            for (int k = 0; k < N; ++k) {
-                sm.Tp[k] = k == 0 ? 1.0 : 0.0;
-                sm.Tc[k] = k == 1 ? 1.0 : 0.0;
-                sm.b[k] = sm.X[0] * sm.Tp[k] + (N > 1 ? sm.X[1] * sm.Tc[k] : 0.0);
-            }
+            // Chebyshev -> powers of t (lane k holds coefficient k of T_(j-1), T_j)
+            double Tp = lane == 0 ? 1.0 : 0.0;
+            double Tc = lane == 1 ? 1.0 : 0.0;
+            double b = bcast(x, 0) * Tp + (N > 1 ? bcast(x, 1) * Tc : 0.0);
+#pragma unroll
             for (int j = 1; j + 1 < N; ++j) {
-                for (int k = 0; k < N; ++k) sm.Tn[k] = (k > 0 ? 2.0 * sm.Tc[k - 1] : 0.0) - sm.Tp[k];
-                for (int k = 0; k < N; ++k) {
-                    sm.b[k] += sm.X[j + 1] * sm.Tn[k];
-                    sm.Tp[k] = sm.Tc[k];
-                    sm.Tc[k] = sm.Tn[k];
-                }
+                const double up = __shfl_up(Tc, 1, kWave);
+                const double Tn = (lane > 0 ? 2.0 * up : 0.0) - Tp;
+                b += bcast(x, j + 1) * Tn;
+                Tp = Tc;
+                Tc = Tn;
             }
+            // powers of t -> powers of x: a_k = sum_(j>=k) b_j C(j,k) (-c)^(j-k) s^-j
             const double inv_s = 1.0 / s0;
-            for (int k = 0; k < N; ++k) {
-                double acc = 0.0, binom = 1.0, cpow = 1.0, spow = 1.0;
-                for (int i = 0; i < k; ++i) spow *= inv_s;
-                for (int j = k; j < N; ++j) {
-                    acc += sm.b[j] * binom * cpow * spow;
-                    binom = binom * (double)(j + 1) / (double)(j + 1 - k);
+            double acc = 0.0, binom = 1.0, cpow = 1.0, spow = 1.0;
+            for (int i = 0; i < lane && i < N; ++i) spow *= inv_s;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const double bj = bcast(b, j);
+                if (lane <= j) {
+                    acc += bj * binom * cpow * spow;
+                    binom = binom * (double)(j + 1) / (double)(j + 1 - lane);
                     cpow *= -c0;
                     spow *= inv_s;
                 }
-                out[N + k] = acc;
             }
-        } else if (fz.coef_stride >= N + 2) {
+            if (mine) out[N + lane] = acc;
+        } else if (fz.coef_stride >= N + 2 && lane == 0) {
             out[N] = c0;
             out[N + 1] = s0;
         }
     }
-    w.pstatus[f] = st;
-    if (fz.status) fz.status[f] = st;
+    if (lane == 0) {
+        w.pstatus[f] = st;
+        if (fz.status) fz.status[f] = st;
+    }
 }
 
 __device__ inline void cheb_fail(const FitDesc& d, const Work& w, int64_t f, int maxm, const Finish& fz, int st) {
@@ -458,74 +526,133 @@ __device__ inline void cheb_fail(const FitDesc& d, const Work& w, int64_t f, int
     fz.status[f] = st;
 }
 
-// one block per fit: strided sums over the fit's partial slots, waves in order,
-// then thread 0 finishes (single fit: the slots are the W block partials)
-__global__ void __launch_bounds__(256) k_finish_cheb(FitDesc d, Work w, int64_t W, int maxm, Finish fz) {
-    __shared__ ChebShared sm;
-    __shared__ double sh[4][3 * kChebMax + 1];
-    __shared__ double vv[3 * kChebMax + 1];
+// the summed partials v = [C_1..C_M, E_1..E_M, D_0..D_M] of fit f (uniform)
+// -> S = [C_0..C_2M, D_0..D_M] in this wave's LDS row (C_(M+j) = 2 E_j - C_(M-j)),
+// the record's sums and, if asked, moments_out; lane 0 writes
+template <int M>
+__device__ __forceinline__ void cheb_store_sums(const Work& w, int64_t f, int maxm, double n, const double (&v)[nacc(M)],
+                                       const Finish& fz, double* S) {
+    if (lane_id() == 0) {
+        S[0] = n;
+#pragma unroll
+        for (int k = 1; k <= M; ++k) S[k] = v[k - 1];
+#pragma unroll
+        for (int j = 1; j <= M; ++j) S[M + j] = 2.0 * v[M + j - 1] - S[M - j];
+#pragma unroll
+        for (int j = 0; j <= M; ++j) S[2 * M + 1 + j] = v[2 * M + j];
+        double* r = w.rec + f * rec_len(maxm);
+        for (int k = 0; k <= 2 * M; ++k) r[rec_S(maxm) + k] = S[k];
+        for (int j = 0; j <= M; ++j) r[rec_T(maxm) + j] = S[2 * M + 1 + j];
+        if (fz.moments_out) {
+            fz.moments_out[0] = r[0];
+            fz.moments_out[1] = r[1];
+            for (int k = 0; k < 3 * M + 2; ++k) fz.moments_out[2 + k] = S[k];
+        }
+    }
+    wave_lds_fence();
+}
+
+// Single fit of degree M (one block): the block's threads sum the W block
+// partials (sum-major; thread t takes blocks t, t + 256, ...; then waves in
+// order) and wave 0 finishes.
+template <int M>
+__global__ void __launch_bounds__(256) k_finish_cheb_single(FitDesc d, Work w, int64_t W, int maxm, Finish fz) {
+    constexpr int K = nacc(M);
+    __shared__ double sh[4][K];
+    __shared__ double S[3 * M + 2];
+    const int wid = wave_id_in_block(), lane = lane_id();
+    const int pst = w.pstatus[0];
+    if (pst != LSEFIT_OK) {
+        if (threadIdx.x == 0 && fz.mode != kMomentsOnly) cheb_fail(d, w, 0, maxm, fz, pst);
+        return;
+    }
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (int64_t g = threadIdx.x; g < W; g += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += w.part[(int64_t)k * W + g];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[wid][k] = v[k];
+    }
+    __syncthreads();
+    if (wid != 0) return;
+    const int nw = blockDim.x / kWave;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double acc = sh[0][k];
+        for (int i = 1; i < nw; ++i) acc += sh[i][k];
+        v[k] = acc;
+    }
+    cheb_store_sums<M>(w, 0, maxm, (double)d.n_single, v, fz, S);
+    if (fz.mode != kMomentsOnly) cheb_solve_wave<M>(w, 0, maxm, w.rec[0], w.rec[1], S, fz);
+}
+
+// Batch, degrees up to MAXC: wave v of block b finishes fits 4b + v,
+// 4b + v + 4 gridDim.x, ..., summing the partial slots of the waves that
+// streamed each.
+template <int MAXC>
+__global__ void __launch_bounds__(256) k_finish_cheb_batch(FitDesc d, Work w, int64_t W, int maxm, Finish fz) {
+    __shared__ double S[4][3 * MAXC + 2];
+    const int wid = wave_id_in_block(), lane = lane_id();
     const int stride = nacc(maxm);
-    const bool single = is_single(d);
-    for (int64_t f = blockIdx.x; f < d.batch; f += gridDim.x) {
+    const int64_t NT = w.tile_start[d.batch];
+    for (int64_t f = (int64_t)blockIdx.x * 4 + wid; f < d.batch; f += (int64_t)gridDim.x * 4) {
         const int pst = w.pstatus[f];
         if (pst != LSEFIT_OK) {
-            if (threadIdx.x == 0 && fz.mode != kMomentsOnly) cheb_fail(d, w, f, maxm, fz, pst);
+            if (lane == 0 && fz.mode != kMomentsOnly) cheb_fail(d, w, f, maxm, fz, pst);
             continue;
         }
-        const int m = fit_deg(d, f);
-        int64_t w0 = 0, w1 = W - 1, NT = 0;
-        if (!single) {
-            NT = w.tile_start[d.batch];
-            w0 = wave_of_tile(w.tile_start[f], NT, W);
-            w1 = wave_of_tile(w.tile_start[f + 1] - 1, NT, W);
-        }
+        const int64_t w0 = wave_of_tile(w.tile_start[f], NT, W);
+        const int64_t w1 = wave_of_tile(w.tile_start[f + 1] - 1, NT, W);
         auto body = [&]<int M>() {
             constexpr int K = nacc(M);
             double v[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) v[k] = 0.0;
-            for (int64_t wv = w0 + threadIdx.x; wv <= w1; wv += blockDim.x) {
-                if (!single && !wave_owns_tiles(wv, NT, W)) continue;
-                const double* p = w.part + (single ? wv : wv + f) * stride;
+            for (int64_t wv = w0 + lane; wv <= w1; wv += kWave) {
+                if (!wave_owns_tiles(wv, NT, W)) continue;
+                const double* p = w.part + (wv + f) * stride;
 #pragma unroll
                 for (int k = 0; k < K; ++k) v[k] += p[k];
             }
 #pragma unroll
             for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-            if (lane_id() == 0) {
-#pragma unroll
-                for (int k = 0; k < K; ++k) sh[wave_id_in_block()][k] = v[k];
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                const int nw = blockDim.x / kWave;
-                for (int k = 0; k < K; ++k) {
-                    double acc = sh[0][k];
-                    for (int i = 1; i < nw; ++i) acc += sh[i][k];
-                    vv[k] = acc;
-                }
-                cheb_finish(w, f, M, maxm, (double)(fit_hi(d, f) - fit_lo(d, f)), vv, fz, sm);
-            }
-            __syncthreads();
+            const double* r = w.rec + f * rec_len(maxm);
+            cheb_store_sums<M>(w, f, maxm, (double)(fit_hi(d, f) - fit_lo(d, f)), v, fz, S[wid]);
+            if (fz.mode != kMomentsOnly) cheb_solve_wave<M>(w, f, maxm, r[0], r[1], S[wid], fz);
+            wave_lds_fence();
         };
-        dispatch_degree<kChebMax>(m, body);
+        dispatch_degree<MAXC>(fit_deg(d, f), body);
     }
 }
 
-// one fit from caller-provided sums [c, s, C_0..C_2m, D_0..D_m]
-__global__ void k_solve_cheb_moments(const double* __restrict__ mom, Work w, int m, Finish fz) {
-    __shared__ ChebShared sm;
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    w.rec[0] = mom[0];
-    w.rec[1] = mom[1];
-    const bool ok = mom[1] > 0.0 && isfinite(mom[0]) && isfinite(mom[1]);
-    w.pstatus[0] = ok ? LSEFIT_OK : LSEFIT_ERR_NONFINITE;
+// one fit of degree M from caller-provided sums [c, s, C_0..C_2m, D_0..D_m], one wave
+template <int M>
+__global__ void __launch_bounds__(64) k_solve_cheb_moments(const double* __restrict__ mom, Work w, Finish fz) {
+    __shared__ double S[3 * M + 2];
+    const int lane = lane_id();
+    const double c0 = mom[0], s0 = mom[1];
+    if (lane == 0) {
+        w.rec[0] = c0;
+        w.rec[1] = s0;
+    }
+    const bool ok = s0 > 0.0 && isfinite(c0) && isfinite(s0);
     if (!ok) {
-        const FitDesc d{nullptr, nullptr, 0, 1, m};
-        cheb_fail(d, w, 0, m, fz, LSEFIT_ERR_NONFINITE);
+        if (lane == 0) {
+            w.pstatus[0] = LSEFIT_ERR_NONFINITE;
+            const FitDesc d{nullptr, nullptr, 0, 1, M};
+            cheb_fail(d, w, 0, M, fz, LSEFIT_ERR_NONFINITE);
+        }
         return;
     }
-    cheb_finish(w, 0, m, m, mom[2], mom + 3, fz, sm);
+    for (int k = lane; k < 3 * M + 2; k += kWave) S[k] = mom[2 + k];
+    wave_lds_fence();
+    cheb_solve_wave<M>(w, 0, M, c0, s0, S, fz);
 }
 
 template <typename In>
@@ -584,15 +711,29 @@ hipError_t launch_moments_cheb(const FitDesc& d, const Work& w, int maxm, int dt
 
 hipError_t launch_solve_cheb_moments(const double* moments, const Work& w, int m, const Finish& fz,
                                     hipStream_t st) {
-    hipLaunchKernelGGL(k_solve_cheb_moments, dim3(1), dim3(64), 0, st, moments, w, m, fz);
+    auto body = [&]<int M>() { hipLaunchKernelGGL(k_solve_cheb_moments<M>, dim3(1), dim3(kWave), 0, st, moments, w, fz); };
+    dispatch_degree<kChebMax>(m, body);
     return hipGetLastError();
 }
 
 hipError_t launch_finish_cheb(const FitDesc& d, const Work& w, int maxm, int64_t W, const Finish& fz,
                               hipStream_t st) {
-    int64_t blocks = d.batch < 65536 ? d.batch : 65536;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_finish_cheb, dim3(blocks), dim3(256), 0, st, d, w, W, maxm, fz);
+    if (is_single(d)) {
+        auto body = [&]<int M>() {
+            hipLaunchKernelGGL(k_finish_cheb_single<M>, dim3(1), dim3(256), 0, st, d, w, W, maxm, fz);
+        };
+        dispatch_degree<kChebMax>(d.degree, body);
+        return hipGetLastError();
+    }
+    int64_t blocks = (d.batch + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    const dim3 grid(blocks), block(256);
+    if (maxm <= 4)
+        hipLaunchKernelGGL(k_finish_cheb_batch<4>, grid, block, 0, st, d, w, W, maxm, fz);
+    else if (maxm <= 8)
+        hipLaunchKernelGGL(k_finish_cheb_batch<8>, grid, block, 0, st, d, w, W, maxm, fz);
+    else
+        hipLaunchKernelGGL(k_finish_cheb_batch<kChebMax>, grid, block, 0, st, d, w, W, maxm, fz);
     return hipGetLastError();
 }
 

@@ -245,7 +245,10 @@ __device__ inline void stream_segment(const In* __restrict__ x, const In* __rest
 // single fit: the whole grid strides over the 16-byte vectors of x and y (wave
 // g reads vectors g*64 + lane, then every W*64 further), so consecutive waves
 // read consecutive kilobytes and the grid sweeps the arrays front to back.
-// Wave 0 also takes the unaligned head and the ragged tail.
+// Wave 0 also takes the unaligned head and the ragged tail.  The next round's
+// U vectors per array are loaded before the current round is accumulated, so
+// that a wave covers its own load latency with its arithmetic (few waves fit
+// per SIMD at high degree).
 template <int U, typename In, class Acc>
 __device__ inline void stream_strided(const In* __restrict__ x, const In* __restrict__ y, int64_t n, int mis,
                                       int64_t gwave, int64_t W, Acc& acc) {
@@ -253,30 +256,53 @@ __device__ inline void stream_strided(const In* __restrict__ x, const In* __rest
     using V = typename VecOf<In>::type;
     const int lane = lane_id();
     const int64_t step = W * kWave;
-    if (mis >= 0) {
-        int64_t a = (VW - mis) % VW;
-        if (a > n) a = n;
-        const int64_t nv = (n - a) / VW;
-        const int64_t b = a + nv * VW;
-        if (gwave == 0 && lane < a) acc.scalar(ld_scalar(x + lane), ld_scalar(y + lane));
-        const V* __restrict__ xv = reinterpret_cast<const V*>(x + a);
-        const V* __restrict__ yv = reinterpret_cast<const V*>(y + a);
-        int64_t j = gwave * kWave + lane;
-        for (; j + (int64_t)(U - 1) * step < nv; j += (int64_t)U * step) {
-            V xs[U], ys[U];
+    if (mis < 0) {
+        for (int64_t i = gwave * kWave + lane; i < n; i += step) acc.scalar(ld_scalar(x + i), ld_scalar(y + i));
+        return;
+    }
+    int64_t a = (VW - mis) % VW;
+    if (a > n) a = n;
+    const int64_t nv = (n - a) / VW;
+    const int64_t b = a + nv * VW;
+    if (gwave == 0 && lane < a) acc.scalar(ld_scalar(x + lane), ld_scalar(y + lane));
+    const V* __restrict__ xv = reinterpret_cast<const V*>(x + a);
+    const V* __restrict__ yv = reinterpret_cast<const V*>(y + a);
+    const int64_t span = (int64_t)(U - 1) * step;
+    int64_t j = gwave * kWave + lane;
+    bool have = j + span < nv;
+    V xs[U], ys[U];
+    if (have) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xs[u] = ld_stream(xv + j + u * step);
+            ys[u] = ld_stream(yv + j + u * step);
+        }
+    }
+    while (have) {
+        const int64_t jn = j + (int64_t)U * step;
+        const bool next = jn + span < nv;
+        V xn[U], yn[U];
+        if (next) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                xs[u] = ld_stream(xv + j + u * step);
-                ys[u] = ld_stream(yv + j + u * step);
+                xn[u] = ld_stream(xv + jn + u * step);
+                yn[u] = ld_stream(yv + jn + u * step);
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) acc.template vec<V, VW>(xs[u], ys[u]);
         }
-        for (; j < nv; j += step) acc.template vec<V, VW>(ld_stream(xv + j), ld_stream(yv + j));
-        if (gwave == 0 && lane < n - b) acc.scalar(ld_scalar(x + b + lane), ld_scalar(y + b + lane));
-    } else {
-        for (int64_t i = gwave * kWave + lane; i < n; i += step) acc.scalar(ld_scalar(x + i), ld_scalar(y + i));
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc.template vec<V, VW>(xs[u], ys[u]);
+        if (next) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                xs[u] = xn[u];
+                ys[u] = yn[u];
+            }
+        }
+        j = jn;
+        have = next;
     }
+    for (; j < nv; j += step) acc.template vec<V, VW>(ld_stream(xv + j), ld_stream(yv + j));
+    if (gwave == 0 && lane < n - b) acc.scalar(ld_scalar(x + b + lane), ld_scalar(y + b + lane));
 }
 
 // run body.template operator()<m>() for the runtime degree m (1 <= m <= MAXM)
@@ -460,10 +486,9 @@ __device__ inline void finish_single_block(const FitDesc& d, const Work& w, int6
         for (int k = 0; k < K; ++k) v[k] = 0.0;
 #pragma unroll 4
         for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
-            const double* p = w.part + g * stride;
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                if (k < nk) v[k] += p[k];
+                if (k < nk) v[k] += w.part[(int64_t)k * G + g];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
@@ -549,7 +574,8 @@ __device__ inline void single_range(const FitDesc& d, const Work& w, const In* _
 }
 
 // single fit: the waves of a block add their wave sums in order into one
-// partial per block (part[blockIdx.x]); blocks whose waves own no tiles write zeros
+// partial per block, stored sum-major (sum k of block g at part[k G + g], G
+// blocks), so that the finish reads the partials of each sum contiguously
 template <int K, int STRIDE>
 __device__ inline void single_block_partial(const Work& w, const double (&v)[K]) {
     __shared__ double sh[4][STRIDE];
@@ -562,7 +588,7 @@ __device__ inline void single_block_partial(const Work& w, const double (&v)[K])
         const int nw = blockDim.x / kWave;
         double acc = sh[0][threadIdx.x];
         for (int i = 1; i < nw; ++i) acc += sh[i][threadIdx.x];
-        w.part[(int64_t)blockIdx.x * STRIDE + threadIdx.x] = acc;
+        w.part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = acc;
     }
 }
 

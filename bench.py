@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc output folders into the traffic summary")
     ap.add_argument("--out", type=str, default=None, help="where --summarize-pmc writes (default: profiles/)")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "TITLE", "COMMAND"),
+                    help="turn a rocprofv3 --kernel-trace --stats folder into a text summary (--out: where)")
     return ap.parse_args()
 
 
@@ -119,6 +121,34 @@ def summarize_pmc(fetch_dir, write_dir, out_path=None):
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
+
+
+def summarize_trace(folder, title, command, out_path=None):
+    """Per-kernel call count and duration (avg/min/max) of the library's kernels
+    from a rocprofv3 --kernel-trace --stats output folder, as a short text summary."""
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(folder, "**", "*kernel_stats.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if "lsefit" in r.get("Name", ""):
+                    rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                                 float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+    lines = [f"# rocprofv3 kernel-trace summary: {title}",
+             "# command (on the MI355X box, from /tmp with TMPDIR=/tmp):",
+             f"#   {command}",
+             "# summarised by: python3 bench.py --summarize-trace DIR TITLE COMMAND --out FILE",
+             f"#   (DIR = {folder}, TITLE and COMMAND = the two lines above, FILE = this file)"]
+    for name, calls, avg, mn, mx in sorted(rows, key=lambda r: -r[1] * r[2]):
+        short = name.split("(")[0]
+        lines.append(f"{short:60s} calls {calls:6d}  avg {avg:10.2f} us  min {mn:10.2f} us  max {mx:10.2f} us")
+    text = "\n".join(lines) + "\n"
+    if out_path:
+        os.makedirs(os.path.dirname(os.path.abspath(out_path)), exist_ok=True)
+        with open(out_path, "w") as fh:
+            fh.write(text)
+    print(text, end="")
 
 
 def traffic_bytes(kernel="moments"):
@@ -496,6 +526,9 @@ def main():
     args = parse()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, out_path=args.out)
+        return 0
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace, out_path=args.out)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -11,7 +11,8 @@ Workload (default): one cubic fit of n = 1e8 float32 points, x ~ U[-1, 1],
 coefficients N(0, 1), noise N(0, 0.01^2).  Both accumulation forms are timed
 (float64 accumulation; compensated float32 with one float64 refinement pass);
 ``value`` is the points/s of the form named by --form (default: the faster of
-the two that meets the 1e-6 coefficient bound).
+the two that meets the 1e-6 coefficient bound).  The streaming QR route
+(fit_qr) is timed on the same data as a third, reported form ("qr").
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -181,13 +182,16 @@ def traffic_bytes(kernel="moments"):
 # GPU timing
 # ---------------------------------------------------------------------------
 class SingleFitRunner:
-    """Pre-allocated buffers and one C-ABI step (fit_single: the fused single-fit call)."""
+    """Pre-allocated buffers and one C-ABI step: fit_single (the fused single-fit
+    call) or, with route="qr", fit_qr (the streaming QR route)."""
 
-    def __init__(self, x, y, degree, precision, **opts):
+    def __init__(self, x, y, degree, precision, route="moments", **opts):
         import torch
         from paper_1512_08017_amd import _lib, api
         self.L = _lib.load()
         self.x, self.y, self.m, self.precision = x, y, degree, precision
+        self.fn = self.L.fit_qr if route == "qr" else self.L.fit_single
+        self.name = "fit_qr" if route == "qr" else "fit_single"
         self.opt = api.options(degree, precision, 1, **opts)
         nbytes = api.workspace_bytes(1, degree)
         self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
@@ -202,7 +206,7 @@ class SingleFitRunner:
         self._check = _lib.check
 
     def step(self):
-        self._check(self.L.fit_single(*self.args), "fit_single")
+        self._check(self.fn(*self.args), self.name)
 
 
 def _region(runner, steps):
@@ -573,8 +577,8 @@ def main():
         return 0
 
     forms = {}
-    for prec in ("f64", "f32c"):
-        r = SingleFitRunner(x, y, args.degree, prec)
+    for prec, route in (("f64", "moments"), ("f32c", "moments"), ("qr", "qr")):
+        r = SingleFitRunner(x, y, args.degree, "f64" if prec == "qr" else prec, route=route)
         ms, wall_ms, ms_inst, kern = time_steps(r, args.steps, args.warmup)
         st = int(r.status.cpu()[0])
         forms[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall_ms, "instrumented_ms_per_step": ms_inst,
@@ -596,7 +600,7 @@ def main():
         a = f.pop("coef")
         f["max_rel_coef_err"] = float(np.max(np.abs(a - ref["a"])) / np.max(np.abs(ref["a"])))
 
-    ok = {p: f for p, f in forms.items() if f["status"] == 0 and f["max_rel_coef_err"] <= 1e-6}
+    ok = {p: f for p, f in forms.items() if f["status"] == 0 and f["max_rel_coef_err"] <= 1e-6 and p != "qr"}
     if args.form == "auto":
         head = max(ok, key=lambda p: ok[p]["points_per_s"]) if ok else "f64"
     else:

@@ -200,6 +200,27 @@ lsefit_status fit_solve(const double* moments, const lsefit_options* opt,
 lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
                          void* ws, size_t ws_bytes, double* coef, int32_t* status, double* moments, void* stream);
 
+/* One fit through an orthogonal factorisation instead of the normal equations
+ * (the QR route of Sec. III, which Sec. V's "methods other than Gaussian
+ * elimination" points to): every lane of the streaming pass keeps a triangular
+ * factor of the rows (1, t, .., t^m | y) it reads, updated with square-root-free
+ * Givens rotations (Gentleman), and the factors are merged lane -> wave ->
+ * block -> fit in a fixed order (a tall-skinny tree).  The error is governed by
+ * cond(V), V_ik = t_i^k, not by cond(V)^2 as for the power sums; the pass costs
+ * about (m+1)(m+2)/2 + 12(m+1) float64 operations per point instead of 4m+2.
+ *  x, y, n, dt, ws: as fit_single (same workspace size)
+ *  opt:      degree 1..LSEFIT_MAX_DEGREE, range (as fit_single); precision
+ *            must be LSEFIT_PREC_F64 and basis monomial (else UNSUPPORTED);
+ *            solver and refine_steps are ignored
+ *  coef:     output, device float64 [2(m+1)]: a_0..a_m (x-basis), b_0..b_m (t-basis)
+ *  status:   output, device int32 [1]; SINGULAR when fewer than m+1 points or
+ *            some |R_ii| <= 2^-40 max_k |R_kk|
+ *  info:     optional output (NULL to skip), device float64 [3]: c, s and the
+ *            residual sum of squares sum_i (y_i - f(x_i))^2 (NaN unless OK)
+ * fit_residuals may follow on the same workspace.  Errors as fit_moments. */
+lsefit_status fit_qr(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
+                     void* ws, size_t ws_bytes, double* coef, int32_t* status, double* info, void* stream);
+
 /* B independent fits over CSR segments: fit f owns points offsets[f] ..
  * offsets[f+1]-1 of x and y (Sec. II applied to each segment).
  *  offsets:   device int64 [B+1], non-decreasing, offsets[0] = 0

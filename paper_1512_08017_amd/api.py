@@ -175,6 +175,45 @@ def fit(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None,
     return FitResult(coef[:m1], coef[m1:], status, mom, ws, o)
 
 
+@dataclass
+class QRResult:
+    coef: torch.Tensor       # a_0..a_m, x-basis, float64 (device)
+    coef_t: torch.Tensor     # b_0..b_m, t-basis
+    status: torch.Tensor     # int32 [1]
+    info: torch.Tensor       # [c, s, sum of squared residuals]
+    ws: torch.Tensor | None = None
+    options: Options | None = None
+
+    @property
+    def center(self):
+        return float(self.info[0])
+
+    @property
+    def scale(self):
+        return float(self.info[1])
+
+    @property
+    def sse(self):
+        return float(self.info[2])
+
+
+def fit_qr(x, y, degree: int, center=None, scale=None, ws=None) -> QRResult:
+    """The same fit through a streaming QR factorisation (error ~ cond(V), not cond(V)^2)."""
+    _check_points(x, y)
+    L = _lib.load()
+    o = options(degree, "f64", 0, center, scale)
+    nbytes = workspace_bytes(1, degree)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
+    m1 = degree + 1
+    coef = torch.empty(2 * m1, dtype=torch.float64, device=x.device)
+    status = torch.empty(1, dtype=torch.int32, device=x.device)
+    info = torch.empty(3, dtype=torch.float64, device=x.device)
+    check(L.fit_qr(_ptr(x), _ptr(y), x.numel(), _DT[x.dtype], ctypes.byref(o), _ptr(ws), ws.numel(), _ptr(coef),
+                   _ptr(status), _ptr(info), _stream(x.device)), "fit_qr")
+    return QRResult(coef[:m1], coef[m1:], status, info, ws, o)
+
+
 def fit_split(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None,
               solver: str = "gepp", basis: str = "monomial") -> FitResult:
     """The same fit through the two-call form (fit_moments, then fit_solve)."""

@@ -40,7 +40,9 @@ Layout layout(int64_t B, int maxM, int64_t W) {
     L.rec = off;
     off = align_up(off + sizeof(double) * (size_t)B * rec_len(maxM));
     L.part = off;
-    off = align_up(off + sizeof(double) * (size_t)(W + B) * nacc(maxM));
+    // a single fit may also hold per-block QR factors (fit_qr, degree <= LSEFIT_MAX_DEGREE)
+    const int per = (B == 1 && maxM <= LSEFIT_MAX_DEGREE && qr_len(maxM) > nacc(maxM)) ? qr_len(maxM) : nacc(maxM);
+    off = align_up(off + sizeof(double) * (size_t)(W + B) * per);
     L.block_tot = off;
     off = align_up(off + sizeof(int64_t) * (size_t)((B + kPlanThreads - 1) / kPlanThreads));
     L.total = off + kAlign;   // slack for aligning the caller's base pointer
@@ -450,6 +452,26 @@ lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype d
     if (r != LSEFIT_OK || !refining(opt)) return r;
     const Finish fz{kRefine, coef, stride, 1, status, nullptr, opt->solver};
     return single_pass(true, d, w, opt, dt, x, y, L, mis, fz, st);
+}
+
+lsefit_status fit_qr(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt, void* ws,
+                     size_t ws_bytes, double* coef, int32_t* status, double* info, void* stream) {
+    if (!coef || !status) return LSEFIT_ERR_INVALID_ARG;
+    Layout lay;
+    lsefit_schedule sched;
+    const lsefit_status v = check_single(x, y, n, dt, opt, ws, ws_bytes, &lay, &sched);
+    if (v != LSEFIT_OK) return v;
+    if (opt->precision != LSEFIT_PREC_F64 || chebyshev(opt)) return LSEFIT_ERR_UNSUPPORTED;
+    hipStream_t st = (hipStream_t)stream;
+    const FitDesc d{nullptr, nullptr, n, 1, opt->degree};
+    const Work w = carve(ws, lay);
+    const Launch L = to_launch(sched);
+    const int mis = common_mis(dt, {x, y});
+    const RangeArg ra{opt->range_mode, opt->center, opt->scale};
+    LSEFIT_TRY(timed(kTimeMoments, st, [&] { return launch_qr_single(d, w, dt, x, y, L, mis, ra, st); }));
+    LSEFIT_TRY(timed(kTimeCombine, st,
+                     [&] { return launch_qr_finish(d, w, grid_blocks(L), coef, status, info, st); }));
+    return LSEFIT_OK;
 }
 
 lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,

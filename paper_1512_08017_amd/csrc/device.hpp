@@ -18,6 +18,9 @@ constexpr int kMaxDeg = LSEFIT_MAX_DEGREE;
 
 // Per-wave partial sums of one degree-m segment: S_1..S_2m then T_0..T_m.
 __host__ __device__ constexpr int nacc(int m) { return 3 * m + 1; }
+// flat length of a streaming QR factor of degree m: d, th (m+1 each), the strict
+// upper triangle of the unit factor, the residual sum of squares
+__host__ __device__ constexpr int qr_len(int m) { return 2 * (m + 1) + m * (m + 1) / 2 + 1; }
 
 // Per-fit record kept in the workspace (float64 slots), for a call whose
 // largest degree is M:
@@ -51,7 +54,7 @@ struct Work {
     int32_t* pstatus;     // [B] status found while building the tile table
     double* rec;          // [B * rec_len(M)]
     double* part;         // [(W + B) * nacc(M)] per-(wave, fit) partial sums (batched) or
-                          // per-block partial sums (single fit)
+                          // per-block partial sums (single fit; [W * max(nacc, qr_len)])
     int64_t* block_tot;   // [ceil(B / kPlanThreads)] tile totals of the tile-table blocks
 };
 

@@ -98,4 +98,11 @@ hipError_t launch_finish_cheb(const FitDesc& d, const Work& w, int maxm, int64_t
 hipError_t launch_solve_cheb_moments(const double* moments, const Work& w, int m, const Finish& fz,
                                     hipStream_t st);
 
+// Streaming QR of one fit (degree d.degree): per-block factors into w.part,
+// then one block merges them, solves and writes [a | b], the status and info.
+hipError_t launch_qr_single(const FitDesc& d, const Work& w, int dtype, const void* x, const void* y,
+                            const Launch& L, int mis, const RangeArg& ra, hipStream_t st);
+hipError_t launch_qr_finish(const FitDesc& d, const Work& w, int64_t G, double* coef, int32_t* status, double* info,
+                            hipStream_t st);
+
 }  // namespace lsefit

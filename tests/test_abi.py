@@ -82,6 +82,20 @@ def test_fit_moments_host_validation(kw, n, dt, expect):
     assert L.fit_moments(FAKE, FAKE, n, dt, ctypes.byref(o), FAKE, 1 << 30, FAKE, None) == expect
 
 
+@pytest.mark.parametrize("kw,expect", [
+    ({"degree": 9}, _lib.INVALID_ARG),
+    ({"precision": 1}, _lib.UNSUPPORTED),            # the QR route accumulates in float64 only
+    ({"basis": 1}, _lib.UNSUPPORTED),                # monomial basis only
+])
+def test_fit_qr_host_validation(kw, expect):
+    L = _lib.load()
+    o = _opt(**kw)
+    assert L.fit_qr(FAKE, FAKE, 100, _lib.F32, ctypes.byref(o), FAKE, 1 << 30, FAKE, FAKE, None, None) == expect
+    assert L.fit_qr(FAKE, FAKE, 100, _lib.F32, ctypes.byref(_opt()), FAKE, 16, FAKE, FAKE, None, None) == _lib.WORKSPACE
+    assert L.fit_qr(FAKE, FAKE, 100, _lib.F32, ctypes.byref(_opt()), FAKE, 1 << 30, None, FAKE, None,
+                    None) == _lib.INVALID_ARG
+
+
 def test_fit_moments_workspace_too_small():
     L = _lib.load()
     o = _opt()

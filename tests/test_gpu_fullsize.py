@@ -12,6 +12,7 @@ benchmark uses (the default schedule), against the oracle.
 * 4,096 fits x 4,096 points, m = 2: forward, then the adjoint through autograd,
   checked on 64 sampled fits against the closed-form float64 adjoint and on 4 of
   them against central finite differences over all 8,192 inputs.
+* the streaming QR route on the cubic, <= 1e-9 normwise against the same oracle.
 * Chebyshev basis, n = 1e8 float32 points of the Runge function, m = 12, given
   and automatic range: the Chebyshev coefficients against the plain-C oracle's
   entrywise Gram route, <= 1e-9 normwise.
@@ -48,6 +49,18 @@ def test_cubic_full(cubic, precision, tol):
     assert e <= tol
     # the generating coefficients are recovered to the noise level
     assert np.max(np.abs(res.coef.cpu().numpy() - wl.true_coef)) < 1e-3
+
+
+def test_cubic_full_qr(cubic):
+    """The streaming QR route on the same 1e8 points (benchmark launch shape)."""
+    wl, x, y, ref = cubic
+    announce("cubic full, QR route")
+    res = lf.fit_qr(x, y, 3)
+    torch.cuda.synchronize()
+    assert int(res.status.cpu()[0]) == 0
+    e = normwise(res.coef.cpu().numpy(), ref["a"])
+    announce(f"  normwise error {e:.3e}")
+    assert e <= 1e-9
 
 
 @pytest.fixture(scope="module")

@@ -1,0 +1,131 @@
+"""GPU parity of the streaming QR route (fit_qr) against the oracle's
+Householder QR (the comparator of Sec. III, in its tall-skinny tree form).
+
+Both are backward-stable least-squares solvers, so their difference is
+bounded by the perturbation bound of the problem:
+    |db| / |b| <= C eps (kappa + kappa^2 eta),  eta = |r| / (|V| |b|),
+with kappa = cond(V) of the t-basis Vandermonde matrix, r the residual and
+C = 1e3 (row updates per lane, the merge tree and the change of basis).  The
+gate is that bound, and never looser than 1e-9 normwise where it is smaller.
+The same bound makes the QR route usable where the power sums are not: on
+[0, 1] without centring at m = 8, cond(V)^2 ~ 1e13.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import announce, normwise, to_dev, torch
+from oracle import c_oracle, fp64, qr
+from paper_1512_08017_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+lf = pytest.importorskip("paper_1512_08017_amd")
+EPS = np.finfo(np.float64).eps
+
+
+def qr_bound(x, y, m, c, s, b_ref):
+    V = qr.vandermonde(x, m, c, s)
+    sv = np.linalg.svd(V, compute_uv=False)
+    kappa = sv[0] / sv[-1]
+    r = np.asarray(y, np.float64) - V @ b_ref
+    eta = np.linalg.norm(r) / (sv[0] * np.linalg.norm(b_ref))
+    return max(1e-9, 1e3 * EPS * (kappa + kappa * kappa * eta)), kappa
+
+
+def run(x, y, m, **kw):
+    res = lf.fit_qr(to_dev(x), to_dev(y), m, **kw)
+    torch.cuda.synchronize()
+    return res
+
+
+@pytest.mark.parametrize("m", range(1, 9))
+def test_every_degree_given_range(m):
+    announce(f"qr m={m} given range")
+    wl = W.random_small(60_007, m, seed=800 + m, dtype=np.float64)
+    res = run(wl.x, wl.y, m, center=0.0, scale=1.0)
+    b_ref = qr.lstsq_qr(wl.x, wl.y, m, 0.0, 1.0)
+    tol, kappa = qr_bound(wl.x, wl.y, m, 0.0, 1.0, b_ref)
+    assert int(res.status.cpu()[0]) == 0
+    e = normwise(res.coef_t.cpu().numpy(), b_ref)
+    announce(f"  t-basis error {e:.2e} (gate {tol:.1e}, cond(V) {kappa:.1e})")
+    assert e <= tol
+    assert res.center == 0.0 and res.scale == 1.0
+
+
+@pytest.mark.parametrize("n,dtype", [(2, np.float64), (9, np.float64), (4097, np.float32), (1_000_003, np.float32)])
+def test_sizes_automatic_range(n, dtype):
+    m = 1 if n < 4 else 3
+    announce(f"qr n={n} {np.dtype(dtype).name} m={m}")
+    wl = W.random_small(n, m, seed=n, dtype=dtype, lo=-3.0, hi=5.0)
+    res = run(wl.x, wl.y, m)
+    ref = c_oracle.fit(wl.x, wl.y, m)
+    assert int(res.status.cpu()[0]) == 0
+    assert normwise(res.coef.cpu().numpy(), ref["a"]) <= 1e-9
+
+
+def test_ill_conditioned_where_power_sums_fail():
+    """x on [0, 1] with c = 0, s = 1 (no centring), m = 8, nearly noiseless
+    (cond(V) ~ 7e5, so cond(V)^2 eps ~ 1e-4): the QR route stays inside its
+    bound, the power sums lose about cond(V) times more."""
+    m = 8
+    wl = W.random_small(200_003, m, seed=900, dtype=np.float64, lo=0.0, hi=1.0, noise_sd=1e-9)
+    res = run(wl.x, wl.y, m, center=0.0, scale=1.0)
+    mom = lf.fit(to_dev(wl.x), to_dev(wl.y), m, center=0.0, scale=1.0)
+    torch.cuda.synchronize()
+    b_ref = qr.lstsq_qr(wl.x, wl.y, m, 0.0, 1.0)
+    tol, kappa = qr_bound(wl.x, wl.y, m, 0.0, 1.0, b_ref)
+    e_qr = normwise(res.coef_t.cpu().numpy(), b_ref)
+    e_mom = normwise(mom.coef_t.cpu().numpy(), b_ref)
+    announce(f"  cond(V) {kappa:.1e}: QR route {e_qr:.2e} (gate {tol:.1e}), power sums {e_mom:.2e}")
+    assert int(res.status.cpu()[0]) == 0
+    assert e_qr <= tol
+    assert e_qr * 100 < e_mom
+
+
+def test_residual_sum_of_squares():
+    m = 4
+    wl = W.random_small(123_457, m, seed=901, dtype=np.float32, lo=-2.0, hi=2.0)
+    x, y = to_dev(wl.x), to_dev(wl.y)
+    res = lf.fit_qr(x, y, m)
+    sse_pass, _ = lf.residuals(x, y, res)
+    torch.cuda.synchronize()
+    ref = c_oracle.fit(wl.x, wl.y, m)
+    sse_ref = fp64.sse(wl.x, wl.y, ref["a"])
+    assert abs(res.sse - sse_ref) <= 1e-9 * sse_ref
+    assert abs(float(sse_pass.cpu()[0]) - sse_ref) <= 1e-9 * sse_ref
+
+
+def test_degenerate_inputs():
+    x = to_dev(np.full(50, 0.25))
+    y = to_dev(np.linspace(0.0, 1.0, 50))
+    r = lf.fit_qr(x, y, 2)
+    torch.cuda.synchronize()
+    assert int(r.status.cpu()[0]) == 2 and np.isnan(r.coef.cpu().numpy()).all()
+    wl = W.random_small(1000, 3, seed=902, dtype=np.float64)
+    yb = wl.y.copy()
+    yb[500] = np.nan
+    r = lf.fit_qr(to_dev(wl.x), to_dev(yb), 3)
+    torch.cuda.synchronize()
+    assert int(r.status.cpu()[0]) == 3 and np.isnan(r.coef.cpu().numpy()).all()
+    # exactly determined: m + 1 distinct points are interpolated
+    xi = np.array([-1.0, -0.25, 0.5, 1.0])
+    yi = np.array([2.0, -1.0, 0.5, 3.0])
+    r = lf.fit_qr(to_dev(xi), to_dev(yi), 3, center=0.0, scale=1.0)
+    torch.cuda.synchronize()
+    a = r.coef.cpu().numpy()
+    assert int(r.status.cpu()[0]) == 0
+    assert np.max(np.abs(np.polynomial.polynomial.polyval(xi, a) - yi)) <= 1e-12
+
+
+def test_misaligned_and_reproducible():
+    wl = W.random_small(300_001, 3, seed=903, dtype=np.float32)
+    x, y = to_dev(wl.x), to_dev(wl.y)
+    ref = c_oracle.fit(wl.x[1:], wl.y[1:], 3)
+    r1 = lf.fit_qr(x[1:], y[1:], 3)
+    r2 = lf.fit_qr(x[1:], y[1:], 3)
+    r3 = lf.fit_qr(x[1:], y[:-1], 3)   # x and y misaligned differently: scalar loads
+    torch.cuda.synchronize()
+    assert normwise(r1.coef.cpu().numpy(), ref["a"]) <= 1e-9
+    assert np.array_equal(r1.coef.cpu().numpy(), r2.coef.cpu().numpy())
+    ref3 = c_oracle.fit(wl.x[1:], wl.y[:-1], 3)
+    assert normwise(r3.coef.cpu().numpy(), ref3["a"]) <= 1e-9

@@ -81,8 +81,9 @@ typedef enum { LSEFIT_PREC_F64 = 0, LSEFIT_PREC_F32C = 1 } lsefit_precision;
  *  LSEFIT_RANGE_GIVEN: c = center, s = scale for every fit (s > 0; a power
  *                      of two keeps t exact).
  *  LSEFIT_RANGE_AUTO:  monomial basis: from a sample of x (single fit: up to
- *                      256 evenly strided points; batched: up to 16 per fit,
- *                      first and last included): s = 2^ceil(log2(half-range))
+ *                      256 evenly strided points, first and last included;
+ *                      batched: the first 8 and the last 8 points of each
+ *                      fit, all of a shorter one): s = 2^ceil(log2(half-range))
  *                      and c = the mid-range rounded to a multiple of s/8,
  *                      replaced by 0 when it is below 2^-6 times the
  *                      half-range; c is then rounded to float32.  The result

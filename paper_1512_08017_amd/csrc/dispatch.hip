@@ -11,8 +11,8 @@ namespace lsefit {
 // tile table of a batch, in two launches.  Pass A: one thread per fit counts
 // its tiles (ceil(L / tile), every point of every fit is in exactly one tile),
 // sets its plan status (bad degree or segment -> INVALID_ARG, fewer than m+1
-// points -> SINGULAR), writes (c, s) (given, or from up to 16 evenly strided
-// samples of its x, first and last included, all loaded in one round), and
+// points -> SINGULAR), writes (c, s) (given, or from the first 8 and the last
+// 8 points of its x, all of a shorter fit, loaded in one round), and
 // scans the tile counts of its block.  Pass B adds the tile totals of the
 // blocks before it.  Integer sums: the result does not depend on the order.
 // ---------------------------------------------------------------------------
@@ -38,12 +38,19 @@ __global__ void __launch_bounds__(kPlanThreads)
         w.pstatus[f] = st;
         double cc = c, ss = s;
         if (!range_given) {
-            const int64_t K = L < kRangeBatchSamples ? L : kRangeBatchSamples;
+            // the first and the last kRangeBatchSamples / 2 points (all of a
+            // shorter fit): two cache lines per fit, and the exact extent of
+            // sorted data
+            constexpr int H = kRangeBatchSamples / 2;
             double v[kRangeBatchSamples];
 #pragma unroll
             for (int i = 0; i < kRangeBatchSamples; ++i) {
                 v[i] = NAN;
-                if (i < K) v[i] = (double)x[lo + (K == 1 ? 0 : (int64_t)i * (L - 1) / (K - 1))];
+                if (L <= kRangeBatchSamples) {
+                    if (i < L) v[i] = (double)x[lo + i];
+                } else {
+                    v[i] = (double)x[i < H ? lo + i : lo + L - kRangeBatchSamples + i];
+                }
             }
             double mn = INFINITY, mx = -INFINITY;
 #pragma unroll

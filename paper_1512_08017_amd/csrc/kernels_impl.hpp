@@ -511,10 +511,17 @@ __device__ inline void finish_single_block(const FitDesc& d, const Work& w, int6
     dispatch_degree<MAXM>(d.degree, body);
 }
 
-constexpr int kFinishThreads = 256;
+// The finish block has one thread per block partial (a multiple of 64, at
+// most 1024), so each thread waits for one round trip to memory only.
+constexpr int kFinishMaxThreads = 1024;
+
+__host__ __device__ inline int finish_threads(int64_t G) {
+    const int64_t t = (G + kWave - 1) / kWave * kWave;
+    return (int)(t < kWave ? kWave : (t > kFinishMaxThreads ? kFinishMaxThreads : t));
+}
 
 template <int MAXM>
-__global__ void __launch_bounds__(kFinishThreads) k_finish_single(FitDesc d, Work w, int64_t G, Finish fz) {
+__global__ void __launch_bounds__(kFinishMaxThreads) k_finish_single(FitDesc d, Work w, int64_t G, Finish fz) {
     finish_single_block<MAXM>(d, w, G, fz);
 }
 
@@ -1035,7 +1042,7 @@ hipError_t Launchers<MAXM>::combine(const FitDesc& d, const Work& w, const Launc
 
 template <int MAXM>
 hipError_t Launchers<MAXM>::finish_single(const FitDesc& d, const Work& w, int64_t G, const Finish& fz, hipStream_t st) {
-    hipLaunchKernelGGL(k_finish_single<MAXM>, dim3(1), dim3(kFinishThreads), 0, st, d, w, G, fz);
+    hipLaunchKernelGGL(k_finish_single<MAXM>, dim3(1), dim3(finish_threads(G)), 0, st, d, w, G, fz);
     return hipGetLastError();
 }
 

@@ -257,9 +257,22 @@ def cpu_baseline(x_np, y_np, degree, target_s):
         if el >= target_s or reps >= 1000:
             break
     used = c_oracle.max_threads()
+    # one thread (the paper's sequential execution), on a bounded prefix of the same points
+    n1 = min(x_np.shape[0], 20_000_000)
+    t1 = time.perf_counter()
+    reps1 = 0
+    while True:
+        c_oracle.fit(x_np[:n1], y_np[:n1], degree, threads=1)
+        reps1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= target_s / 3 or reps1 >= 100:
+            break
+    c_oracle.fit(x_np[:1000], y_np[:1000], degree, threads=threads)   # back to all threads
     return {"value": x_np.shape[0] * reps / el, "unit": "points/s", "cores": int(used), "kind": "oracle",
             "sample": f"{reps} full pass(es) of the plain-C float64 oracle over the same {x_np.shape[0]:,} points "
-                      f"(compensated sums + partial-pivoting elimination), {el:.1f} s on {used} host threads"}, res
+                      f"(compensated sums + partial-pivoting elimination), {el:.1f} s on {used} host threads",
+            "single_thread": {"value": n1 * reps1 / el1, "unit": "points/s",
+                              "sample": f"{reps1} pass(es) over the first {n1:,} points on 1 thread, {el1:.1f} s"}}, res
 
 
 # ---------------------------------------------------------------------------
@@ -282,6 +295,45 @@ def _time(fn, steps, warmup):
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / steps
+
+
+MALL_FLUSH_BYTES = 1 << 30   # > the 256 MB Infinity Cache
+
+
+def _cold_warm(fn, reps):
+    """Median and minimum per-call time of fn, warm (back to back) and cold
+    (after writing a 1 GiB scratch buffer, which evicts the 256 MB MALL), each
+    call between its own pair of events on the current stream."""
+    import torch
+    flush = torch.empty(MALL_FLUSH_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    out = {}
+    for kind in ("warm", "cold"):
+        ts = []
+        for i in range(reps):
+            if kind == "cold":
+                flush.fill_(float(i))
+            a, b = _events()
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        ts.sort()
+        out[f"{kind}_median_ms"] = ts[len(ts) // 2]
+        out[f"{kind}_min_ms"] = ts[0]
+    del flush
+    return out
+
+
+def measured_ceiling_gbps():
+    """Best read bandwidth of the project's read probe, from its stored summary (or None)."""
+    path = os.path.join(PROFILES, "read_probe_ceiling.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("best:"):
+            return float(line.split()[1])
+    return None
 
 
 def _kernel_avgs():
@@ -411,6 +463,7 @@ def bench_grad(args):
     bwd_bytes = 16.0 * P
     return {"workload": f"grad_batch: {bf.batch} fits x 4096 float32 points, m=2, forward + adjoint",
             "points": P, "ms_per_step": ms, "points_per_s": P / (ms * 1e-3),
+            "per_call": _cold_warm(fwd_bwd, 20),
             "step_gbps": (fwd_bytes + bwd_bytes) / (ms * 1e-3) / 1e9, "kernels": kern,
             "moments_gbps": fwd_bytes / (kern["moments"]["avg_ms"] * 1e-3) / 1e9,
             "adjoint_gbps": bwd_bytes / (kern["adjoint"]["avg_ms"] * 1e-3) / 1e9,
@@ -433,7 +486,7 @@ def bench_single_workload(args, name):
         ms, wall, ms_inst, kern = time_steps(r, args.steps, args.warmup)
         out[prec] = {"ms_per_step": ms, "points_per_s": wl.n / (ms * 1e-3), "kernels": kern,
                      "moments_gbps": 2 * esize * wl.n / (kern["moments"]["avg_ms"] * 1e-3) / 1e9,
-                     "status": int(r.status.cpu()[0])}
+                     "status": int(r.status.cpu()[0]), "per_call": _cold_warm(r.step, 20)}
     return out
 
 
@@ -584,7 +637,8 @@ def main():
         forms[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall_ms, "instrumented_ms_per_step": ms_inst,
                        "points_per_s": args.n / (ms * 1e-3),
                        "step_gbps": (8.0 * args.n * (2 if prec == "f32c" else 1)) / (ms * 1e-3) / 1e9,
-                       "kernels": kern, "status": st, "coef": r.coef[: args.degree + 1].cpu().numpy()}
+                       "kernels": kern, "status": st, "coef": r.coef[: args.degree + 1].cpu().numpy(),
+                       "per_call": _cold_warm(r.step, 20)}
         log(f"{prec}: {ms:.4f} ms/step, {forms[prec]['points_per_s']:.3e} points/s, kernels {kern}")
 
     cpu = None
@@ -612,11 +666,14 @@ def main():
     if mk:
         achieved = bytes_per_launch / (mk["avg_ms"] * 1e-3) / 1e9
         traffic = traffic_bytes("moments")
+        ceiling = measured_ceiling_gbps()
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 4),
                 "kernel": "k_moments", "avg_launch_ms": round(mk["avg_ms"], 5),
-                "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+                "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                "measured_read_ceiling": ceiling,
+                "frac_of_measured_ceiling": None if ceiling is None else round(achieved / ceiling, 4)}
     line = {
         "metric": METRIC,
         "value": round(hf["points_per_s"], 1),

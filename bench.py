@@ -361,7 +361,8 @@ def _instrumented(fn, steps):
 def bench_ragged(args):
     """65,536 ragged fits (log-uniform lengths in [16, 65536], degree 1..3): one
     persistent batched launch sequence (tuned plan, graph replay) against a
-    sequence of single-fit calls, one per fit, on the same GPU."""
+    sequence of single-fit calls, one per fit, on the same GPU; and the
+    streaming QR route over the same batch."""
     import numpy as np
     import torch
     import paper_1512_08017_amd as lf
@@ -392,6 +393,18 @@ def bench_ragged(args):
                      "moments_gbps": 8.0 * P / (kern["moments"]["avg_ms"] * 1e-3) / 1e9}
         plan.close()
         log(f"ragged {prec}: {out[prec]}")
+    # the streaming QR route over the same batch (default schedule, eager)
+    coef = torch.zeros(bf.batch, 4, dtype=torch.float64, device=dev)
+    status = torch.zeros(bf.batch, dtype=torch.int32, device=dev)
+    sse = torch.zeros(bf.batch, dtype=torch.float64, device=dev)
+    wsq = torch.zeros(api.workspace_bytes(bf.batch, 3), dtype=torch.uint8, device=dev)
+    qr_fn = lambda: lf.fit_qr_batched(x, y, off, dg, 3, ws=wsq, out=(coef, status, sse))
+    qr_ms = _time(qr_fn, args.steps, args.warmup)
+    kern = _instrumented(qr_fn, args.steps)
+    out["qr"] = {"eager_default_ms": qr_ms, "points_per_s": P / (qr_ms * 1e-3), "kernels": kern,
+                 "all_ok": bool((status.cpu().numpy() == 0).all()),
+                 "moments_gbps": 8.0 * P / (kern["moments"]["avg_ms"] * 1e-3) / 1e9}
+    log(f"ragged qr: {out['qr']}")
     # per-fit baseline: one fit_single call per fit on the same stream
     L = _lib.load()
     nfit = min(args.per_fit_limit, bf.batch)

@@ -222,6 +222,20 @@ lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype d
 lsefit_status fit_qr(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
                      void* ws, size_t ws_bytes, double* coef, int32_t* status, double* info, void* stream);
 
+/* fit_qr for B independent fits over CSR segments (layout as fit_batched):
+ * every wave factors its segment of each fit it streams, and one thread per
+ * fit merges the fit's factors in wave order and solves.
+ *  coef:     output, device float64 [B * coef_stride]: a_0..a_m of fit f
+ *  status:   output, device int32 [B]
+ *  sse:      optional output (NULL to skip), device float64 [B]: the residual
+ *            sum of squares of each fit (NaN unless OK)
+ *  ws:       >= lsefit_workspace_bytes(B, opt->degree, NULL) bytes (the
+ *            default schedule; no plan)
+ * opt, errors and limits as fit_qr; fit_residuals may follow on the same ws. */
+lsefit_status fit_qr_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
+                             int64_t batch, lsefit_dtype dt, const lsefit_options* opt, void* ws, size_t ws_bytes,
+                             double* coef, int32_t coef_stride, int32_t* status, double* sse, void* stream);
+
 /* B independent fits over CSR segments: fit f owns points offsets[f] ..
  * offsets[f+1]-1 of x and y (Sec. II applied to each segment).
  *  offsets:   device int64 [B+1], non-decreasing, offsets[0] = 0

@@ -5,7 +5,7 @@ loaded on the first call and its absence is an error (there is no CPU path).
 """
 from __future__ import annotations
 
-__all__ = ["fit", "fit_split", "fit_moments", "fit_solve", "fit_qr", "fit_batched", "fit_backward", "lsefit", "LseFit",
+__all__ = ["fit", "fit_split", "fit_moments", "fit_solve", "fit_qr", "fit_qr_batched", "fit_batched", "fit_backward", "lsefit", "LseFit",
            "Plan", "FitResult", "QRResult", "residuals", "residuals_batched", "default_schedule", "set_default_schedule",
            "workspace_bytes", "device_cus", "LsefitError"]
 

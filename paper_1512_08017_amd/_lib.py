@@ -22,7 +22,8 @@ STATUS_NAMES = {OK: "ok", INVALID_ARG: "invalid_arg", SINGULAR: "singular", NONF
 # C-ABI symbols the library must export (one per declaration in include/lsefit.h)
 EXPORTS = (
     "lsefit_workspace_bytes", "lsefit_default_schedule", "lsefit_set_default_schedule",
-    "fit_moments", "fit_solve", "fit_single", "fit_qr", "fit_batched", "fit_backward", "fit_residuals",
+    "fit_moments", "fit_solve", "fit_single", "fit_qr", "fit_qr_batched", "fit_batched", "fit_backward",
+    "fit_residuals",
     "fit_plan_create", "fit_plan_tune", "fit_plan_set_schedule", "fit_plan_get_schedule",
     "fit_plan_set_graph", "fit_plan_destroy", "lsefit_status_string", "lsefit_device_cus",
     "lsefit_timing_enable", "lsefit_timing_reset", "lsefit_timing_read", "lsefit_read_probe",
@@ -73,6 +74,7 @@ def load():
     L.fit_solve.argtypes = [vp, OptP, vp, vp, i64, i32, vp, sz, vp, vp, vp]
     L.fit_single.argtypes = [vp, vp, i64, i32, OptP, vp, sz, vp, vp, vp, vp]
     L.fit_qr.argtypes = [vp, vp, i64, i32, OptP, vp, sz, vp, vp, vp, vp]
+    L.fit_qr_batched.argtypes = [vp, vp, vp, vp, i64, i32, OptP, vp, sz, vp, i32, vp, vp, vp]
     L.fit_batched.argtypes = [vp, vp, vp, vp, i64, i32, OptP, vp, vp, sz, vp, i32, vp, vp]
     L.fit_backward.argtypes = [vp, vp, vp, vp, i64, i32, OptP, vp, vp, sz, vp, i32, vp, vp, vp]
     L.fit_residuals.argtypes = [vp, vp, vp, vp, i64, i64, i32, OptP, vp, vp, sz, vp, vp, vp]
@@ -90,7 +92,7 @@ def load():
     L.lsefit_read_probe.argtypes = [vp, vp, i64, SchP, i32, i32, vp, sz, vp]
     L.lsefit_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     for name in ("lsefit_default_schedule", "lsefit_set_default_schedule", "fit_moments", "fit_solve", "fit_single",
-                 "fit_qr", "fit_residuals",
+                 "fit_qr", "fit_qr_batched", "fit_residuals",
                  "fit_batched", "fit_backward", "fit_plan_create", "fit_plan_tune", "fit_plan_set_schedule",
                  "fit_plan_get_schedule", "fit_plan_set_graph", "lsefit_timing_enable", "lsefit_timing_reset",
                  "lsefit_timing_read", "lsefit_read_probe"):

@@ -214,6 +214,30 @@ def fit_qr(x, y, degree: int, center=None, scale=None, ws=None) -> QRResult:
     return QRResult(coef[:m1], coef[m1:], status, info, ws, o)
 
 
+def fit_qr_batched(x, y, offsets, degrees, max_degree: int, center=None, scale=None, coef_stride=None, ws=None,
+                   out=None):
+    """Independent fits over CSR segments through the streaming QR route;
+    returns (coef [B, stride], status [B], sse [B], ws)."""
+    _check_batch(x, y, offsets, degrees)
+    L = _lib.load()
+    B = degrees.numel()
+    o = options(max_degree, "f64", 0, center, scale)
+    stride = coef_stride or (max_degree + 1)
+    if out is None:
+        coef = torch.zeros((B, stride), dtype=torch.float64, device=x.device)
+        status = torch.empty(B, dtype=torch.int32, device=x.device)
+        sse = torch.empty(B, dtype=torch.float64, device=x.device)
+    else:
+        coef, status, sse = out
+    nbytes = workspace_bytes(max(B, 1), max_degree)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
+    check(L.fit_qr_batched(_ptr(x), _ptr(y), _ptr(offsets), _ptr(degrees), B, _DT[x.dtype], ctypes.byref(o),
+                           _ptr(ws), ws.numel(), _ptr(coef), stride, _ptr(status), _ptr(sse), _stream(x.device)),
+          "fit_qr_batched")
+    return coef, status, sse, ws
+
+
 def fit_split(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None,
               solver: str = "gepp", basis: str = "monomial") -> FitResult:
     """The same fit through the two-call form (fit_moments, then fit_solve)."""

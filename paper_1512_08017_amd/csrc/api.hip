@@ -40,8 +40,8 @@ Layout layout(int64_t B, int maxM, int64_t W) {
     L.rec = off;
     off = align_up(off + sizeof(double) * (size_t)B * rec_len(maxM));
     L.part = off;
-    // a single fit may also hold per-block QR factors (fit_qr, degree <= LSEFIT_MAX_DEGREE)
-    const int per = (B == 1 && maxM <= LSEFIT_MAX_DEGREE && qr_len(maxM) > nacc(maxM)) ? qr_len(maxM) : nacc(maxM);
+    // the slots may also hold streaming QR factors (fit_qr, degree <= LSEFIT_MAX_DEGREE)
+    const int per = (maxM <= LSEFIT_MAX_DEGREE && qr_len(maxM) > nacc(maxM)) ? qr_len(maxM) : nacc(maxM);
     off = align_up(off + sizeof(double) * (size_t)(W + B) * per);
     L.block_tot = off;
     off = align_up(off + sizeof(int64_t) * (size_t)((B + kPlanThreads - 1) / kPlanThreads));
@@ -471,6 +471,31 @@ lsefit_status fit_qr(const void* x, const void* y, int64_t n, lsefit_dtype dt, c
     LSEFIT_TRY(timed(kTimeMoments, st, [&] { return launch_qr_single(d, w, dt, x, y, L, mis, ra, st); }));
     LSEFIT_TRY(timed(kTimeCombine, st,
                      [&] { return launch_qr_finish(d, w, grid_blocks(L), coef, status, info, st); }));
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_qr_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
+                             int64_t batch, lsefit_dtype dt, const lsefit_options* opt, void* ws, size_t ws_bytes,
+                             double* coef, int32_t coef_stride, int32_t* status, double* sse, void* stream) {
+    if (batch < 0 || !opts_ok(opt, dt, true)) return LSEFIT_ERR_INVALID_ARG;
+    if (batch == 0) return LSEFIT_OK;
+    if (!x || !y || !offsets || !degrees || !coef || !status) return LSEFIT_ERR_INVALID_ARG;
+    if (coef_stride < opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
+    if (opt->precision != LSEFIT_PREC_F64 || chebyshev(opt)) return LSEFIT_ERR_UNSUPPORTED;
+    const lsefit_schedule sched = current_default();
+    const Launch L = to_launch(sched);
+    const Layout lay = layout(batch, opt->degree, L.waves);
+    if (!ws || ws_bytes < lay.total) return LSEFIT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const FitDesc d{offsets, degrees, 0, batch, opt->degree};
+    const Work w = carve(ws, lay);
+    const bool given = opt->range_mode == LSEFIT_RANGE_GIVEN;
+    const int mis = common_mis(dt, {x, y});
+    LSEFIT_TRY(launch_plan(d, w, opt->degree, L.tile, given, opt->center, opt->scale, dt, x, w.block_tot, st));
+    LSEFIT_TRY(timed(kTimeMoments, st, [&] { return launch_qr_batch(d, w, opt->degree, dt, x, y, L, mis, st); }));
+    LSEFIT_TRY(timed(kTimeCombine, st, [&] {
+        return launch_qr_combine(d, w, opt->degree, L.waves, coef, coef_stride, status, sse, st);
+    }));
     return LSEFIT_OK;
 }
 

@@ -1,4 +1,5 @@
-// Host-side launchers of the streaming and solve kernels (defined in kernels.hip).
+// Host-side launchers of the streaming and solve kernels (monomial basis: kernels_m1..8.hip through
+// dispatch.hip; Chebyshev basis: cheb.hip; streaming QR: tsqr.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -104,5 +105,11 @@ hipError_t launch_qr_single(const FitDesc& d, const Work& w, int dtype, const vo
                             const Launch& L, int mis, const RangeArg& ra, hipStream_t st);
 hipError_t launch_qr_finish(const FitDesc& d, const Work& w, int64_t G, double* coef, int32_t* status, double* info,
                             hipStream_t st);
+// Streaming QR of a batch: per-(wave, fit) factors into w.part (after the tile
+// table), then one thread per fit merges, solves and writes a, status, sse.
+hipError_t launch_qr_batch(const FitDesc& d, const Work& w, int maxm, int dtype, const void* x, const void* y,
+                           const Launch& L, int mis, hipStream_t st);
+hipError_t launch_qr_combine(const FitDesc& d, const Work& w, int maxm, int64_t W, double* coef, int32_t coef_stride,
+                             int32_t* status, double* sse, hipStream_t st);
 
 }  // namespace lsefit

@@ -223,33 +223,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(qr_wav
     block_merge_store<M + 1>(w, acc.q);
 }
 
-// Merge the G block factors (thread t takes blocks t, t + 256, ..., in order;
-// then lanes, then waves, in order), solve Rb b = th, and write a_0..a_m,
-// b_0..b_m, the status and, if asked, info = [c, s, e].  Singular when some
-// d_i <= 2^-80 max_k d_k (|R_ii| <= 2^-40 max_k |R_kk|), or fewer than m+1 points.
-template <int M>
-__global__ void __launch_bounds__(256)
-    k_qr_finish(FitDesc d, Work w, int64_t G, int maxm, double* __restrict__ coef, int32_t* __restrict__ status,
-                double* __restrict__ info) {
-    constexpr int N = M + 1;
-    constexpr int LEN = GivensQR<N>::LEN;
-    __shared__ double sh[4][LEN];
-    GivensQR<N> q;
-    q.zero();
-    for (int64_t g = threadIdx.x; g < G; g += blockDim.x) q.merge([&](int j) { return w.part[(int64_t)j * G + g]; });
-    wave_merge(q);
-    const int wid = wave_id_in_block();
-    if (lane_id() == 0 && wid > 0) {
-#pragma unroll
-        for (int j = 0; j < LEN; ++j) sh[wid][j] = q.flat(j);
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    const int nw = blockDim.x / kWave;
-    for (int v = 1; v < nw; ++v) q.merge([&](int j) { return sh[v][j]; });
-    double* r = w.rec;
-    const double c = r[0], s = r[1];
-    int st = d.n_single < N ? LSEFIT_ERR_SINGULAR : LSEFIT_OK;
+// Solve Rb b = th for a merged factor of npts rows and write a_0..a_m to out
+// (then b_0..b_m after them with write_b) and b to the record; returns the
+// status.  Singular when fewer than m+1 points or some d_i <= 2^-80 max_k d_k
+// (|R_ii| <= 2^-40 max_k |R_kk|); non-finite when any entry is.
+template <int N>
+__device__ inline int qr_solve_store(const GivensQR<N>& q, int64_t npts, double c, double s, double* rec_b,
+                                     double* out, bool write_b) {
+    int st = npts < N ? LSEFIT_ERR_SINGULAR : LSEFIT_OK;
     bool finite = isfinite(q.e);
     double dmax = 0.0;
 #pragma unroll
@@ -284,17 +265,112 @@ __global__ void __launch_bounds__(256)
     }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        coef[k] = a[k];
-        coef[N + k] = b[k];
-        r[rec_b(maxm) + k] = b[k];
+        out[k] = a[k];
+        if (write_b) out[N + k] = b[k];
+        rec_b[k] = b[k];
     }
+    return st;
+}
+
+// Merge the G block factors (thread t takes blocks t, t + 256, ..., in order;
+// then lanes, then waves, in order), solve, and write [a | b], the status and,
+// if asked, info = [c, s, e].
+template <int M>
+__global__ void __launch_bounds__(256)
+    k_qr_finish(FitDesc d, Work w, int64_t G, int maxm, double* __restrict__ coef, int32_t* __restrict__ status,
+                double* __restrict__ info) {
+    constexpr int N = M + 1;
+    constexpr int LEN = GivensQR<N>::LEN;
+    __shared__ double sh[4][LEN];
+    GivensQR<N> q;
+    q.zero();
+    for (int64_t g = threadIdx.x; g < G; g += blockDim.x) q.merge([&](int j) { return w.part[(int64_t)j * G + g]; });
+    wave_merge(q);
+    const int wid = wave_id_in_block();
+    if (lane_id() == 0 && wid > 0) {
+#pragma unroll
+        for (int j = 0; j < LEN; ++j) sh[wid][j] = q.flat(j);
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int nw = blockDim.x / kWave;
+    for (int v = 1; v < nw; ++v) q.merge([&](int j) { return sh[v][j]; });
+    double* r = w.rec;
+    const int st = qr_solve_store<N>(q, d.n_single, r[0], r[1], r + rec_b(maxm), coef, true);
     w.pstatus[0] = st;
     status[0] = st;
     if (info) {
-        info[0] = c;
-        info[1] = s;
+        info[0] = r[0];
+        info[1] = r[1];
         info[2] = st == LSEFIT_OK ? q.e : NAN;
     }
+}
+
+// ---------------------------------------------------------------------------
+// batches: each wave factors its segment of every fit it streams, merges the
+// factor to lane 0 and writes it to the fit's slot w + f (qr_len(maxm)
+// doubles); one thread per fit then merges the fit's slots in wave order
+// ---------------------------------------------------------------------------
+template <typename In, int MAXC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(qr_waves_per_eu(MAXC))))
+    k_qr_batch(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t tile, int64_t W,
+               int mis, int maxm) {
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    const int stride = qr_len(maxm);
+    const int rl = rec_len(maxm);
+    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
+        if (w.pstatus[f] != LSEFIT_OK) return;
+        const double c = w.rec[f * rl + 0];
+        const double inv_s = 1.0 / w.rec[f * rl + 1];
+        double* __restrict__ out = w.part + slot * stride;
+        auto body = [&]<int M>() {
+            AccQR<M> acc;
+            acc.init(c, inv_s);
+            stream_segment<1>(x, y, lo, hi, mis, acc);
+            wave_merge(acc.q);
+            if (lane_id() == 0) {
+#pragma unroll
+                for (int j = 0; j < GivensQR<M + 1>::LEN; ++j) out[j] = acc.q.flat(j);
+            }
+        };
+        dispatch_degree<MAXC>(fit_deg(d, f), body);
+    });
+}
+
+template <int MAXC>
+__global__ void __launch_bounds__(256)
+    k_qr_combine(FitDesc d, Work w, int64_t W, int maxm, double* __restrict__ coef, int32_t coef_stride,
+                 int32_t* __restrict__ status, double* __restrict__ sse) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= d.batch) return;
+    double* out = coef + f * (int64_t)coef_stride;
+    const int m = fit_deg(d, f);
+    const int pst = w.pstatus[f];
+    if (pst != LSEFIT_OK) {
+        const int n = (m >= 1 && m <= maxm) ? m + 1 : coef_stride;
+        for (int k = 0; k < n; ++k) out[k] = NAN;
+        status[f] = pst;
+        if (sse) sse[f] = NAN;
+        return;
+    }
+    const int stride = qr_len(maxm);
+    const int64_t NT = w.tile_start[d.batch];
+    const int64_t w0 = wave_of_tile(w.tile_start[f], NT, W), w1 = wave_of_tile(w.tile_start[f + 1] - 1, NT, W);
+    double* r = w.rec + f * rec_len(maxm);
+    auto body = [&]<int M>() {
+        GivensQR<M + 1> q;
+        q.zero();
+        for (int64_t wv = w0; wv <= w1; ++wv) {
+            if (!wave_owns_tiles(wv, NT, W)) continue;
+            const double* p = w.part + (wv + f) * stride;
+            q.merge([&](int j) { return p[j]; });
+        }
+        const int st = qr_solve_store<M + 1>(q, fit_hi(d, f) - fit_lo(d, f), r[0], r[1], r + rec_b(maxm), out, false);
+        w.pstatus[f] = st;
+        status[f] = st;
+        if (sse) sse[f] = st == LSEFIT_OK ? q.e : NAN;
+    };
+    dispatch_degree<MAXC>(m, body);
 }
 
 hipError_t launch_qr_single(const FitDesc& d, const Work& w, int dtype, const void* x, const void* y,
@@ -309,6 +385,34 @@ hipError_t launch_qr_single(const FitDesc& d, const Work& w, int dtype, const vo
                                (const double*)y, L.waves, mis, ra);
     };
     dispatch_degree<LSEFIT_MAX_DEGREE>(d.degree, body);
+    return hipGetLastError();
+}
+
+hipError_t launch_qr_batch(const FitDesc& d, const Work& w, int maxm, int dtype, const void* x, const void* y,
+                           const Launch& L, int mis, hipStream_t st) {
+    const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
+    auto go = [&]<int MAXC>() {
+        if (dtype == LSEFIT_F32)
+            hipLaunchKernelGGL((k_qr_batch<float, MAXC>), grid, block, 0, st, d, w, (const float*)x, (const float*)y,
+                               L.tile, L.waves, mis, maxm);
+        else
+            hipLaunchKernelGGL((k_qr_batch<double, MAXC>), grid, block, 0, st, d, w, (const double*)x,
+                               (const double*)y, L.tile, L.waves, mis, maxm);
+    };
+    if (maxm <= 4) go.template operator()<4>();
+    else go.template operator()<LSEFIT_MAX_DEGREE>();
+    return hipGetLastError();
+}
+
+hipError_t launch_qr_combine(const FitDesc& d, const Work& w, int maxm, int64_t W, double* coef, int32_t coef_stride,
+                             int32_t* status, double* sse, hipStream_t st) {
+    const int64_t blocks = (d.batch + 255) / 256;
+    if (maxm <= 4)
+        hipLaunchKernelGGL(k_qr_combine<4>, dim3(blocks), dim3(256), 0, st, d, w, W, maxm, coef, coef_stride, status,
+                           sse);
+    else
+        hipLaunchKernelGGL(k_qr_combine<LSEFIT_MAX_DEGREE>, dim3(blocks), dim3(256), 0, st, d, w, W, maxm, coef,
+                           coef_stride, status, sse);
     return hipGetLastError();
 }
 

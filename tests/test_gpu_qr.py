@@ -129,3 +129,71 @@ def test_misaligned_and_reproducible():
     assert np.array_equal(r1.coef.cpu().numpy(), r2.coef.cpu().numpy())
     ref3 = c_oracle.fit(wl.x[1:], wl.y[:-1], 3)
     assert normwise(r3.coef.cpu().numpy(), ref3["a"]) <= 1e-9
+
+
+# ---------------------------------------------------------------------------
+# batches (fit_qr_batched)
+# ---------------------------------------------------------------------------
+RAGGED = [0, 1, 2, 5, 9, 17, 63, 64, 65, 255, 257, 1000, 4097, 70_001, 0, 30_000, 12_345, 40]
+
+
+@pytest.mark.parametrize("maxdeg,dtype", [(3, np.float32), (8, np.float64), (6, np.float32)])
+def test_batched_given_range_against_householder(maxdeg, dtype):
+    """t = x / 8 for every fit (given range), so b_k = 8^k a_k exactly; each
+    fit's b against the oracle's Householder QR, gated by its own bound."""
+    announce(f"qr batched maxdeg={maxdeg} {np.dtype(dtype).name}")
+    rng = np.random.default_rng(20 + maxdeg)
+    deg = rng.integers(1, maxdeg + 1, len(RAGGED)).astype(np.int32)
+    bf = W.random_batch(RAGGED, deg, seed=21 + maxdeg, lo=-5.0, hi=5.0, dtype=dtype)
+    coef, status, sse, _ = lf.fit_qr_batched(to_dev(bf.x), to_dev(bf.y), to_dev(bf.offsets), to_dev(bf.degrees),
+                                             maxdeg, center=0.0, scale=8.0)
+    torch.cuda.synchronize()
+    coef, status, sse = coef.cpu().numpy(), status.cpu().numpy(), sse.cpu().numpy()
+    for f in range(bf.batch):
+        m = int(bf.degrees[f])
+        lo, hi = bf.offsets[f], bf.offsets[f + 1]
+        if hi - lo < m + 1:
+            assert status[f] == 2 and np.isnan(coef[f, : m + 1]).all() and np.isnan(sse[f])
+            continue
+        assert status[f] == 0, (f, status[f])
+        xf, yf = bf.x[lo:hi].astype(np.float64), bf.y[lo:hi].astype(np.float64)
+        b_ref = qr.lstsq_qr(xf, yf, m, 0.0, 8.0)
+        tol, kappa = qr_bound(xf, yf, m, 0.0, 8.0, b_ref)
+        b_gpu = coef[f, : m + 1] * 8.0 ** np.arange(m + 1)
+        e = normwise(b_gpu, b_ref)
+        assert e <= tol, (f, m, hi - lo, e, tol, kappa)
+        r = yf - qr.vandermonde(xf, m, 0.0, 8.0) @ b_ref
+        ssr = float(r @ r)
+        assert abs(sse[f] - ssr) <= 1e-9 * max(ssr, 1e-300) + 1e3 * EPS * float(yf @ yf), (f, sse[f], ssr)
+
+
+def test_batched_automatic_range_and_residual_pass():
+    rng = np.random.default_rng(30)
+    lengths = rng.integers(50, 20_000, 300)
+    deg = rng.integers(1, 4, 300).astype(np.int32)
+    bf = W.random_batch(lengths, deg, seed=31, lo=-5.0, hi=5.0)
+    x, y, off, dg = to_dev(bf.x), to_dev(bf.y), to_dev(bf.offsets), to_dev(bf.degrees)
+    coef, status, sse, ws = lf.fit_qr_batched(x, y, off, dg, 3)
+    sse_pass, _ = lf.residuals_batched(x, y, off, dg, 3, ws=ws)
+    torch.cuda.synchronize()
+    ref, rst = c_oracle.fit_batched(bf.x, bf.y, bf.offsets, bf.degrees, stride=4)
+    coef, status, sse, sse_pass = coef.cpu().numpy(), status.cpu().numpy(), sse.cpu().numpy(), sse_pass.cpu().numpy()
+    assert (status == 0).all() and (rst == 0).all()
+    for f in range(bf.batch):
+        m = int(bf.degrees[f])
+        assert normwise(coef[f, : m + 1], ref[f, : m + 1]) <= 1e-9
+    assert np.max(np.abs(sse - sse_pass) / sse_pass) <= 1e-9
+
+
+def test_batched_degenerate_fits_stay_local():
+    bf = W.random_batch([100, 100, 100, 100], [3, 0, 9, 2], seed=32)
+    y = bf.y.copy()
+    y[350] = np.nan                      # inside the fourth fit
+    coef, status, sse, _ = lf.fit_qr_batched(to_dev(bf.x), to_dev(y), to_dev(bf.offsets), to_dev(bf.degrees), 8,
+                                             coef_stride=9)
+    torch.cuda.synchronize()
+    coef, status = coef.cpu().numpy(), status.cpu().numpy()
+    assert list(status) == [0, 1, 1, 3]
+    assert np.isnan(coef[1]).all() and np.isnan(coef[2]).all() and np.isnan(coef[3, :3]).all()
+    ref = c_oracle.fit(bf.x[:100], bf.y[:100], 3)
+    assert normwise(coef[0, :4], ref["a"]) <= 1e-9

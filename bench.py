@@ -106,11 +106,11 @@ def summarize_pmc(fetch_dir, write_dir, out_path=None):
     lines = ["# HBM traffic of the power-sum kernel (k_moments) and the refinement kernel (k_refine)",
              "# workload: cubic fit, n = 1e8 float32 points (800,000,000 algorithmic bytes per pass)",
              "# commands (two runs, one counter each):",
-             "#   rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o run --output-format csv -- "
+             f"#   rocprofv3 --pmc FETCH_SIZE -d {fetch_dir} -o run --output-format csv -- "
              "python3 bench.py --pmc-probe",
-             "#   rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o run --output-format csv -- "
+             f"#   rocprofv3 --pmc WRITE_SIZE -d {write_dir} -o run --output-format csv -- "
              "python3 bench.py --pmc-probe",
-             "#   python3 bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write "
+             f"#   python3 bench.py --summarize-pmc {fetch_dir} {write_dir} "
              "--out profiles/moments_cubic_f32_traffic.txt",
              f"# {COPY_BYTES_NOTE}",
              f"kernel_hash {kernel_hash()}"]

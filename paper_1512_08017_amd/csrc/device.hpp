@@ -169,6 +169,68 @@ __device__ inline void walk_segments(const FitDesc& d, const int64_t* __restrict
     }
 }
 
+// walk_segments for the passes that need only a fit's range record, status
+// and degree: the next fit's metadata is loaded before the current segment is
+// streamed, so that its latency overlaps the segment's loads instead of
+// following them.  fn(f, lo, hi, slot, meta).
+struct SegMeta {
+    int64_t fs, fe, lo, hi;   // tiles and points of the fit
+    double c, s;              // its range record
+    int st, deg;              // its plan status and degree
+};
+
+__device__ inline SegMeta load_meta(const FitDesc& d, const int64_t* __restrict__ tile_start,
+                                    const int32_t* __restrict__ pstatus, const double* __restrict__ rec, int rl,
+                                    int64_t f) {
+    SegMeta m;
+    m.fs = tile_start[f];
+    m.fe = tile_start[f + 1];
+    m.lo = fit_lo(d, f);
+    m.hi = fit_hi(d, f);
+    m.st = pstatus[f];
+    m.deg = fit_deg(d, f);
+    m.c = rec[f * rl];
+    m.s = rec[f * rl + 1];
+    return m;
+}
+
+template <class Fn>
+__device__ inline void walk_segments_ahead(const FitDesc& d, const int64_t* __restrict__ tile_start,
+                                           const int32_t* __restrict__ pstatus, const double* __restrict__ rec,
+                                           int rl, int64_t tile, int64_t wave, int64_t W, Fn&& fn) {
+    const int64_t NT = tile_start[d.batch];
+    const int64_t t0 = wave * NT / W;
+    const int64_t t1 = (wave + 1) * NT / W;
+    if (t0 >= t1) return;
+    int64_t lo = 0, hi = d.batch;   // largest f with tile_start[f] <= t0
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (tile_start[mid] <= t0) lo = mid;
+        else hi = mid;
+    }
+    int64_t f = lo;
+    SegMeta cur = load_meta(d, tile_start, pstatus, rec, rl, f);
+    int64_t t = t0;
+    while (t < t1) {
+        if (cur.fe <= t) {   // a fit without tiles (or before t0)
+            ++f;
+            cur = load_meta(d, tile_start, pstatus, rec, rl, f);
+            continue;
+        }
+        const int64_t te = cur.fe < t1 ? cur.fe : t1;
+        const bool more = te < t1;   // then fit f + 1 < B holds the next tile
+        SegMeta nxt = cur;
+        if (more) nxt = load_meta(d, tile_start, pstatus, rec, rl, f + 1);
+        const int64_t plo = cur.lo + (t - cur.fs) * tile;
+        int64_t phi = cur.lo + (te - cur.fs) * tile;
+        if (phi > cur.hi) phi = cur.hi;
+        fn(f, plo, phi, wave + f, cur);
+        t = te;
+        ++f;
+        cur = nxt;
+    }
+}
+
 // the wave that owns tile t (inverse of the split above)
 __device__ inline int64_t wave_of_tile(int64_t t, int64_t NT, int64_t W) { return ((t + 1) * W - 1) / NT; }
 

@@ -626,15 +626,15 @@ __global__ void __launch_bounds__(256)
         dispatch_degree<MAXM>(d.degree, body);
         return;
     }
-    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
-        if (w.pstatus[f] != LSEFIT_OK) return;
-        const double c = w.rec[f * rl + 0];
-        const double inv_s = 1.0 / w.rec[f * rl + 1];
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, tile, wave, W,
+                        [&](int64_t f, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
+        if (mt.st != LSEFIT_OK) return;
+        const double inv_s = 1.0 / mt.s;
         double* __restrict__ out = w.part + slot * stride;
         auto body = [&]<int M>() {
             using Acc = std::conditional_t<PREC == LSEFIT_PREC_F64, AccF64<M>, AccF32C<M>>;
             Acc acc;
-            acc.init(c, inv_s);
+            acc.init(mt.c, inv_s);
             stream_segment<U>(x, y, lo, hi, mis, acc);
             double v[nacc(M)];
             acc.out(v);
@@ -645,7 +645,7 @@ __global__ void __launch_bounds__(256)
                 for (int k = 0; k < nacc(M); ++k) out[k] = v[k];
             }
         };
-        dispatch_degree<MAXM>(fit_deg(d, f), body);
+        dispatch_degree<MAXM>(mt.deg, body);
     });
 }
 

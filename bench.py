@@ -508,10 +508,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 def cheb_flops_per_point(m: int) -> int:
     """float64 flops of one point of the Chebyshev streaming pass (fma = 2):
-    t (fma), 2t, then T_2..T_2m by T_(k+1) = 2t T_k - T_(k-1) (2m-1 fma), the
-    2m sums of T_k and D_0 (adds), and D_1..D_m (fma)."""
-    fma = 1 + (2 * m - 1) + m
-    add = 1 + 2 * m + 1
+    t (fma), 2t (add), T_2..T_m by T_(k+1) = 2t T_k - T_(k-1) (m-1 fma), the
+    sums C_1..C_m and D_0 (m+1 adds), D_1..D_m and E_1..E_m = sum T_m T_j
+    (2m fma)."""
+    fma = 1 + (m - 1) + 2 * m
+    add = 1 + m + 1
     return 2 * fma + add
 
 

@@ -673,6 +673,9 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
                             const int32_t* degrees, int64_t batch, const lsefit_options* opt, double* coef,
                             int32_t coef_stride, int32_t* status, void* stream, int32_t reps, double* best_ms_out) {
     if (!plan || !opts_ok(opt, plan->dtype, true) || batch < 1 || batch > plan->batch) return LSEFIT_ERR_INVALID_ARG;
+    if (!x || !y || !offsets || !degrees || !coef || !status) return LSEFIT_ERR_INVALID_ARG;
+    if (opt->degree > plan->max_degree || coef_stride < opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
+    if (unsupported(opt, plan->dtype)) return LSEFIT_ERR_UNSUPPORTED;
     if (reps < 1) reps = 3;
     hipStream_t st = (hipStream_t)stream;
     const FitDesc d{offsets, degrees, 0, batch, opt->degree};
@@ -687,25 +690,29 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
                     lsefit_schedule s{cus * wpc, wpb, tile, unroll};
                     if (to_launch(s).waves <= plan->max_waves) cands.push_back(s);
                 }
-    hipEvent_t e0, e1;
-    LSEFIT_TRY(hipEventCreate(&e0));
-    LSEFIT_TRY(hipEventCreate(&e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return LSEFIT_ERR_DEVICE;
+    }
     double best = 1e300;
     lsefit_schedule best_s = plan->sched;
+    lsefit_status r = LSEFIT_OK;
     for (const auto& s : cands) {
         // one untimed run, then the timed ones
-        lsefit_status r = enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, s, st);
-        if (r != LSEFIT_OK) {
-            hipEventDestroy(e0);
-            hipEventDestroy(e1);
-            return r;
+        r = enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, s, st);
+        if (r != LSEFIT_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) {
+            r = LSEFIT_ERR_DEVICE;
+            break;
         }
-        LSEFIT_TRY(hipEventRecord(e0, st));
-        for (int i = 0; i < reps; ++i) enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, s, st);
-        LSEFIT_TRY(hipEventRecord(e1, st));
-        LSEFIT_TRY(hipEventSynchronize(e1));
+        for (int i = 0; i < reps && r == LSEFIT_OK; ++i)
+            r = enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, s, st);
         float ms = 0.f;
-        LSEFIT_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (r == LSEFIT_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            r = LSEFIT_ERR_DEVICE;
+        if (r != LSEFIT_OK) break;
         const double per = ms / reps;
         if (per < best) {
             best = per;
@@ -714,6 +721,7 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    if (r != LSEFIT_OK) return r;
     plan->sched = best_s;
     plan->drop_graph();
     if (best_ms_out) *best_ms_out = best;

@@ -141,6 +141,27 @@ def test_null_pointers_rejected():
     L.fit_plan_destroy(None)
 
 
+@pytest.mark.gpu
+def test_plan_tune_validates_against_the_plan():
+    """A degree above the plan's, a short stride or a null pointer never reaches
+    the kernels (the plan's workspace is sized for its own maximum degree)."""
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    assert L.fit_plan_create(ctypes.byref(h), 10, 2, _lib.F32, 0) == _lib.OK
+    try:
+        best = ctypes.c_double(0.0)
+        o3 = _opt(degree=3)
+        o2 = _opt(degree=2)
+        assert L.fit_plan_tune(h, FAKE, FAKE, FAKE, FAKE, 10, ctypes.byref(o3), FAKE, 4, FAKE, None, 1,
+                               ctypes.byref(best)) == _lib.INVALID_ARG
+        assert L.fit_plan_tune(h, FAKE, FAKE, FAKE, FAKE, 10, ctypes.byref(o2), FAKE, 2, FAKE, None, 1,
+                               ctypes.byref(best)) == _lib.INVALID_ARG
+        assert L.fit_plan_tune(h, None, FAKE, FAKE, FAKE, 10, ctypes.byref(o2), FAKE, 3, FAKE, None, 1,
+                               ctypes.byref(best)) == _lib.INVALID_ARG
+    finally:
+        L.fit_plan_destroy(h)
+
+
 def test_default_schedule_setter_validates():
     L = _lib.load()
     bad = _lib.Schedule(0, 4, 256, 2)

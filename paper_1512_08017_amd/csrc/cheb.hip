@@ -311,129 +311,6 @@ __global__ void __launch_bounds__(256)
 // registers for the elimination, and the lanes share pivot rows and solved
 // unknowns through readlane.
 // ---------------------------------------------------------------------------
-__device__ inline double bcast(double v, int src) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-    return __hiloint2double(hi, lo);
-}
-
-// orders this wave's LDS writes before its later LDS reads
-__device__ inline void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
-
-// max |G| over the N x N part held by lanes 0..N-1
-template <int M>
-__device__ inline double wave_amax(const double (&row)[M + 2]) {
-    constexpr int N = M + 1;
-    double la = 0.0;
-    if (lane_id() < N) {
-#pragma unroll
-        for (int c = 0; c < N; ++c) la = fmax(la, fabs(row[c]));
-    }
-    double amax = 0.0;
-#pragma unroll
-    for (int r = 0; r < N; ++r) amax = fmax(amax, bcast(la, r));
-    return amax;
-}
-
-// Partial pivoting (first row of largest magnitude), singular when a pivot is
-// at most 2^-40 max|G|; the same operations, in the same order per entry, as an
-// elimination by one thread.  On success lane i < N holds x_i in xl.
-template <int M>
-__device__ __forceinline__ int wave_gepp(double (&row)[M + 2], double& xl) {
-    constexpr int N = M + 1;
-    const int lane = lane_id();
-    const double tiny = ldexp(wave_amax<M>(row), -40);
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        int p = k;
-        double pv = fabs(bcast(row[k], k));
-#pragma unroll
-        for (int r = k + 1; r < N; ++r) {
-            const double v = fabs(bcast(row[k], r));
-            if (v > pv) {
-                pv = v;
-                p = r;
-            }
-        }
-        if (!(pv > tiny)) return LSEFIT_ERR_SINGULAR;
-        p = __builtin_amdgcn_readfirstlane(p);
-        if (p != k) {
-#pragma unroll
-            for (int c = k; c <= N; ++c) {
-                const double a = bcast(row[c], p), b = bcast(row[c], k);
-                if (lane == k) row[c] = a;
-                else if (lane == p) row[c] = b;
-            }
-        }
-        const double pk = bcast(row[k], k);
-        if (lane > k && lane < N) {
-            const double l = row[k] / pk;
-#pragma unroll
-            for (int c = k; c <= N; ++c) row[c] -= l * bcast(row[c], k);
-        }
-    }
-    xl = 0.0;
-#pragma unroll
-    for (int i = N - 1; i >= 0; --i) {
-        double acc = row[N];
-#pragma unroll
-        for (int c = i + 1; c < N; ++c) acc -= row[c] * bcast(xl, c);
-        const double xi = bcast(acc / row[i], i);
-        if (lane == i) xl = xi;
-    }
-    return LSEFIT_OK;
-}
-
-// G = L L^T (lane r holds row r of L), then L z = D and L^T x = z; lane i < N
-// holds x_i in xl
-template <int M>
-__device__ __forceinline__ int wave_cholesky(const double (&row)[M + 2], double& xl) {
-    constexpr int N = M + 1;
-    const int lane = lane_id();
-    const double tiny = ldexp(wave_amax<M>(row), -40);
-    double L[M + 1];
-#pragma unroll
-    for (int c = 0; c < N; ++c) L[c] = 0.0;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        double dg = bcast(row[j], j);
-#pragma unroll
-        for (int k = 0; k < j; ++k) {
-            const double ljk = bcast(L[k], j);
-            dg -= ljk * ljk;
-        }
-        if (!(dg > tiny)) return LSEFIT_ERR_SINGULAR;
-        const double ljj = sqrt(dg);
-        if (lane == j) {
-            L[j] = ljj;
-        } else if (lane > j && lane < N) {
-            double acc = row[j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) acc -= L[k] * bcast(L[k], j);
-            L[j] = acc / ljj;
-        }
-    }
-    double zl = 0.0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        double acc = row[N];
-#pragma unroll
-        for (int k = 0; k < i; ++k) acc -= L[k] * bcast(zl, k);
-        const double zi = bcast(acc / L[i], i);
-        if (lane == i) zl = zi;
-    }
-    xl = 0.0;
-#pragma unroll
-    for (int i = N - 1; i >= 0; --i) {
-        double acc = bcast(zl, i);
-#pragma unroll
-        for (int k = i + 1; k < N; ++k) acc -= bcast(L[i], k) * bcast(xl, k);
-        const double xi = acc / bcast(L[i], i);
-        if (lane == i) xl = xi;
-    }
-    return LSEFIT_OK;
-}
-
 // S = this wave's LDS row [C_0..C_2m, D_0..D_m] of fit f (written and fenced by
 // the caller): assemble, solve, write the Chebyshev coefficients (then, with
 // write_b, the x-basis coefficients after them; else c and s after them when
@@ -552,13 +429,14 @@ __device__ __forceinline__ void cheb_store_sums(const Work& w, int64_t f, int ma
     wave_lds_fence();
 }
 
-// Single fit of degree M (one block): the block's threads sum the W block
-// partials (sum-major; thread t takes blocks t, t + 256, ...; then waves in
-// order) and wave 0 finishes.
+// Single fit of degree M (one block of finish_threads(W) threads): the threads
+// sum the W block partials (sum-major; thread t takes blocks t, t + blockDim,
+// ...; then waves in order) and wave 0 finishes.
 template <int M>
-__global__ void __launch_bounds__(256) k_finish_cheb_single(FitDesc d, Work w, int64_t W, int maxm, Finish fz) {
+__global__ void __launch_bounds__(kFinishMaxThreads)
+    k_finish_cheb_single(FitDesc d, Work w, int64_t W, int maxm, Finish fz) {
     constexpr int K = nacc(M);
-    __shared__ double sh[4][K];
+    __shared__ double sh[kFinishMaxThreads / kWave][K];
     __shared__ double S[3 * M + 2];
     const int wid = wave_id_in_block(), lane = lane_id();
     const int pst = w.pstatus[0];
@@ -581,13 +459,7 @@ __global__ void __launch_bounds__(256) k_finish_cheb_single(FitDesc d, Work w, i
     }
     __syncthreads();
     if (wid != 0) return;
-    const int nw = blockDim.x / kWave;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double acc = sh[0][k];
-        for (int i = 1; i < nw; ++i) acc += sh[i][k];
-        v[k] = acc;
-    }
+    wave_column_sums<K, K>(sh, blockDim.x / kWave, v);
     cheb_store_sums<M>(w, 0, maxm, (double)d.n_single, v, fz, S);
     if (fz.mode != kMomentsOnly) cheb_solve_wave<M>(w, 0, maxm, w.rec[0], w.rec[1], S, fz);
 }
@@ -720,7 +592,7 @@ hipError_t launch_finish_cheb(const FitDesc& d, const Work& w, int maxm, int64_t
                               hipStream_t st) {
     if (is_single(d)) {
         auto body = [&]<int M>() {
-            hipLaunchKernelGGL(k_finish_cheb_single<M>, dim3(1), dim3(256), 0, st, d, w, W, maxm, fz);
+            hipLaunchKernelGGL(k_finish_cheb_single<M>, dim3(1), dim3(finish_threads(W)), 0, st, d, w, W, maxm, fz);
         };
         dispatch_degree<kChebMax>(d.degree, body);
         return hipGetLastError();

@@ -403,6 +403,151 @@ __device__ inline void to_x_basis(const double (&b)[N], double c, double s, doub
     }
 }
 
+// ---------------------------------------------------------------------------
+// solving a normal system with one wave: lane r < N holds row r of [A | rhs]
+// in registers; pivot rows and solved unknowns are shared with readlane.
+// The same operations, in the same order per entry, as the one-thread
+// solvers above.
+// ---------------------------------------------------------------------------
+__device__ inline double bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// v[k] = sh[0][k] + sh[1][k] + ... + sh[nw-1][k] (in that order) in every
+// lane of the calling wave: lane k adds column k, readlane shares the sums
+// (K <= 64)
+template <int K, int S>
+__device__ inline void wave_column_sums(const double (*sh)[S], int nw, double (&v)[K]) {
+    static_assert(K <= 64 && K <= S, "one lane per sum");
+    const int lane = lane_id();
+    double t = 0.0;
+    if (lane < K) {
+        t = sh[0][lane];
+        for (int i = 1; i < nw; ++i) t += sh[i][lane];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = bcast(t, k);
+}
+
+// orders this wave's LDS writes before its later LDS reads
+__device__ inline void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// max |G| over the N x N part held by lanes 0..N-1
+template <int M>
+__device__ inline double wave_amax(const double (&row)[M + 2]) {
+    constexpr int N = M + 1;
+    double la = 0.0;
+    if (lane_id() < N) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) la = fmax(la, fabs(row[c]));
+    }
+    double amax = 0.0;
+#pragma unroll
+    for (int r = 0; r < N; ++r) amax = fmax(amax, bcast(la, r));
+    return amax;
+}
+
+// Partial pivoting (first row of largest magnitude), singular when a pivot is
+// at most 2^-40 max|G|; the same operations, in the same order per entry, as an
+// elimination by one thread.  On success lane i < N holds x_i in xl.
+template <int M>
+__device__ __forceinline__ int wave_gepp(double (&row)[M + 2], double& xl) {
+    constexpr int N = M + 1;
+    const int lane = lane_id();
+    const double tiny = ldexp(wave_amax<M>(row), -40);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        int p = k;
+        double pv = fabs(bcast(row[k], k));
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            const double v = fabs(bcast(row[k], r));
+            if (v > pv) {
+                pv = v;
+                p = r;
+            }
+        }
+        if (!(pv > tiny)) return LSEFIT_ERR_SINGULAR;
+        p = __builtin_amdgcn_readfirstlane(p);
+        if (p != k) {
+#pragma unroll
+            for (int c = k; c <= N; ++c) {
+                const double a = bcast(row[c], p), b = bcast(row[c], k);
+                if (lane == k) row[c] = a;
+                else if (lane == p) row[c] = b;
+            }
+        }
+        const double pk = bcast(row[k], k);
+        if (lane > k && lane < N) {
+            const double l = row[k] / pk;
+#pragma unroll
+            for (int c = k; c <= N; ++c) row[c] -= l * bcast(row[c], k);
+        }
+    }
+    xl = 0.0;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        double acc = row[N];
+#pragma unroll
+        for (int c = i + 1; c < N; ++c) acc -= row[c] * bcast(xl, c);
+        const double xi = bcast(acc / row[i], i);
+        if (lane == i) xl = xi;
+    }
+    return LSEFIT_OK;
+}
+
+// G = L L^T (lane r holds row r of L), then L z = D and L^T x = z; lane i < N
+// holds x_i in xl
+template <int M>
+__device__ __forceinline__ int wave_cholesky(const double (&row)[M + 2], double& xl) {
+    constexpr int N = M + 1;
+    const int lane = lane_id();
+    const double tiny = ldexp(wave_amax<M>(row), -40);
+    double L[M + 1];
+#pragma unroll
+    for (int c = 0; c < N; ++c) L[c] = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double dg = bcast(row[j], j);
+#pragma unroll
+        for (int k = 0; k < j; ++k) {
+            const double ljk = bcast(L[k], j);
+            dg -= ljk * ljk;
+        }
+        if (!(dg > tiny)) return LSEFIT_ERR_SINGULAR;
+        const double ljj = sqrt(dg);
+        if (lane == j) {
+            L[j] = ljj;
+        } else if (lane > j && lane < N) {
+            double acc = row[j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) acc -= L[k] * bcast(L[k], j);
+            L[j] = acc / ljj;
+        }
+    }
+    double zl = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double acc = row[N];
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc -= L[k] * bcast(zl, k);
+        const double zi = bcast(acc / L[i], i);
+        if (lane == i) zl = zi;
+    }
+    xl = 0.0;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        double acc = bcast(zl, i);
+#pragma unroll
+        for (int k = i + 1; k < N; ++k) acc -= bcast(L[i], k) * bcast(xl, k);
+        const double xi = acc / bcast(L[i], i);
+        if (lane == i) xl = xi;
+    }
+    return LSEFIT_OK;
+}
+
 // (M^T g)_j = sum_{k<=j} C(j,k) (-c)^(j-k) s^-j g_k : the adjoint of to_x_basis
 template <int N>
 __device__ inline void to_t_basis_adjoint(const double (&g)[N], double c, double s, double (&gt)[N]) {

@@ -467,12 +467,109 @@ __device__ inline void block_combine_fit(const FitDesc& d, const Work& w, int64_
     dispatch_degree<MAXM>(fit_deg(d, f), body);
 }
 
+// finish_fit by one wave (every lane holds the same v): the normal system is
+// solved with a row per lane (wave_gepp / wave_cholesky, the same operations
+// per entry as hankel_solve / hankel_cholesky) and the change back to the
+// x-basis runs with a coefficient per lane.  sm: 3M+2 doubles of this wave's LDS.
+template <int M, int MAXM>
+__device__ inline void finish_fit_wave(const FitDesc& d, const Work& w, int64_t f, const double (&v)[nacc(M)],
+                                       const Finish& fz, double* sm) {
+    constexpr int N = M + 1;
+    constexpr int rl = rec_len(MAXM);
+    const int lane = lane_id();
+    const bool mine = lane < N;
+    if (fz.mode == kSSE) {
+        if (lane == 0) fz.coef[f] = v[0];
+        return;
+    }
+    double* r = w.rec + f * rl;
+    const double c = r[0], s = r[1];
+    // S_0..S_2M and the right side (T, or the refinement sums) into LDS
+    if (lane == 0) {
+        if (fz.mode == kRefine) {
+#pragma unroll
+            for (int k = 0; k <= 2 * M; ++k) sm[k] = r[rec_S(MAXM) + k];
+#pragma unroll
+            for (int j = 0; j < N; ++j) sm[2 * M + 1 + j] = v[j];
+        } else {
+            sm[0] = (double)(fit_hi(d, f) - fit_lo(d, f));
+#pragma unroll
+            for (int k = 1; k <= 2 * M; ++k) sm[k] = v[k - 1];
+#pragma unroll
+            for (int j = 0; j < N; ++j) sm[2 * M + 1 + j] = v[2 * M + j];
+#pragma unroll
+            for (int k = 0; k <= 2 * M; ++k) r[rec_S(MAXM) + k] = sm[k];
+#pragma unroll
+            for (int j = 0; j < N; ++j) r[rec_T(MAXM) + j] = sm[2 * M + 1 + j];
+            if (fz.moments_out) {
+                fz.moments_out[0] = c;
+                fz.moments_out[1] = s;
+#pragma unroll
+                for (int k = 0; k < 3 * M + 2; ++k) fz.moments_out[2 + k] = sm[k];
+            }
+        }
+    }
+    wave_lds_fence();
+    if (fz.mode == kMomentsOnly) return;
+    double row[M + 2];
+    bool finite = true;
+#pragma unroll
+    for (int cc = 0; cc <= N; ++cc) row[cc] = 0.0;
+    if (mine) {
+#pragma unroll
+        for (int cc = 0; cc < N; ++cc) {
+            row[cc] = sm[lane + cc];
+            finite = finite && isfinite(row[cc]);
+        }
+        row[N] = sm[2 * M + 1 + lane];
+        finite = finite && isfinite(row[N]);
+    }
+    wave_lds_fence();
+    double x = 0.0;
+    int st = __ballot(!finite) ? LSEFIT_ERR_NONFINITE
+                               : (fz.solver == LSEFIT_SOLVER_CHOLESKY ? wave_cholesky<M>(row, x)
+                                                                      : wave_gepp<M>(row, x));
+    if (st == LSEFIT_OK && __ballot(mine && !isfinite(x))) st = LSEFIT_ERR_NONFINITE;
+    double b = x;
+    if (fz.mode == kRefine && mine) b = r[rec_b(MAXM) + lane] + x;
+    // a_k = sum_(j>=k) b_j C(j,k) (-c)^(j-k) s^-j, lane k (the order of to_x_basis)
+    double a = 0.0;
+    if (st == LSEFIT_OK) {
+        const double inv_s = 1.0 / s;
+        double binom = 1.0, cpow = 1.0, spow = 1.0;
+        for (int i = 0; i < lane && i < N; ++i) spow *= inv_s;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const double bj = bcast(b, j);
+            if (lane <= j) {
+                a += bj * binom * cpow * spow;
+                binom = binom * (double)(j + 1) / (double)(j + 1 - lane);
+                cpow *= -c;
+                spow *= inv_s;
+            }
+        }
+        if (__ballot(mine && !isfinite(a))) st = LSEFIT_ERR_NONFINITE;
+    }
+    if (st != LSEFIT_OK) a = b = NAN;
+    if (mine) {
+        double* a_out = fz.coef + f * (int64_t)fz.coef_stride;
+        r[rec_b(MAXM) + lane] = b;
+        a_out[lane] = a;
+        if (fz.write_b) a_out[N + lane] = b;
+    }
+    if (lane == 0) {
+        w.pstatus[f] = st;
+        fz.status[f] = st;
+    }
+}
+
 // single fit: the threads of one block sum the G block partials (thread t takes
-// blocks t, t + blockDim, ...; then waves in order) and thread 0 finishes the fit
+// blocks t, t + blockDim, ...; then waves in order) and wave 0 finishes the fit
 template <int MAXM>
 __device__ inline void finish_single_block(const FitDesc& d, const Work& w, int64_t G, const Finish& fz) {
     constexpr int stride = nacc(MAXM);
     __shared__ double sh[16][stride];
+    __shared__ double sm[3 * MAXM + 2];
     const int pst = w.pstatus[0];
     if (pst != LSEFIT_OK) {
         if (threadIdx.x == 0 && fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, 0, fz, pst);
@@ -497,23 +594,19 @@ __device__ inline void finish_single_block(const FitDesc& d, const Work& w, int6
             for (int k = 0; k < K; ++k) sh[wave_id_in_block()][k] = v[k];
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const int nw = blockDim.x / kWave;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                double acc = sh[0][k];
-                for (int i = 1; i < nw; ++i) acc += sh[i][k];
-                v[k] = acc;
-            }
-            finish_fit<M, MAXM>(d, w, 0, v, fz);
+        if (wave_id_in_block() == 0) {
+            wave_column_sums<K, stride>(sh, blockDim.x / kWave, v);
+            finish_fit_wave<M, MAXM>(d, w, 0, v, fz, sm);
         }
     };
     dispatch_degree<MAXM>(d.degree, body);
 }
 
-// The finish block has one thread per block partial (a multiple of 64, at
-// most 1024), so each thread waits for one round trip to memory only.
-constexpr int kFinishMaxThreads = 1024;
+// The finish block has one thread per block partial (a multiple of 64), at
+// most 512: the loop over a thread's partials does not overlap its loads, so
+// every further partial per thread costs a memory round trip, and up to 512
+// threads the solve keeps a budget of 256 registers.
+constexpr int kFinishMaxThreads = 512;
 
 __host__ __device__ inline int finish_threads(int64_t G) {
     const int64_t t = (G + kWave - 1) / kWave * kWave;

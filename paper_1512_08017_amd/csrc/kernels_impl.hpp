@@ -416,57 +416,6 @@ __device__ inline void fail_fit(const FitDesc& d, const Work& w, int64_t f, cons
     fz.status[f] = st;
 }
 
-// the threads of one block sum the partial slots of fit f in a fixed order
-// (strided per thread, butterfly per wave, waves in order), then one thread
-// finishes the fit
-template <int MAXM>
-__device__ inline void block_combine_fit(const FitDesc& d, const Work& w, int64_t f, int64_t W, const Finish& fz) {
-    constexpr int stride = nacc(MAXM);
-    __shared__ double sh[4][stride];
-    const int pst = w.pstatus[f];
-    if (pst != LSEFIT_OK) {
-        if (threadIdx.x == 0 && fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, f, fz, pst);
-        return;
-    }
-    const int nw = blockDim.x / kWave;
-    const int64_t NT = w.tile_start[d.batch];
-    const int64_t ts = w.tile_start[f], te = w.tile_start[f + 1];
-    const int64_t w0 = wave_of_tile(ts, NT, W), w1 = wave_of_tile(te - 1, NT, W);
-    auto body = [&]<int M>() {
-        constexpr int K = nacc(M);
-        const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
-        double v[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = 0.0;
-        for (int64_t wv = w0 + threadIdx.x; wv <= w1; wv += blockDim.x) {
-            if (!wave_owns_tiles(wv, NT, W)) continue;
-            const double* p = w.part + (wv + f) * stride;
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k < nk) v[k] += p[k];
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-        const int wv = wave_id_in_block();
-        if (lane_id() == 0) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) sh[wv][k] = v[k];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                double acc = sh[0][k];
-                for (int i = 1; i < nw; ++i) acc += sh[i][k];
-                v[k] = acc;
-            }
-            finish_fit<M, MAXM>(d, w, f, v, fz);
-        }
-        __syncthreads();
-    };
-    dispatch_degree<MAXM>(fit_deg(d, f), body);
-}
-
 // finish_fit by one wave (every lane holds the same v): the normal system is
 // solved with a row per lane (wave_gepp / wave_cholesky, the same operations
 // per entry as hankel_solve / hankel_cholesky) and the change back to the
@@ -561,6 +510,53 @@ __device__ inline void finish_fit_wave(const FitDesc& d, const Work& w, int64_t 
         w.pstatus[f] = st;
         fz.status[f] = st;
     }
+}
+
+// the threads of one block sum the partial slots of fit f in a fixed order
+// (strided per thread, butterfly per wave, waves in order), then wave 0
+// finishes the fit
+template <int MAXM>
+__device__ inline void block_combine_fit(const FitDesc& d, const Work& w, int64_t f, int64_t W, const Finish& fz) {
+    constexpr int stride = nacc(MAXM);
+    __shared__ double sh[4][stride];
+    __shared__ double sm[3 * MAXM + 2];
+    const int pst = w.pstatus[f];
+    if (pst != LSEFIT_OK) {
+        if (threadIdx.x == 0 && fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, f, fz, pst);
+        return;
+    }
+    const int nw = blockDim.x / kWave;
+    const int64_t NT = w.tile_start[d.batch];
+    const int64_t ts = w.tile_start[f], te = w.tile_start[f + 1];
+    const int64_t w0 = wave_of_tile(ts, NT, W), w1 = wave_of_tile(te - 1, NT, W);
+    auto body = [&]<int M>() {
+        constexpr int K = nacc(M);
+        const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = 0.0;
+        for (int64_t wv = w0 + threadIdx.x; wv <= w1; wv += blockDim.x) {
+            if (!wave_owns_tiles(wv, NT, W)) continue;
+            const double* p = w.part + (wv + f) * stride;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k < nk) v[k] += p[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+        const int wv = wave_id_in_block();
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) sh[wv][k] = v[k];
+        }
+        __syncthreads();
+        if (wv == 0) {
+            wave_column_sums<K, stride>(sh, nw, v);
+            finish_fit_wave<M, MAXM>(d, w, f, v, fz, sm);
+        }
+        __syncthreads();
+    };
+    dispatch_degree<MAXM>(fit_deg(d, f), body);
 }
 
 // single fit: the threads of one block sum the G block partials (thread t takes

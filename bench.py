@@ -105,13 +105,13 @@ def summarize_pmc(fetch_dir, write_dir, out_path=None):
         out[counter] = {"moments_kib": sorted(mom), "refine_kib": sorted(ref), "copy_kib": sorted(cpy)}
     lines = ["# HBM traffic of the power-sum kernel (k_moments) and the refinement kernel (k_refine)",
              "# workload: cubic fit, n = 1e8 float32 points (800,000,000 algorithmic bytes per pass)",
-             "# commands (two runs, one counter each):",
-             f"#   rocprofv3 --pmc FETCH_SIZE -d {fetch_dir} -o run --output-format csv -- "
-             "python3 bench.py --pmc-probe",
-             f"#   rocprofv3 --pmc WRITE_SIZE -d {write_dir} -o run --output-format csv -- "
-             "python3 bench.py --pmc-probe",
-             f"#   python3 bench.py --summarize-pmc {fetch_dir} {write_dir} "
-             "--out profiles/moments_cubic_f32_traffic.txt",
+             "# commands (two runs, one counter each; on the MI355X machine, from /tmp with TMPDIR=/tmp):",
+             f"#   timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -d {fetch_dir} -o run --output-format csv -- "
+             "python3 /root/repo/bench.py --pmc-probe",
+             f"#   timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE -d {write_dir} -o run --output-format csv -- "
+             "python3 /root/repo/bench.py --pmc-probe",
+             f"#   python3 /root/repo/bench.py --summarize-pmc {fetch_dir} {write_dir} "
+             "--out /root/repo/profiles/moments_cubic_f32_traffic.txt",
              f"# {COPY_BYTES_NOTE}",
              f"kernel_hash {kernel_hash()}"]
     for counter, d in out.items():
@@ -137,9 +137,9 @@ def summarize_trace(folder, title, command, out_path=None):
                     rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
                                  float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
     lines = [f"# rocprofv3 kernel-trace summary: {title}",
-             "# command (on the MI355X box, from /tmp with TMPDIR=/tmp):",
+             "# command (on the MI355X machine, from /tmp with TMPDIR=/tmp):",
              f"#   {command}",
-             "# summarised by: python3 bench.py --summarize-trace DIR TITLE COMMAND --out FILE",
+             "# summarised by: python3 /root/repo/bench.py --summarize-trace DIR TITLE COMMAND --out FILE",
              f"#   (DIR = {folder}, TITLE and COMMAND = the two lines above, FILE = this file)"]
     for name, calls, avg, mn, mx in sorted(rows, key=lambda r: -r[1] * r[2]):
         short = name.split("(")[0]

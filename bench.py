@@ -14,7 +14,7 @@ coefficients N(0, 1), noise N(0, 0.01^2).  Both accumulation forms are timed
 the two that meets the 1e-6 coefficient bound).  The streaming QR route
 (fit_qr) is timed on the same data as a third, reported form ("qr").
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -604,7 +604,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
-              "this build measures one GPU's share; sharding across GPUs is not built", file=sys.stderr)
+              "it measures one GPU's share; sharding across GPUs is not implemented", file=sys.stderr)
         return 2
 
     import numpy as np

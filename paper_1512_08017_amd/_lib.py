@@ -63,8 +63,8 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                           "(or python -m paper_1512_08017_amd.build); the fit has no CPU path")
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1512_08017_amd.build; "
+                           "the fit has no CPU path")
     L = ctypes.CDLL(LIB_PATH)
     L.lsefit_workspace_bytes.argtypes = [i64, i32, SchP]
     L.lsefit_workspace_bytes.restype = sz

@@ -297,6 +297,18 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
                             const int32_t* degrees, int64_t batch, const lsefit_options* opt,
                             double* coef, int32_t coef_stride, int32_t* status, void* stream,
                             int32_t reps, double* best_ms_out);
+/* Schedule cache of fit_plan_tune (for callers that tune the same shapes in
+ * many processes).  With a path set, fit_plan_tune first looks the call's
+ * shape up in that text file: the key is the device (architecture, compute
+ * units), dtype, options, batch and the total points rounded down to a power
+ * of two.  On a hit it installs the cached schedule, runs the fit once with
+ * it (coef and status are written as by a tuning run), writes the cached time
+ * to best_ms_out and times nothing; on a miss it tunes as usual and appends
+ * the result as one line.  Appends within a process are serialised; a file
+ * that cannot be read is treated as empty and one that cannot be written is
+ * left alone (the tuned schedule is still installed).  path NULL or "" turns
+ * the cache off.  The string is copied. */
+lsefit_status fit_plan_set_tune_cache(lsefit_plan* plan, const char* path);
 lsefit_status fit_plan_set_schedule(lsefit_plan* plan, const lsefit_schedule* schedule);
 lsefit_status fit_plan_get_schedule(const lsefit_plan* plan, lsefit_schedule* out);
 lsefit_status fit_plan_set_graph(lsefit_plan* plan, int32_t enable);

@@ -24,7 +24,7 @@ EXPORTS = (
     "lsefit_workspace_bytes", "lsefit_default_schedule", "lsefit_set_default_schedule",
     "fit_moments", "fit_solve", "fit_single", "fit_qr", "fit_qr_batched", "fit_batched", "fit_backward",
     "fit_residuals",
-    "fit_plan_create", "fit_plan_tune", "fit_plan_set_schedule", "fit_plan_get_schedule",
+    "fit_plan_create", "fit_plan_tune", "fit_plan_set_tune_cache", "fit_plan_set_schedule", "fit_plan_get_schedule",
     "fit_plan_set_graph", "fit_plan_destroy", "lsefit_status_string", "lsefit_device_cus",
     "lsefit_timing_enable", "lsefit_timing_reset", "lsefit_timing_read", "lsefit_read_probe",
 )
@@ -81,6 +81,7 @@ def load():
     L.fit_plan_create.argtypes = [ctypes.POINTER(vp), i64, i32, i32, i32]
     L.fit_plan_tune.argtypes = [vp, vp, vp, vp, vp, i64, OptP, vp, i32, vp, vp, i32, ctypes.POINTER(ctypes.c_double)]
     L.fit_plan_set_schedule.argtypes = [vp, SchP]
+    L.fit_plan_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
     L.fit_plan_get_schedule.argtypes = [vp, SchP]
     L.fit_plan_set_graph.argtypes = [vp, i32]
     L.fit_plan_destroy.argtypes = [vp]
@@ -93,7 +94,8 @@ def load():
     L.lsefit_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     for name in ("lsefit_default_schedule", "lsefit_set_default_schedule", "fit_moments", "fit_solve", "fit_single",
                  "fit_qr", "fit_qr_batched", "fit_residuals",
-                 "fit_batched", "fit_backward", "fit_plan_create", "fit_plan_tune", "fit_plan_set_schedule",
+                 "fit_batched", "fit_backward", "fit_plan_create", "fit_plan_tune", "fit_plan_set_tune_cache",
+                 "fit_plan_set_schedule",
                  "fit_plan_get_schedule", "fit_plan_set_graph", "lsefit_timing_enable", "lsefit_timing_reset",
                  "lsefit_timing_read", "lsefit_read_probe"):
         getattr(L, name).restype = i32

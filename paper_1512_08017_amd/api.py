@@ -7,6 +7,8 @@ runs in the library's kernels; there is no CPU path.
 """
 from __future__ import annotations
 
+import os
+
 import ctypes
 from dataclasses import dataclass
 
@@ -319,6 +321,11 @@ class Plan:
 
     def set_graph(self, enable: bool):
         check(self._L.fit_plan_set_graph(self.handle, 1 if enable else 0), "fit_plan_set_graph")
+
+    def set_tune_cache(self, path):
+        """Schedule cache file of tune() (None turns it off); see fit_plan_set_tune_cache."""
+        check(self._L.fit_plan_set_tune_cache(self.handle, None if path is None else os.fsencode(path)),
+              "fit_plan_set_tune_cache")
 
     def tune(self, x, y, offsets, degrees, max_degree=None, precision=None, refine=1, center=None, scale=None,
              reps=3, solver="gepp", basis="monomial") -> float:

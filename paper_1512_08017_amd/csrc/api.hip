@@ -9,9 +9,13 @@
 #include <chrono>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
 #include <new>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "kernels.hpp"
@@ -301,6 +305,7 @@ struct lsefit_plan {
         int32_t* status;
     } key{};
     bool have_key = false;
+    std::string tune_cache;   // schedule cache file of fit_plan_tune ("" = none)
 
     void drop_graph() {
         if (exec) hipGraphExecDestroy(exec);
@@ -310,6 +315,63 @@ struct lsefit_plan {
 };
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// schedule cache of fit_plan_tune: a text file, one line per tuned shape,
+// "<key>\t<waves> <waves_per_block> <tile> <unroll> <ms>".  The key names the
+// device (architecture and compute units) and the shape of the call (dtype,
+// options, batch, and the total points rounded to a power of two); the last
+// line with a key wins.  Lines are appended under a process-wide mutex; a file
+// that cannot be read or written is treated as empty or skipped.
+// ---------------------------------------------------------------------------
+std::mutex g_cache_mu;
+
+std::string tune_key(const lsefit_options* opt, int32_t dt, int64_t batch, int64_t points) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch.resize(colon);
+    }
+    int lg = 0;
+    while (lg < 62 && (int64_t(1) << (lg + 1)) <= points) ++lg;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s cu=%d dt=%d prec=%d refine=%d basis=%d solver=%d range=%d m=%d B=%lld N=2^%d",
+                  arch.c_str(), device_cus(), dt, opt->precision, opt->refine_steps, opt->basis, opt->solver,
+                  opt->range_mode, opt->degree, (long long)batch, lg);
+    return buf;
+}
+
+bool cache_lookup(const std::string& path, const std::string& key, lsefit_schedule* s, double* ms) {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    std::ifstream in(path);
+    if (!in) return false;
+    bool found = false;
+    std::string line;
+    while (std::getline(in, line)) {
+        const size_t tab = line.find('\t');
+        if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != key.size()) continue;
+        std::istringstream vals(line.substr(tab + 1));
+        lsefit_schedule c{};
+        double t = 0.0;
+        if (vals >> c.waves >> c.waves_per_block >> c.tile >> c.unroll >> t) {
+            *s = c;
+            *ms = t;
+            found = true;
+        }
+    }
+    return found;
+}
+
+void cache_store(const std::string& path, const std::string& key, const lsefit_schedule& s, double ms) {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s\t%d %d %d %d %.6f\n", key.c_str(), s.waves, s.waves_per_block, s.tile, s.unroll, ms);
+    std::fclose(f);
+}
 
 bool same_key(const lsefit_plan::Key& a, const lsefit_plan::Key& b) {
     return a.x == b.x && a.y == b.y && a.offsets == b.offsets && a.degrees == b.degrees && a.batch == b.batch &&
@@ -680,6 +742,28 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
     hipStream_t st = (hipStream_t)stream;
     const FitDesc d{offsets, degrees, 0, batch, opt->degree};
     const Work w = carve(plan->ws, layout(plan->batch, plan->max_degree, plan->max_waves));
+    std::string key;
+    if (!plan->tune_cache.empty()) {
+        int64_t ends[2] = {0, 0};
+        if (hipMemcpyAsync(&ends[0], offsets, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&ends[1], offsets + batch, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return LSEFIT_ERR_DEVICE;
+        key = tune_key(opt, plan->dtype, batch, ends[1] - ends[0]);
+        lsefit_schedule cs{};
+        double cms = 0.0;
+        if (cache_lookup(plan->tune_cache, key, &cs, &cms) && schedule_ok(cs) &&
+            to_launch(cs).waves <= plan->max_waves) {
+            // a cached shape: one run with its schedule, no timing
+            const lsefit_status r = enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, cs, st);
+            if (r != LSEFIT_OK) return r;
+            if (hipStreamSynchronize(st) != hipSuccess) return LSEFIT_ERR_DEVICE;
+            plan->sched = cs;
+            plan->drop_graph();
+            if (best_ms_out) *best_ms_out = cms;
+            return LSEFIT_OK;
+        }
+    }
     int cus = device_cus();
     if (cus <= 0) cus = 256;
     std::vector<lsefit_schedule> cands;
@@ -725,6 +809,13 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
     plan->sched = best_s;
     plan->drop_graph();
     if (best_ms_out) *best_ms_out = best;
+    if (!key.empty()) cache_store(plan->tune_cache, key, best_s, best);
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_plan_set_tune_cache(lsefit_plan* plan, const char* path) {
+    if (!plan) return LSEFIT_ERR_INVALID_ARG;
+    plan->tune_cache = path ? path : "";
     return LSEFIT_OK;
 }
 

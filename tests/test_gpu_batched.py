@@ -123,6 +123,52 @@ def test_plan_graph_replays_match_eager():
     plan.close()
 
 
+def test_plan_tune_cache(tmp_path):
+    announce("plan tune cache")
+    rng = np.random.default_rng(12)
+    L = W.ragged_lengths(500, 16, 20_000, rng)
+    deg = rng.integers(1, 4, 500)
+    bf = W.random_batch(L, deg, seed=13, lo=-5.0, hi=5.0)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    cache = tmp_path / "schedules.txt"
+    # a miss tunes and appends one line keyed by the call's shape
+    p1 = lf.Plan(bf.batch, 3)
+    p1.set_tune_cache(str(cache))
+    ms1 = p1.tune(x, y, off, dg, reps=1)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    key, vals = lines[0].split("\t")
+    assert f"B={bf.batch} " in key and " m=3 " in key
+    w, wpb, tile, unroll, ms = vals.split()
+    assert p1.schedule == {"waves": int(w), "waves_per_block": int(wpb), "tile": int(tile), "unroll": int(unroll)}
+    assert float(ms) == pytest.approx(ms1, rel=1e-5)
+    # a hit installs the cached schedule without timing or appending
+    p2 = lf.Plan(bf.batch, 3)
+    p2.set_tune_cache(str(cache))
+    assert p2.tune(x, y, off, dg, reps=1) == pytest.approx(ms1, rel=1e-5)
+    assert p2.schedule == p1.schedule
+    assert len(cache.read_text().splitlines()) == 1
+    # the last line of a key wins; the plan then fits with that schedule
+    cus = lf.device_cus()
+    with open(cache, "a") as fh:
+        fh.write(f"{key}\t{cus * 4} 2 256 1 0.5\n")
+    p3 = lf.Plan(bf.batch, 3)
+    p3.set_tune_cache(str(cache))
+    assert p3.tune(x, y, off, dg, reps=1) == 0.5
+    assert p3.schedule == {"waves": cus * 4, "waves_per_block": 2, "tile": 256, "unroll": 1}
+    coef, status = run_batched(bf, 3, plan=p3)
+    check_against_oracle(bf, coef, status, 1e-9)
+    # another shape misses the cache and adds its own line
+    p4 = lf.Plan(bf.batch - 1, 3)
+    p4.set_tune_cache(str(cache))
+    p4.tune(x, y, off[:-1].contiguous(), dg[:-1].contiguous(), reps=1)
+    assert len(cache.read_text().splitlines()) == 3
+    p4.set_tune_cache(None)
+    for p in (p1, p2, p3, p4):
+        p.close()
+
+
 def test_graph_recaptures_when_pointers_change():
     plan = lf.Plan(3, 2)
     for seed in (10, 11):

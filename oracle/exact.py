@@ -10,6 +10,11 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   to the x-basis.  Singular means an exactly zero pivot.
 * ``normal_residual`` returns V^T r exactly, which is zero at the minimiser
   (the first-order conditions of Sec. II: dPi/da_j = -2 sum_i x_i^j r_i).
+* ``periodic_power_sums`` gives the exact power sums of points lo..hi-1 of
+  the periodic pattern x_i = (2 (i mod 1024) - 1023)/1024,
+  y_i = (i mod 1021)/1024 (the inputs of the 64-bit indexing checks) from
+  their closed form: a sum over i collapses to counts of each residue, and
+  the joint residues of (x, y) repeat every 1024 * 1021 points.
 * ``grid_power_sums`` gives exact power sums for large float inputs whose
   shifted abscissae u_i = (x_i - c)/q are integers (a float32 x in
   [1000, 1001) lies on the 2^-14 grid): the sums over points collapse to sums
@@ -163,3 +168,41 @@ def fit_exact_grid(x, y, m: int, center, scale, quantum):
     if singular:
         return None, None
     return unscale_exact(b, center, scale), b
+
+
+# --- the periodic pattern --------------------------------------------------------
+def _residue_counts(lo: int, hi: int, p: int) -> list:
+    """How many i in [lo, hi) have i mod p == r, for r = 0..p-1."""
+    def upto(n):   # counts over [0, n)
+        q, r = divmod(n, p)
+        return [q + (1 if k < r else 0) for k in range(p)]
+    a, b = upto(hi), upto(lo)
+    return [u - v for u, v in zip(a, b)]
+
+
+def periodic_power_sums(lo: int, hi: int, m: int, px: int = 1024, py: int = 1021):
+    """Exact S_0..S_2m and T_0..T_m (Sec. II sums, c = 0, s = 1) of points
+    lo..hi-1 with x_i = (2 (i mod px) - (px - 1))/px and y_i = (i mod py)/1024."""
+    if m > 3:
+        raise ValueError("the period sums below stay within int64 up to m = 3")
+    cx = _residue_counts(lo, hi, px)
+    num = [2 * a - (px - 1) for a in range(px)]          # x = num / px
+    S = [Fraction(sum(c * v ** k for c, v in zip(cx, num)), px ** k) for k in range(2 * m + 1)]
+    # T_j = sum_i (i mod py) num(i mod px)^j / (1024 px^j): one joint period of
+    # P = px py points, then the remainder, as exact integers
+    P = px * py
+    i = np.arange(P, dtype=np.int64)
+    a = i % py
+    b = 2 * (i % px) - (px - 1)
+    T = []
+    for j in range(m + 1):
+        terms = a * b ** j                                 # |terms| <= 1020 * 1023^3 < 2^41
+        pref = np.concatenate([[0], np.cumsum(terms)])     # |pref| < 2^41 * 2^20 = 2^61
+        full = int(pref[-1])
+
+        def upto(n):
+            q, r = divmod(n, P)
+            return q * full + int(pref[r])
+        T.append(Fraction(upto(hi) - upto(lo), 1024 * px ** j))
+    return S, T
+

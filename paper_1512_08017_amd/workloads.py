@@ -30,6 +30,10 @@ low orders):
 
 * ``runge``           n = 1e8 FP32, x ~ U[-1,1], y = 1/(1 + 25x^2) + N(0, 1e-3^2),
                       m = 12
+
+Inputs beyond 2^31 points (64-bit indexing) use a deterministic pattern whose
+sums have closed forms: ``periodic_points`` (x_i = (2 (i mod 1024) - 1023) /
+1024, y_i = (i mod 1021) / 1024, both exact in float32).
 """
 from __future__ import annotations
 
@@ -229,3 +233,32 @@ def random_batch(lengths, degrees, seed: int, lo=-1.0, hi=1.0, noise_sd=0.1,
     degrees = np.asarray(degrees, dtype=np.int32)
     return _batch("random_batch", lengths, degrees, seed, lo, hi, dtype, noise_sd,
                   _streams(seed), with_target=with_target)
+
+
+# --- a deterministic pattern for any size --------------------------------------
+PERIOD_X = 1024
+PERIOD_Y = 1021
+
+
+def periodic_points_np(lo: int, hi: int):
+    """Points lo..hi-1 of the periodic pattern as float32 numpy arrays."""
+    i = np.arange(lo, hi, dtype=np.int64)
+    x = ((2 * (i % PERIOD_X) - (PERIOD_X - 1)) / PERIOD_X).astype(np.float32)
+    y = ((i % PERIOD_Y) / 1024.0).astype(np.float32)
+    return x, y
+
+
+def periodic_points(n: int, device, chunk: int = 1 << 27):
+    """The first n points of the periodic pattern as float32 tensors on `device`,
+    written chunk by chunk (64-bit indices, no host copy)."""
+    import torch
+    x = torch.empty(n, dtype=torch.float32, device=device)
+    y = torch.empty(n, dtype=torch.float32, device=device)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        i = torch.arange(lo, hi, dtype=torch.int64, device=device)
+        x[lo:hi] = ((2 * (i % PERIOD_X) - (PERIOD_X - 1)).to(torch.float64) / PERIOD_X).to(torch.float32)
+        y[lo:hi] = ((i % PERIOD_Y).to(torch.float64) / 1024.0).to(torch.float32)
+        del i
+    return x, y
+

@@ -430,3 +430,27 @@ def test_adjoint_identities():
     assert abs(np.sum(g["dx"]) - trans) < 1e-9 * (np.abs(g["dx"]).sum())
     dil = -sum(k * gbar[k] * a[k] for k in range(4))
     assert abs(np.dot(fit.x, g["dx"]) - dil) < 1e-9 * (np.abs(fit.x * g["dx"]).sum())
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 3000), (1234, 4321), (1024 * 1021 - 700, 1024 * 1021 + 900)])
+def test_periodic_power_sums_match_brute_force(lo, hi):
+    """The closed form of the periodic pattern's sums (the reference of the
+    beyond-2^31 checks) equals the exact sums over the points themselves,
+    also across a joint period of the two residues."""
+    x, y = W.periodic_points_np(lo, hi)
+    S, T = exact.periodic_power_sums(lo, hi, 3)
+    S2, T2 = exact.power_sums_exact(x, y, 3)
+    assert S == S2 and T == T2
+    assert S[0] == hi - lo
+
+
+def test_periodic_power_sums_are_additive_and_symmetric():
+    """Sums over [a, c) are the sums over [a, b) plus [b, c); over whole
+    periods of x the odd power sums vanish (x takes +-v equally often)."""
+    a, b, c = 5, (1 << 31) - 3, (1 << 31) + 1_000_003
+    S1, T1 = exact.periodic_power_sums(a, b, 3)
+    S2, T2 = exact.periodic_power_sums(b, c, 3)
+    S, T = exact.periodic_power_sums(a, c, 3)
+    assert S == [u + v for u, v in zip(S1, S2)] and T == [u + v for u, v in zip(T1, T2)]
+    Sp, _ = exact.periodic_power_sums(0, 1024 * 4096, 3)
+    assert Sp[1] == Sp[3] == Sp[5] == 0 and Sp[0] == 1024 * 4096

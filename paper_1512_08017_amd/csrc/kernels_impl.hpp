@@ -921,7 +921,9 @@ struct AdjointPoint {
     }
 };
 
-template <int MAXM, typename In>
+// U vectors of x and y per lane are loaded before any is used, so that a wave
+// keeps U rounds of loads in flight (the same unroll as the power-sum pass)
+template <int MAXM, typename In, int U>
 __global__ void __launch_bounds__(256)
     k_adjoint_stream(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ gx,
                      In* __restrict__ gy, int64_t tile, int64_t W, int mis) {
@@ -952,8 +954,7 @@ __global__ void __launch_bounds__(256)
                 const V* yv = reinterpret_cast<const V*>(y + a);
                 V* gxv = reinterpret_cast<V*>(gx + a);
                 V* gyv = reinterpret_cast<V*>(gy + a);
-                for (int64_t j = lane; j < nv; j += kWave) {
-                    const V xs = ld_stream(xv + j), ys = ld_stream(yv + j);
+                auto vec = [&](const V& xs, const V& ys, int64_t j) {
                     V ox, oy;
 #pragma unroll
                     for (int e = 0; e < VW; ++e) {
@@ -964,7 +965,19 @@ __global__ void __launch_bounds__(256)
                     }
                     __builtin_nontemporal_store(ox, gxv + j);
                     __builtin_nontemporal_store(oy, gyv + j);
+                };
+                int64_t j = lane;
+                for (; j + (int64_t)(U - 1) * kWave < nv; j += (int64_t)U * kWave) {
+                    V xs[U], ys[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        xs[u] = ld_stream(xv + j + u * kWave);
+                        ys[u] = ld_stream(yv + j + u * kWave);
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) vec(xs[u], ys[u], j + u * kWave);
                 }
+                for (; j < nv; j += kWave) vec(ld_stream(xv + j), ld_stream(yv + j), j);
                 if (lane < hi - b) P.point((double)x[b + lane], (double)y[b + lane], gx[b + lane], gy[b + lane]);
             } else {
                 for (int64_t i = lo + lane; i < hi; i += kWave) P.point((double)x[i], (double)y[i], gx[i], gy[i]);
@@ -1192,12 +1205,20 @@ hipError_t Launchers<MAXM>::adjoint(const FitDesc& d, const Work& w, int solver,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid(blocks_for(L)), block(L.wpb * kWave);
-    if (dtype == LSEFIT_F32)
-        hipLaunchKernelGGL((k_adjoint_stream<MAXM, float>), grid, block, 0, st, d, w, (const float*)x,
-                           (const float*)y, (float*)gx, (float*)gy, L.tile, L.waves, mis);
-    else
-        hipLaunchKernelGGL((k_adjoint_stream<MAXM, double>), grid, block, 0, st, d, w, (const double*)x,
+#define LSEFIT_ADJ(UU)                                                                                           \
+    if (dtype == LSEFIT_F32)                                                                                     \
+        hipLaunchKernelGGL((k_adjoint_stream<MAXM, float, UU>), grid, block, 0, st, d, w, (const float*)x,      \
+                           (const float*)y, (float*)gx, (float*)gy, L.tile, L.waves, mis);                       \
+    else                                                                                                         \
+        hipLaunchKernelGGL((k_adjoint_stream<MAXM, double, UU>), grid, block, 0, st, d, w, (const double*)x,    \
                            (const double*)y, (double*)gx, (double*)gy, L.tile, L.waves, mis);
+    switch (L.unroll) {
+        case 1: LSEFIT_ADJ(1) break;
+        case 2: LSEFIT_ADJ(2) break;
+        case 4: LSEFIT_ADJ(4) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef LSEFIT_ADJ
     return hipGetLastError();
 }
 

@@ -244,6 +244,38 @@ def time_steps(runner, steps, warmup):
     return ms, wall_ms, ms_inst, kern
 
 
+def residual_pass(runner, n, steps, warmup):
+    """Times fit_residuals after the runner's fit (Table V pass): the sum of
+    squared errors alone (8 B per float32 point read) and with every residual
+    stored (8 B read + 4 B written), plus the residual kernel's own duration."""
+    import torch
+    from paper_1512_08017_amd import _lib
+    L = _lib.load()
+    vp = ctypes.c_void_p
+    x, y = runner.x, runner.y
+    sse = torch.empty(1, dtype=torch.float64, device=x.device)
+    res = torch.empty_like(x)
+    st = vp(torch.cuda.current_stream(x.device).cuda_stream)
+    out = {}
+    for name, rptr, nbytes in (("sse_only", None, 8.0 * n), ("stored", vp(res.data_ptr()), 12.0 * n)):
+        args_ = (vp(x.data_ptr()), vp(y.data_ptr()), None, None, 1, n, 0, ctypes.byref(runner.opt), None,
+                 vp(runner.ws.data_ptr()), runner.ws.numel(), vp(sse.data_ptr()), rptr, st)
+        fn = lambda: _lib.check(L.fit_residuals(*args_), "fit_residuals")
+        ms = _time(fn, steps, warmup)
+        L.lsefit_timing_reset()
+        L.lsefit_timing_enable(1)
+        _time(fn, steps, 0)
+        L.lsefit_timing_enable(0)
+        tot, cnt = ctypes.c_double(0.0), ctypes.c_int64(0)
+        _lib.check(L.lsefit_timing_read(5, ctypes.byref(tot), ctypes.byref(cnt)), "lsefit_timing_read")
+        kms = tot.value / max(cnt.value, 1)
+        out[name] = {"ms_per_call": round(ms, 5), "kernel_ms": round(kms, 5),
+                     "kernel_gbps": round(nbytes / (kms * 1e-3) / 1e9, 1),
+                     "algorithmic_bytes": int(nbytes)}
+    out["sse"] = float(sse.cpu()[0])
+    return out
+
+
 def cpu_baseline(x_np, y_np, degree, target_s):
     from oracle import c_oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
@@ -644,9 +676,13 @@ def main():
         return 0
 
     forms = {}
+    resid = None
     for prec, route in (("f64", "moments"), ("f32c", "moments"), ("qr", "qr")):
         r = SingleFitRunner(x, y, args.degree, "f64" if prec == "qr" else prec, route=route)
         ms, wall_ms, ms_inst, kern = time_steps(r, args.steps, args.warmup)
+        if prec == "f64":
+            resid = residual_pass(r, args.n, min(args.steps, 50), 5)
+            log(f"residual pass: {resid}")
         st = int(r.status.cpu()[0])
         forms[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall_ms, "instrumented_ms_per_step": ms_inst,
                        "points_per_s": args.n / (ms * 1e-3),
@@ -710,6 +746,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": {p: {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in f.items()}
                   for p, f in forms.items()},
+        "residual_pass": resid,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -1012,7 +1012,7 @@ struct ResidPoint {
 
 // one wave: points [lo, hi) of one fit (or the whole grid-stride share of a
 // single fit when `strided`), e^2 summed per lane into acc, e stored if resid
-template <int M, typename In, bool STRIDED>
+template <int M, typename In, bool STRIDED, int U>
 __device__ inline void resid_points(const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ resid,
                                     int64_t lo, int64_t hi, int mis, int64_t gwave, int64_t W,
                                     const ResidPoint<M>& P, double& acc) {
@@ -1036,8 +1036,7 @@ __device__ inline void resid_points(const In* __restrict__ x, const In* __restri
         const V* xv = reinterpret_cast<const V*>(x + a);
         const V* yv = reinterpret_cast<const V*>(y + a);
         V* rv = resid ? reinterpret_cast<V*>(resid + a) : nullptr;
-        for (int64_t j = first; j < nv; j += step) {
-            const V xs = ld_stream(xv + j), ys = ld_stream(yv + j);
+        auto vec = [&](const V& xs, const V& ys, int64_t j) {
             V os;
 #pragma unroll
             for (int e = 0; e < VW; ++e) {
@@ -1046,14 +1045,27 @@ __device__ inline void resid_points(const In* __restrict__ x, const In* __restri
                 os[e] = (In)er;
             }
             if (rv) __builtin_nontemporal_store(os, rv + j);
+        };
+        // U vectors per lane are loaded before any is used (U rounds of loads in flight)
+        int64_t j = first;
+        for (; j + (int64_t)(U - 1) * step < nv; j += (int64_t)U * step) {
+            V xs[U], ys[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                xs[u] = ld_stream(xv + j + u * step);
+                ys[u] = ld_stream(yv + j + u * step);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) vec(xs[u], ys[u], j + u * step);
         }
+        for (; j < nv; j += step) vec(ld_stream(xv + j), ld_stream(yv + j), j);
         if (edge_wave && lane < hi - b) one(b + lane);
     } else {
         for (int64_t i = lo + first; i < hi; i += step) one(i);
     }
 }
 
-template <int MAXM, typename In>
+template <int MAXM, typename In, int U>
 __global__ void __launch_bounds__(256)
     k_residual(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ resid,
                int64_t tile, int64_t W, int mis) {
@@ -1067,7 +1079,7 @@ __global__ void __launch_bounds__(256)
             if (ok) {
                 ResidPoint<M> P;
                 P.init(w.rec, MAXM);
-                resid_points<M, In, true>(x, y, resid, 0, d.n_single, mis, wave, W, P, acc);
+                resid_points<M, In, true, U>(x, y, resid, 0, d.n_single, mis, wave, W, P, acc);
             } else if (resid) {
                 for (int64_t i = wave * kWave + lane_id(); i < d.n_single; i += W * kWave) resid[i] = (In)NAN;
             }
@@ -1087,7 +1099,7 @@ __global__ void __launch_bounds__(256)
             ResidPoint<M> P;
             P.init(w.rec + f * rl, MAXM);
             double acc = 0.0;
-            resid_points<M, In, false>(x, y, resid, lo, hi, mis, 0, W, P, acc);
+            resid_points<M, In, false, U>(x, y, resid, lo, hi, mis, 0, W, P, acc);
             acc = wave_sum(acc);
             if (lane_id() == 0) w.part[slot * stride] = acc;
         };
@@ -1226,12 +1238,20 @@ template <int MAXM>
 hipError_t Launchers<MAXM>::residual(const FitDesc& d, const Work& w, int dtype, const void* x, const void* y,
                                      void* resid, const Launch& L, int mis, hipStream_t st) {
     const dim3 grid(blocks_for(L)), block(L.wpb * kWave);
-    if (dtype == LSEFIT_F32)
-        hipLaunchKernelGGL((k_residual<MAXM, float>), grid, block, 0, st, d, w, (const float*)x, (const float*)y,
-                           (float*)resid, L.tile, L.waves, mis);
-    else
-        hipLaunchKernelGGL((k_residual<MAXM, double>), grid, block, 0, st, d, w, (const double*)x, (const double*)y,
-                           (double*)resid, L.tile, L.waves, mis);
+#define LSEFIT_RES(UU)                                                                                           \
+    if (dtype == LSEFIT_F32)                                                                                     \
+        hipLaunchKernelGGL((k_residual<MAXM, float, UU>), grid, block, 0, st, d, w, (const float*)x,            \
+                           (const float*)y, (float*)resid, L.tile, L.waves, mis);                                \
+    else                                                                                                         \
+        hipLaunchKernelGGL((k_residual<MAXM, double, UU>), grid, block, 0, st, d, w, (const double*)x,          \
+                           (const double*)y, (double*)resid, L.tile, L.waves, mis);
+    switch (L.unroll) {
+        case 1: LSEFIT_RES(1) break;
+        case 2: LSEFIT_RES(2) break;
+        case 4: LSEFIT_RES(4) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef LSEFIT_RES
     return hipGetLastError();
 }
 

@@ -394,7 +394,7 @@ def bench_ragged(args):
     """65,536 ragged fits (log-uniform lengths in [16, 65536], degree 1..3): one
     persistent batched launch sequence (tuned plan, graph replay) against a
     sequence of single-fit calls, one per fit, on the same GPU; and the
-    streaming QR route over the same batch."""
+    streaming QR route and the Chebyshev basis over the same batch."""
     import numpy as np
     import torch
     import paper_1512_08017_amd as lf
@@ -437,6 +437,15 @@ def bench_ragged(args):
                  "all_ok": bool((status.cpu().numpy() == 0).all()),
                  "moments_gbps": 8.0 * P / (kern["moments"]["avg_ms"] * 1e-3) / 1e9}
     log(f"ragged qr: {out['qr']}")
+    # the Chebyshev basis over the same batch (default schedule, eager, automatic
+    # range: the exact extent of each fit in a pass over x, then the sums)
+    cheb_fn = lambda: lf.fit_batched(x, y, off, dg, 3, out=(coef, status), basis="chebyshev")
+    cheb_ms = _time(cheb_fn, args.steps, args.warmup)
+    kern = _instrumented(cheb_fn, args.steps)
+    out["chebyshev"] = {"eager_default_ms": cheb_ms, "points_per_s": P / (cheb_ms * 1e-3), "kernels": kern,
+                        "all_ok": bool((status.cpu().numpy() == 0).all()),
+                        "moments_gbps": 8.0 * P / (kern["moments"]["avg_ms"] * 1e-3) / 1e9}
+    log(f"ragged chebyshev: {out['chebyshev']}")
     # per-fit baseline: one fit_single call per fit on the same stream
     L = _lib.load()
     nfit = min(args.per_fit_limit, bf.batch)

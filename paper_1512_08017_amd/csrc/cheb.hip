@@ -123,10 +123,13 @@ __device__ inline void minmax_strided(const In* __restrict__ x, int64_t n, int m
     }
 }
 
-// x only, one wave over points [lo, hi) of a batch
+// x only, one wave over points [lo, hi) of a batch; U vectors per lane are
+// loaded before any is used (one array: four give a wave the bytes in flight
+// that two of x and y give the power-sum pass)
 template <typename In>
 __device__ inline void minmax_segment(const In* __restrict__ x, int64_t lo, int64_t hi, int mis, MinMax<In>& r) {
     constexpr int VW = VecOf<In>::W;
+    constexpr int U = 4;
     using V = typename VecOf<In>::type;
     const int lane = lane_id();
     if (mis >= 0) {
@@ -136,7 +139,15 @@ __device__ inline void minmax_segment(const In* __restrict__ x, int64_t lo, int6
         const int64_t b = a + nv * VW;
         if (lane < a - lo) r.add(ld_scalar(x + lo + lane));
         const V* __restrict__ xv = reinterpret_cast<const V*>(x + a);
-        for (int64_t j = lane; j < nv; j += kWave) r.template vec<V, VW>(ld_stream(xv + j));
+        int64_t j = lane;
+        for (; j + (int64_t)(U - 1) * kWave < nv; j += (int64_t)U * kWave) {
+            V v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = ld_stream(xv + j + u * kWave);
+#pragma unroll
+            for (int u = 0; u < U; ++u) r.template vec<V, VW>(v[u]);
+        }
+        for (; j < nv; j += kWave) r.template vec<V, VW>(ld_stream(xv + j));
         if (lane < hi - b) r.add(ld_scalar(x + b + lane));
     } else {
         for (int64_t i = lo + lane; i < hi; i += kWave) r.add(ld_scalar(x + i));

@@ -89,16 +89,30 @@ __device__ inline double wave_sum(double v) {
     return __hiloint2double(hi, lo);
 }
 
-__device__ inline double wave_min(double v) {
-#pragma unroll
-    for (int off = kWave / 2; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
-    return v;
+// the same DPP pattern for min and max; lanes of rows outside a row mask
+// receive their own value (min and max have no zero to fall back on)
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_f64_keep(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false));
 }
-__device__ inline double wave_max(double v) {
-#pragma unroll
-    for (int off = kWave / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
-    return v;
+
+template <bool MAX>
+__device__ inline double wave_extreme(double v) {
+    auto op = [](double a, double b) { return MAX ? fmax(a, b) : fmin(a, b); };
+    v = op(v, dpp_f64_keep<0xb1, 0xf>(v));
+    v = op(v, dpp_f64_keep<0x4e, 0xf>(v));
+    v = op(v, dpp_f64_keep<0x141, 0xf>(v));
+    v = op(v, dpp_f64_keep<0x140, 0xf>(v));
+    v = op(v, dpp_f64_keep<0x142, 0xa>(v));
+    v = op(v, dpp_f64_keep<0x143, 0xc>(v));
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
+__device__ inline double wave_min(double v) { return wave_extreme<false>(v); }
+__device__ inline double wave_max(double v) { return wave_extreme<true>(v); }
 
 __device__ inline int wave_id_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }

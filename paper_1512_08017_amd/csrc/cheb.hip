@@ -514,6 +514,78 @@ __global__ void __launch_bounds__(256) k_finish_cheb_batch(FitDesc d, Work w, in
     }
 }
 
+// Batch of degrees <= 4, one fit per thread: the thread sums its fit's partial
+// slots in wave order, forms C_0..C_2M (C_(M+j) = 2 E_j - C_(M-j)) and the Gram
+// system G_jk = (C_(j+k) + C_|j-k|)/2, G c = D, in its registers and solves it
+// (matrix_gepp / matrix_cholesky: the pivot and singular rules of the wave
+// solve).  At these degrees a wave per fit leaves most lanes idle and the
+// batch's small solves in a long serial chain.  Coefficient output as
+// cheb_solve_wave without write_b: c_0..c_M, then (c, s) when the stride holds
+// them.
+template <int MAXC>
+__global__ void __launch_bounds__(256) k_finish_cheb_lane(FitDesc d, Work w, int64_t W, int maxm, Finish fz) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= d.batch) return;
+    const int pst = w.pstatus[f];
+    if (pst != LSEFIT_OK) {
+        if (fz.mode != kMomentsOnly) cheb_fail(d, w, f, maxm, fz, pst);
+        return;
+    }
+    const int stride = nacc(maxm);
+    const int64_t NT = w.tile_start[d.batch];
+    const int64_t w0 = wave_of_tile(w.tile_start[f], NT, W);
+    const int64_t w1 = wave_of_tile(w.tile_start[f + 1] - 1, NT, W);
+    auto body = [&]<int M>() {
+        constexpr int N = M + 1;
+        constexpr int K = nacc(M);
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = 0.0;
+        for (int64_t wv = w0; wv <= w1; ++wv) {
+            if (!wave_owns_tiles(wv, NT, W)) continue;
+            const double* p = w.part + (wv + f) * stride;
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] += p[k];
+        }
+        double S[2 * M + 1], D[N];
+        S[0] = (double)(fit_hi(d, f) - fit_lo(d, f));
+#pragma unroll
+        for (int k = 1; k <= M; ++k) S[k] = v[k - 1];
+#pragma unroll
+        for (int j = 1; j <= M; ++j) S[M + j] = 2.0 * v[M + j - 1] - S[M - j];
+#pragma unroll
+        for (int j = 0; j <= M; ++j) D[j] = v[2 * M + j];
+        double* r = w.rec + f * rec_len(maxm);
+#pragma unroll
+        for (int k = 0; k <= 2 * M; ++k) r[rec_S(maxm) + k] = S[k];
+#pragma unroll
+        for (int j = 0; j <= M; ++j) r[rec_T(maxm) + j] = D[j];
+        if (fz.mode == kMomentsOnly) return;
+        double A[N][N + 1], X[1][N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) A[j][k] = 0.5 * (S[j + k] + S[j > k ? j - k : k - j]);
+            A[j][N] = D[j];
+        }
+        const int st = fz.solver == LSEFIT_SOLVER_CHOLESKY ? matrix_cholesky<N, 1>(A, X) : matrix_gepp<N, 1>(A, X);
+        double* out = fz.coef + f * (int64_t)fz.coef_stride;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double c = st == LSEFIT_OK ? X[0][k] : NAN;
+            out[k] = c;
+            r[rec_b(maxm) + k] = c;
+        }
+        if (st == LSEFIT_OK && fz.coef_stride >= N + 2) {
+            out[N] = r[0];
+            out[N + 1] = r[1];
+        }
+        w.pstatus[f] = st;
+        if (fz.status) fz.status[f] = st;
+    };
+    dispatch_degree<MAXC>(fit_deg(d, f), body);
+}
+
 // one fit of degree M from caller-provided sums [c, s, C_0..C_2m, D_0..D_m], one wave
 template <int M>
 __global__ void __launch_bounds__(64) k_solve_cheb_moments(const double* __restrict__ mom, Work w, Finish fz) {
@@ -606,6 +678,10 @@ hipError_t launch_finish_cheb(const FitDesc& d, const Work& w, int maxm, int64_t
             hipLaunchKernelGGL(k_finish_cheb_single<M>, dim3(1), dim3(finish_threads(W)), 0, st, d, w, W, maxm, fz);
         };
         dispatch_degree<kChebMax>(d.degree, body);
+        return hipGetLastError();
+    }
+    if (maxm <= 4 && !fz.write_b && !fz.moments_out) {
+        hipLaunchKernelGGL(k_finish_cheb_lane<4>, dim3((d.batch + 255) / 256), dim3(256), 0, st, d, w, W, maxm, fz);
         return hipGetLastError();
     }
     int64_t blocks = (d.batch + 3) / 4;

@@ -253,28 +253,25 @@ __device__ inline int64_t wave_of_tile(int64_t t, int64_t NT, int64_t W) { retur
 __device__ inline bool wave_owns_tiles(int64_t w, int64_t NT, int64_t W) { return w * NT / W < (w + 1) * NT / W; }
 
 // ---------------------------------------------------------------------------
-// Gaussian elimination with partial pivoting on A_jk = S_(j+k) (Sec. II).
-// Pivot: first row of largest magnitude.  Singular when a pivot is at most
-// 2^-40 max|A|.  N = m + 1; several right-hand sides are eliminated together.
+// Gaussian elimination with partial pivoting on an augmented normal matrix
+// [A | B] (Sec. II: A_jk = S_(j+k) in the power basis; the Gram matrix of the
+// Chebyshev basis otherwise).  Pivot: first row of largest magnitude.
+// Singular when a pivot is at most 2^-40 max|A|.  N = m + 1; several
+// right-hand sides are eliminated together.
 // ---------------------------------------------------------------------------
 template <int N, int R>
-__device__ inline int hankel_solve(const double* S, const double (&rhs)[R][N], double (&X)[R][N]) {
-    double A[N][N + R];
+__device__ inline int matrix_gepp(double (&A)[N][N + R], double (&X)[R][N]) {
     double amax = 0.0;
     bool finite = true;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            A[j][k] = S[j + k];
             finite = finite && isfinite(A[j][k]);
             amax = fmax(amax, fabs(A[j][k]));
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            A[j][N + r] = rhs[r][j];
-            finite = finite && isfinite(rhs[r][j]);
-        }
+        for (int r = 0; r < R; ++r) finite = finite && isfinite(A[j][N + r]);
     }
     if (!finite) return LSEFIT_ERR_NONFINITE;
     const double tiny = ldexp(amax, -40);
@@ -327,28 +324,30 @@ __device__ inline int hankel_solve(const double* S, const double (&rhs)[R][N], d
     return LSEFIT_OK;
 }
 
-// Cholesky (L L^T) solve of the same normal system: A_jk = S_(j+k) is symmetric
+// Cholesky (L L^T) solve of a normal system A X = B held as an augmented
+// matrix (the columns past N are the right-hand sides): A is symmetric
 // positive definite when the fit is determined, so no pivoting is needed.
 // Singular when a diagonal of the Schur complement is at most 2^-40 max|A|.
 template <int N, int R>
-__device__ inline int hankel_cholesky(const double* S, const double (&rhs)[R][N], double (&X)[R][N]) {
+__device__ inline int matrix_cholesky(const double (&A)[N][N + R], double (&X)[R][N]) {
     double Lm[N][N];
     double amax = 0.0;
     bool finite = true;
 #pragma unroll
-    for (int k = 0; k <= 2 * (N - 1); ++k) {
-        finite = finite && isfinite(S[k]);
-        amax = fmax(amax, fabs(S[k]));
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            finite = finite && isfinite(A[j][k]);
+            amax = fmax(amax, fabs(A[j][k]));
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) finite = finite && isfinite(A[j][N + r]);
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int j = 0; j < N; ++j) finite = finite && isfinite(rhs[r][j]);
     if (!finite) return LSEFIT_ERR_NONFINITE;
     const double tiny = ldexp(amax, -40);
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        double dgl = S[2 * j];
+        double dgl = A[j][j];
 #pragma unroll
         for (int k = 0; k < j; ++k) dgl -= Lm[j][k] * Lm[j][k];
         if (!(dgl > tiny)) return LSEFIT_ERR_SINGULAR;
@@ -356,7 +355,7 @@ __device__ inline int hankel_cholesky(const double* S, const double (&rhs)[R][N]
         Lm[j][j] = ljj;
 #pragma unroll
         for (int i = j + 1; i < N; ++i) {
-            double acc = S[i + j];
+            double acc = A[i][j];
 #pragma unroll
             for (int k = 0; k < j; ++k) acc -= Lm[i][k] * Lm[j][k];
             Lm[i][j] = acc / ljj;
@@ -367,7 +366,7 @@ __device__ inline int hankel_cholesky(const double* S, const double (&rhs)[R][N]
         double z[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            double acc = rhs[r][i];
+            double acc = A[i][N + r];
 #pragma unroll
             for (int k = 0; k < i; ++k) acc -= Lm[i][k] * z[k];
             z[i] = acc / Lm[i][i];
@@ -386,6 +385,32 @@ __device__ inline int hankel_cholesky(const double* S, const double (&rhs)[R][N]
         for (int i = 0; i < N; ++i)
             if (!isfinite(X[r][i])) return LSEFIT_ERR_NONFINITE;
     return LSEFIT_OK;
+}
+
+// the Hankel normal system of Sec. II, A_jk = S_(j+k), with R right-hand sides
+template <int N, int R>
+__device__ inline void hankel_assemble(const double* S, const double (&rhs)[R][N], double (&A)[N][N + R]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) A[j][k] = S[j + k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) A[j][N + r] = rhs[r][j];
+    }
+}
+
+template <int N, int R>
+__device__ inline int hankel_solve(const double* S, const double (&rhs)[R][N], double (&X)[R][N]) {
+    double A[N][N + R];
+    hankel_assemble<N, R>(S, rhs, A);
+    return matrix_gepp<N, R>(A, X);
+}
+
+template <int N, int R>
+__device__ inline int hankel_cholesky(const double* S, const double (&rhs)[R][N], double (&X)[R][N]) {
+    double A[N][N + R];
+    hankel_assemble<N, R>(S, rhs, A);
+    return matrix_cholesky<N, R>(A, X);
 }
 
 // the normal-system solve the options ask for

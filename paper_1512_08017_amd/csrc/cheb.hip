@@ -207,10 +207,11 @@ __global__ void __launch_bounds__(256) k_range_fold_single(Work w, int64_t G) {
 // batch: one (min, max) pair per (wave, fit) slot
 template <typename In>
 __global__ void __launch_bounds__(256)
-    k_range_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, int64_t tile, int64_t W, int mis) {
+    k_range_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, int64_t tile, int64_t W, int mis, int maxm) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
-    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
-        if (w.pstatus[f] != LSEFIT_OK) return;
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rec_len(maxm), tile, wave, W,
+                        [&](int64_t, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
+        if (mt.st != LSEFIT_OK) return;
         MinMax<In> r;
         minmax_segment(x, lo, hi, mis, r);
         const double a = wave_min((double)r.lo), b = wave_max((double)r.hi);
@@ -297,10 +298,11 @@ __global__ void __launch_bounds__(256)
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     const int stride = nacc(maxm);
     const int rl = rec_len(maxm);
-    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
-        if (w.pstatus[f] != LSEFIT_OK) return;
-        const double c = w.rec[f * rl + 0];
-        const double inv_s = 1.0 / w.rec[f * rl + 1];
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, tile, wave, W,
+                        [&](int64_t, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
+        if (mt.st != LSEFIT_OK) return;
+        const double c = mt.c;
+        const double inv_s = 1.0 / mt.s;
         double* __restrict__ out = w.part + slot * stride;
         auto body = [&]<int M>() {
             AccCheb<M> acc;
@@ -312,7 +314,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
                 for (int k = 0; k < nacc(M); ++k) out[k] = v[k];
         };
-        dispatch_degree<MAXC>(fit_deg(d, f), body);
+        dispatch_degree<MAXC>(mt.deg, body);
     });
 }
 
@@ -644,7 +646,7 @@ hipError_t range_cheb_typed(const FitDesc& d, const Work& w, int maxm, const In*
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_range_cheb_batch<In>), dim3(G), dim3(L.wpb * kWave), 0, st, d, w, x, L.tile, L.waves,
-                       mis);
+                       mis, maxm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_range_fold_batch, dim3((d.batch + 255) / 256), dim3(256), 0, st, d, w, L.waves, maxm);

@@ -766,11 +766,12 @@ __global__ void __launch_bounds__(256)
         dispatch_degree<MAXM>(d.degree, body);
         return;
     }
-    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
-        if (w.pstatus[f] != LSEFIT_OK) return;
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, tile, wave, W,
+                        [&](int64_t f, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
+        if (mt.st != LSEFIT_OK) return;
         const double* r = w.rec + f * rl;
-        const double c = r[0];
-        const double inv_s = 1.0 / r[1];
+        const double c = mt.c;
+        const double inv_s = 1.0 / mt.s;
         double* __restrict__ out = w.part + slot * stride;
         auto body = [&]<int M>() {
             AccRefine<M> acc;
@@ -784,7 +785,7 @@ __global__ void __launch_bounds__(256)
                 for (int k = 0; k <= M; ++k) out[k] = v[k];
             }
         };
-        dispatch_degree<MAXM>(fit_deg(d, f), body);
+        dispatch_degree<MAXM>(mt.deg, body);
     });
 }
 

@@ -116,8 +116,9 @@ typedef enum { LSEFIT_SOLVER_GEPP = 0, LSEFIT_SOLVER_CHOLESKY = 1 } lsefit_solve
  *      coefficients in t) followed by a_0..a_m (x-basis); batched fits write
  *      c_0..c_m and, when coef_stride >= m + 3, the fit's center and scale.
  *      fit_moments writes [c, s, C_0..C_2m, D_0..D_m] (same length 3m+4) and
- *      fit_solve reads that layout.  fit_backward and fit_residuals do not
- *      take this basis (UNSUPPORTED). */
+ *      fit_solve reads that layout.  fit_residuals evaluates the fitted
+ *      series by Clenshaw's recurrence; fit_backward does not take this basis
+ *      (UNSUPPORTED). */
 typedef enum { LSEFIT_BASIS_MONOMIAL = 0, LSEFIT_BASIS_CHEBYSHEV = 1 } lsefit_basis;
 
 typedef struct lsefit_options {
@@ -274,7 +275,8 @@ lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets,
  * (Sec. III), e_i = y_i - f(x_i), and the sum of squared errors Pi = sum e_i^2
  * of Sec. II, per fit.  Must follow a fit on the same workspace (or plan), with
  * the same x, y and options: the per-fit (c, s) and t-basis coefficients are
- * read from there, and e_i is formed in the t variable in float64.
+ * read from there, and e_i is formed in the t variable in float64 (Chebyshev
+ * basis: f = sum_j c_j T_j(t) by Clenshaw's recurrence).
  *  offsets:    NULL -> one fit of n points (after fit_single or fit_solve;
  *              degrees and batch ignored); else the batch of fit_batched
  *  sse:        output, device float64 [batch] (or [1]); NaN for fits whose

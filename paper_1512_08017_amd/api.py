@@ -266,12 +266,12 @@ def residuals(x, y, result: FitResult, store: bool = False):
 
 
 def residuals_batched(x, y, offsets, degrees, max_degree: int, ws=None, plan=None, store: bool = False,
-                      precision: str = "f64", center=None, scale=None, solver: str = "gepp"):
+                      precision: str = "f64", center=None, scale=None, solver: str = "gepp", basis: str = "monomial"):
     """Per-fit sums of squared residuals after fit_batched on the same workspace or plan."""
     _check_batch(x, y, offsets, degrees)
     L = _lib.load()
     B = degrees.numel()
-    o = options(max_degree, precision, 0, center, scale, solver)
+    o = options(max_degree, precision, 0, center, scale, solver, basis)
     sse = torch.empty(B, dtype=torch.float64, device=x.device)
     res = torch.empty_like(x) if store else None
     check(L.fit_residuals(_ptr(x), _ptr(y), _ptr(offsets), _ptr(degrees), B, x.numel(), _DT[x.dtype],

@@ -644,7 +644,6 @@ lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets
                             int64_t batch, int64_t n, lsefit_dtype dt, const lsefit_options* opt, lsefit_plan* plan,
                             void* ws, size_t ws_bytes, double* sse, void* residuals, void* stream) {
     if (!x || !y || !sse || !opts_ok(opt, dt, offsets != nullptr)) return LSEFIT_ERR_INVALID_ARG;
-    if (chebyshev(opt)) return LSEFIT_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     const int mis = common_mis(dt, {x, y, residuals});
     if (!offsets) {
@@ -655,6 +654,12 @@ lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets
         const FitDesc d{nullptr, nullptr, n, 1, opt->degree};
         const Work w = carve(ws, lay);
         const Launch L = to_launch(sched);
+        if (chebyshev(opt)) {
+            LSEFIT_TRY(timed(kTimeResidual, st, [&] {
+                return launch_residual_cheb(d, w, opt->degree, dt, x, y, residuals, sse, L, mis, st);
+            }));
+            return LSEFIT_OK;
+        }
         const Finish fz{kSSE, sse, 1, 0, nullptr, nullptr, opt->solver};
         LSEFIT_TRY(timed(kTimeResidual, st,
                          [&] { return launch_residual(d, w, opt->degree, dt, x, y, residuals, L, mis, st); }));
@@ -677,6 +682,12 @@ lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets
         w = carve(ws, lay);
     }
     const Launch L = to_launch(sched);
+    if (chebyshev(opt)) {
+        LSEFIT_TRY(timed(kTimeResidual, st, [&] {
+            return launch_residual_cheb(d, w, opt->degree, dt, x, y, residuals, sse, L, mis, st);
+        }));
+        return LSEFIT_OK;
+    }
     const Finish fz{kSSE, sse, 1, 0, nullptr, nullptr, opt->solver};
     LSEFIT_TRY(timed(kTimeResidual, st,
                      [&] { return launch_residual(d, w, opt->degree, dt, x, y, residuals, L, mis, st); }));

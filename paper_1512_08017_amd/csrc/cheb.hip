@@ -588,6 +588,118 @@ __global__ void __launch_bounds__(256) k_finish_cheb_lane(FitDesc d, Work w, int
     dispatch_degree<MAXC>(fit_deg(d, f), body);
 }
 
+// ---------------------------------------------------------------------------
+// residuals (Table V's errors at any degree): e = y - f(t) with
+// f = sum_j c_j T_j(t) by Clenshaw's recurrence b_j = c_j + 2t b_(j+1) - b_(j+2),
+// f = c_0 + t b_1 - b_2, in float64 in the t variable; the point loop is the
+// monomial residual pass's.  Partial sums of e^2: one per block (single fit)
+// or per (wave, fit) slot, one double each.
+// ---------------------------------------------------------------------------
+template <int M>
+struct ChebResidPoint {
+    double cf[M + 1];
+    double inv_s, nc;
+    __device__ inline void init(const double* r, int maxm) {
+        inv_s = 1.0 / r[1];
+        nc = -r[0] * inv_s;
+#pragma unroll
+        for (int j = 0; j <= M; ++j) cf[j] = r[rec_b(maxm) + j];
+    }
+    __device__ inline double err(double xv, double yv) const {
+        const double t = fma(xv, inv_s, nc);
+        const double t2 = t + t;
+        double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+        for (int j = M; j >= 1; --j) {
+            const double b0 = fma(t2, b1, cf[j] - b2);
+            b2 = b1;
+            b1 = b0;
+        }
+        return yv - fma(t, b1, cf[0] - b2);
+    }
+};
+
+template <typename In, int U, int M>
+__global__ void __launch_bounds__(256)
+    k_residual_cheb_single(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y,
+                           In* __restrict__ resid, int64_t W, int mis, int maxm) {
+    __shared__ double sh[4];
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    double acc = 0.0;
+    if (w.pstatus[0] == LSEFIT_OK) {
+        ChebResidPoint<M> P;
+        P.init(w.rec, maxm);
+        resid_points<ChebResidPoint<M>, In, true, U>(x, y, resid, 0, d.n_single, mis, wave, W, P, acc);
+    } else if (resid) {
+        for (int64_t i = wave * kWave + lane_id(); i < d.n_single; i += W * kWave) resid[i] = (In)NAN;
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) sh[wave_id_in_block()] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int i = 1; i < (int)(blockDim.x / kWave); ++i) t += sh[i];
+        w.part[blockIdx.x] = t;
+    }
+}
+
+template <typename In, int U, int MAXC>
+__global__ void __launch_bounds__(256)
+    k_residual_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y,
+                          In* __restrict__ resid, int64_t tile, int64_t W, int mis, int maxm) {
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    const int rl = rec_len(maxm);
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, tile, wave, W,
+                        [&](int64_t f, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
+        if (mt.st != LSEFIT_OK) {
+            if (resid)
+                for (int64_t i = lo + lane_id(); i < hi; i += kWave) resid[i] = (In)NAN;
+            return;
+        }
+        auto body = [&]<int M>() {
+            ChebResidPoint<M> P;
+            P.init(w.rec + f * rl, maxm);
+            double acc = 0.0;
+            resid_points<ChebResidPoint<M>, In, false, U>(x, y, resid, lo, hi, mis, 0, W, P, acc);
+            acc = wave_sum(acc);
+            if (lane_id() == 0) w.part[slot] = acc;
+        };
+        dispatch_degree<MAXC>(mt.deg, body);
+    });
+}
+
+// sse of a single fit: one block sums the G block partials in a fixed order
+__global__ void __launch_bounds__(256) k_sse_fold_single(Work w, int64_t G, double* __restrict__ sse) {
+    __shared__ double sh[4];
+    double t = 0.0;
+    for (int64_t g = threadIdx.x; g < G; g += blockDim.x) t += w.part[g];
+    t = wave_sum(t);
+    if (lane_id() == 0) sh[wave_id_in_block()] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = sh[0];
+        for (int i = 1; i < (int)(blockDim.x / kWave); ++i) s += sh[i];
+        sse[0] = w.pstatus[0] == LSEFIT_OK ? s : NAN;
+    }
+}
+
+// sse of each fit of a batch: one thread per fit sums its slots in wave order
+__global__ void __launch_bounds__(256) k_sse_fold_batch(FitDesc d, Work w, int64_t W, double* __restrict__ sse) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= d.batch) return;
+    if (w.pstatus[f] != LSEFIT_OK) {
+        sse[f] = NAN;
+        return;
+    }
+    const int64_t NT = w.tile_start[d.batch];
+    const int64_t w0 = wave_of_tile(w.tile_start[f], NT, W);
+    const int64_t w1 = wave_of_tile(w.tile_start[f + 1] - 1, NT, W);
+    double s = 0.0;
+    for (int64_t wv = w0; wv <= w1; ++wv)
+        if (wave_owns_tiles(wv, NT, W)) s += w.part[wv + f];
+    sse[f] = s;
+}
+
 // one fit of degree M from caller-provided sums [c, s, C_0..C_2m, D_0..D_m], one wave
 template <int M>
 __global__ void __launch_bounds__(64) k_solve_cheb_moments(const double* __restrict__ mom, Work w, Finish fz) {
@@ -671,6 +783,46 @@ hipError_t launch_solve_cheb_moments(const double* moments, const Work& w, int m
     auto body = [&]<int M>() { hipLaunchKernelGGL(k_solve_cheb_moments<M>, dim3(1), dim3(kWave), 0, st, moments, w, fz); };
     dispatch_degree<kChebMax>(m, body);
     return hipGetLastError();
+}
+
+template <typename In, int U>
+hipError_t residual_cheb_typed(const FitDesc& d, const Work& w, int maxm, const In* x, const In* y, In* resid,
+                               double* sse, const Launch& L, int mis, hipStream_t st) {
+    const int64_t G = L.waves / L.wpb;
+    const dim3 grid(G), block(L.wpb * kWave);
+    if (is_single(d)) {
+        auto body = [&]<int M>() {
+            hipLaunchKernelGGL((k_residual_cheb_single<In, U, M>), grid, block, 0, st, d, w, x, y, resid, L.waves,
+                               mis, maxm);
+        };
+        dispatch_degree<kChebMax>(d.degree, body);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sse_fold_single, dim3(1), dim3(256), 0, st, w, G, sse);
+        return hipGetLastError();
+    }
+    if (maxm <= 4)
+        hipLaunchKernelGGL((k_residual_cheb_batch<In, U, 4>), grid, block, 0, st, d, w, x, y, resid, L.tile, L.waves,
+                           mis, maxm);
+    else if (maxm <= 8)
+        hipLaunchKernelGGL((k_residual_cheb_batch<In, U, 8>), grid, block, 0, st, d, w, x, y, resid, L.tile, L.waves,
+                           mis, maxm);
+    else
+        hipLaunchKernelGGL((k_residual_cheb_batch<In, U, kChebMax>), grid, block, 0, st, d, w, x, y, resid, L.tile,
+                           L.waves, mis, maxm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sse_fold_batch, dim3((d.batch + 255) / 256), dim3(256), 0, st, d, w, L.waves, sse);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_cheb(const FitDesc& d, const Work& w, int maxm, int dtype, const void* x, const void* y,
+                                void* resid, double* sse, const Launch& L, int mis, hipStream_t st) {
+    if (dtype == LSEFIT_F32)
+        return residual_cheb_typed<float, 2>(d, w, maxm, (const float*)x, (const float*)y, (float*)resid, sse, L,
+                                             mis, st);
+    return residual_cheb_typed<double, 2>(d, w, maxm, (const double*)x, (const double*)y, (double*)resid, sse, L,
+                                          mis, st);
 }
 
 hipError_t launch_finish_cheb(const FitDesc& d, const Work& w, int maxm, int64_t W, const Finish& fz,

@@ -98,6 +98,10 @@ hipError_t launch_finish_cheb(const FitDesc& d, const Work& w, int maxm, int64_t
                               hipStream_t st);
 hipError_t launch_solve_cheb_moments(const double* moments, const Work& w, int m, const Finish& fz,
                                     hipStream_t st);
+// residuals of Chebyshev-basis fits: e = y - sum_j c_j T_j(t) per point
+// (optionally stored) and sse[f] = sum e^2 (NaN for fits whose status is not OK)
+hipError_t launch_residual_cheb(const FitDesc& d, const Work& w, int maxm, int dtype, const void* x, const void* y,
+                                void* resid, double* sse, const Launch& L, int mis, hipStream_t st);
 
 // Streaming QR of one fit (degree d.degree): per-block factors into w.part,
 // then one block merges them, solves and writes [a | b], the status and info.

@@ -1013,10 +1013,10 @@ struct ResidPoint {
 
 // one wave: points [lo, hi) of one fit (or the whole grid-stride share of a
 // single fit when `strided`), e^2 summed per lane into acc, e stored if resid
-template <int M, typename In, bool STRIDED, int U>
+template <class PT, typename In, bool STRIDED, int U>
 __device__ inline void resid_points(const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ resid,
                                     int64_t lo, int64_t hi, int mis, int64_t gwave, int64_t W,
-                                    const ResidPoint<M>& P, double& acc) {
+                                    const PT& P, double& acc) {
     constexpr int VW = VecOf<In>::W;
     using V = typename VecOf<In>::type;
     const int lane = lane_id();
@@ -1080,7 +1080,7 @@ __global__ void __launch_bounds__(256)
             if (ok) {
                 ResidPoint<M> P;
                 P.init(w.rec, MAXM);
-                resid_points<M, In, true, U>(x, y, resid, 0, d.n_single, mis, wave, W, P, acc);
+                resid_points<ResidPoint<M>, In, true, U>(x, y, resid, 0, d.n_single, mis, wave, W, P, acc);
             } else if (resid) {
                 for (int64_t i = wave * kWave + lane_id(); i < d.n_single; i += W * kWave) resid[i] = (In)NAN;
             }
@@ -1100,7 +1100,7 @@ __global__ void __launch_bounds__(256)
             ResidPoint<M> P;
             P.init(w.rec + f * rl, MAXM);
             double acc = 0.0;
-            resid_points<M, In, false, U>(x, y, resid, lo, hi, mis, 0, W, P, acc);
+            resid_points<ResidPoint<M>, In, false, U>(x, y, resid, lo, hi, mis, 0, W, P, acc);
             acc = wave_sum(acc);
             if (lane_id() == 0) w.part[slot * stride] = acc;
         };

@@ -134,8 +134,10 @@ def test_null_pointers_rejected():
     cheb = _opt(basis=1)
     assert L.fit_backward(FAKE, FAKE, FAKE, FAKE, 10, _lib.F32, ctypes.byref(cheb), None, FAKE, 1 << 30, FAKE, 4,
                           FAKE, FAKE, None) == _lib.UNSUPPORTED     # no adjoint for the Chebyshev basis
-    assert L.fit_residuals(FAKE, FAKE, None, None, 1, 100, _lib.F32, ctypes.byref(cheb), None, FAKE, 1 << 30,
-                           FAKE, None, None) == _lib.UNSUPPORTED
+    assert L.fit_residuals(FAKE, FAKE, None, None, 1, 100, _lib.F32, ctypes.byref(cheb), None, FAKE, 8,
+                           FAKE, None, None) == _lib.WORKSPACE      # Chebyshev residuals are taken; ws too small
+    assert L.fit_residuals(FAKE, FAKE, None, None, 1, 12, _lib.F32, ctypes.byref(_opt(basis=1, degree=12)), None,
+                           FAKE, 1 << 30, FAKE, None, None) == _lib.INVALID_ARG   # n < m + 1
     h = ctypes.c_void_p()
     assert L.fit_plan_create(ctypes.byref(h), 10, 17, _lib.F32, 0) == _lib.INVALID_ARG
     L.fit_plan_destroy(None)

@@ -271,3 +271,60 @@ def test_batched_plan_graph_replays():
         assert np.max(np.abs(got[ok] - eager[ok]) / np.maximum(np.abs(eager[ok]), 1e-300)) <= 1e-12
     assert np.array_equal(status.cpu().numpy(), est.cpu().numpy())
     plan.close()
+
+
+# --- residuals (Table V's errors) of Chebyshev-basis fits ------------------------
+def residual_reference(x, y, c, center, scale):
+    """e = y - sum_j c_j T_j(t) in float64 from the oracle's coefficients."""
+    t = (np.asarray(x, dtype=np.float64) - center) / scale
+    T = cheb.cheb_values(t, len(c) - 1)
+    f = sum(cj * Tj for cj, Tj in zip(c, T))
+    return np.asarray(y, dtype=np.float64) - f
+
+
+@pytest.mark.parametrize("m,auto", [(3, False), (12, False), (16, True)])
+def test_residuals_single(m, auto):
+    announce(f"chebyshev residuals m={m} auto={auto}")
+    wl = W.runge(n=40_009, seed=300 + m, dtype=np.float32)
+    x, y = to_dev(wl.x), to_dev(wl.y)
+    kw = {} if auto else {"center": 0.0, "scale": 1.0}
+    res = lf.fit(x, y, m, basis="chebyshev", **kw)
+    sse, e = lf.residuals(x, y, res, store=True)
+    torch.cuda.synchronize()
+    c0, s0 = (cheb.cheb_range(wl.x) if auto else (0.0, 1.0))
+    assert (res.center, res.scale) == (c0, s0)
+    ref = cheb.fit_cheb(wl.x, wl.y, m, c0, s0)
+    e_ref = residual_reference(wl.x, wl.y, ref["c"], c0, s0)
+    e_gpu = e.cpu().numpy().astype(np.float64)
+    ymax = float(np.max(np.abs(wl.y)))
+    # e is stored in the input dtype (float32): one rounding of e on top of the
+    # coefficient gate
+    assert np.all(np.abs(e_gpu - e_ref) <= TOL * ymax + 2.0 ** -23 * np.abs(e_ref))
+    sse_ref = float(np.sum(e_ref * e_ref))
+    assert abs(float(sse.cpu()[0]) - sse_ref) <= 1e-9 * sse_ref
+
+
+def test_residuals_batched():
+    announce("chebyshev residuals, batched")
+    rng = np.random.default_rng(14)
+    lengths = [200, 300, 4_097, 20_000, 2, 9_999]
+    deg = np.array([16, 5, 12, 2, 3, 8], dtype=np.int32)
+    bf = W.random_batch(lengths, deg, seed=15, lo=-3.0, hi=7.0, dtype=np.float64)
+    x, y, off, dg = to_dev(bf.x), to_dev(bf.y), to_dev(bf.offsets), to_dev(bf.degrees)
+    coef, status, ws = lf.fit_batched(x, y, off, dg, 16, basis="chebyshev", coef_stride=19)
+    sse, e = lf.residuals_batched(x, y, off, dg, 16, ws=ws, store=True, basis="chebyshev")
+    torch.cuda.synchronize()
+    status, sse, e = status.cpu().numpy(), sse.cpu().numpy(), e.cpu().numpy()
+    for f in range(bf.batch):
+        lo, hi = int(bf.offsets[f]), int(bf.offsets[f + 1])
+        if status[f] != 0:
+            assert np.isnan(sse[f]) and np.isnan(e[lo:hi]).all()
+            continue
+        c0, s0 = cheb.cheb_range(bf.x[lo:hi])
+        ref = cheb.fit_cheb(bf.x[lo:hi], bf.y[lo:hi], int(deg[f]), c0, s0)
+        e_ref = residual_reference(bf.x[lo:hi], bf.y[lo:hi], ref["c"], c0, s0)
+        ymax = float(np.max(np.abs(bf.y[lo:hi])))
+        assert np.max(np.abs(e[lo:hi] - e_ref)) <= TOL * ymax, f
+        sse_ref = float(np.sum(e_ref * e_ref))
+        assert abs(sse[f] - sse_ref) <= 1e-9 * max(sse_ref, ymax * ymax * 1e-12), f
+    assert status[4] != 0     # two points cannot determine a cubic

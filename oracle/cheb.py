@@ -17,6 +17,14 @@ V_ij = T_j(t_i) the normal equations read G c = V^T y, G = V^T V.
 * ``cheb_to_monomial``: c -> b with sum_j c_j T_j(t) = sum_k b_k t^k, from the
   recurrence applied to coefficient vectors.
 * ``cheb_range``: the (c, s) that put the data's extent on [-1, 1].
+* ``cheb_gradients``: dL/dx and dL/dy of a scalar loss L(c) of the Chebyshev
+  coefficients, for a given (c, s).  With lambda = G^-1 dL/dc (G symmetric),
+  dL/dD = lambda and dL/dG = -lambda c^T; since D_j = sum_i y_i T_j(t_i) and
+  G_jk = sum_i T_j(t_i) T_k(t_i),
+    dL/dy_i = q(t_i),  dL/dt_i = q'(t_i) (y_i - f(t_i)) - q(t_i) f'(t_i),
+  with f = sum_j c_j T_j, q = sum_j lambda_j T_j, and dL/dx_i = dL/dt_i / s.
+  T_j' = j U_(j-1) with the second-kind U_0 = 1, U_1 = 2t,
+  U_(k+1) = 2t U_k - U_(k-1).
 """
 from __future__ import annotations
 
@@ -105,3 +113,33 @@ def fit_cheb_exact(xs, ys, m: int, center=0, scale=1):
     r = [sum((row[j] * yy for row, yy in zip(cols, yv)), Fraction(0)) for j in range(m + 1)]
     c, singular = exact.gepp_exact(G, r)
     return None if singular else c
+
+
+def cheb_derivative_values(t, m: int) -> list:
+    """[T_0'(t), .., T_m'(t)] for an array t (float64), T_j' = j U_(j-1)."""
+    t = np.asarray(t, dtype=np.float64)
+    U = [np.ones_like(t), 2.0 * t]
+    for k in range(1, m):
+        U.append(2.0 * t * U[k] - U[k - 1])
+    return [np.zeros_like(t)] + [j * U[j - 1] for j in range(1, m + 1)]
+
+
+def cheb_gradients(x, y, m: int, gbar, center: float = 0.0, scale: float = 1.0) -> dict:
+    """Gradients of L with dL/dc = gbar through the Chebyshev-basis fit (float64)."""
+    t = fp64.change_of_variable(x, center, scale)
+    yv = np.asarray(y, dtype=np.float64)
+    T = cheb_values(t, m)
+    dT = cheb_derivative_values(t, m)
+    G = [[math.fsum((T[j] * T[k]).tolist()) for k in range(m + 1)] for j in range(m + 1)]
+    r = [math.fsum((T[j] * yv).tolist()) for j in range(m + 1)]
+    c, st = fp64.gepp(G, r)
+    lam, st2 = fp64.gepp(G, [float(g) for g in gbar])
+    if st != fp64.OK or st2 != fp64.OK:
+        return {"status": st if st != fp64.OK else st2}
+    f = sum(cj * Tj for cj, Tj in zip(c, T))
+    fp = sum(cj * dTj for cj, dTj in zip(c, dT))
+    q = sum(lj * Tj for lj, Tj in zip(lam, T))
+    qp = sum(lj * dTj for lj, dTj in zip(lam, dT))
+    return {"gx": (qp * (yv - f) - q * fp) / scale, "gy": q, "lam": np.array(lam), "c": np.array(c),
+            "status": fp64.OK}
+

@@ -102,3 +102,58 @@ def test_cheb_range_maps_extent_onto_unit_interval():
         assert (f.min() - c) / s == -1.0 and (f.max() - c) / s == 1.0
     assert cheb.cheb_range(np.full(5, 2.5)) == (2.5, 1.0)
     assert cheb.cheb_range(np.array([np.nan, np.inf])) == (0.0, 1.0)
+
+
+def test_cheb_derivative_values_closed_form():
+    """T_j'(cos th) = j sin(j th) / sin(th)."""
+    th = np.linspace(0.1, 3.0, 23)
+    dT = cheb.cheb_derivative_values(np.cos(th), 9)
+    for j in range(10):
+        assert np.allclose(dT[j], j * np.sin(j * th) / np.sin(th), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("m", [1, 4, 9])
+def test_cheb_gradients_against_autograd(m):
+    """The closed-form adjoint equals torch's float64 reverse mode through the
+    fit's definition (Gram matrix V^T V, right side V^T y, linear solve)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(20 + m)
+    n = 300
+    x = rng.uniform(-2.0, 3.0, n)
+    y = np.cos(x) + 0.1 * rng.standard_normal(n)
+    gbar = rng.standard_normal(m + 1)
+    c0, s0 = 0.5, 2.5
+    got = cheb.cheb_gradients(x, y, m, gbar, c0, s0)
+    xt = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    yt = torch.tensor(y, dtype=torch.float64, requires_grad=True)
+    t = (xt - c0) / s0
+    cols = [torch.ones_like(t), t]
+    for k in range(1, m):
+        cols.append(2 * t * cols[k] - cols[k - 1])
+    V = torch.stack(cols[: m + 1], dim=1)
+    c = torch.linalg.solve(V.T @ V, V.T @ yt)
+    (c @ torch.tensor(gbar, dtype=torch.float64)).backward()
+    assert np.allclose(got["c"], c.detach().numpy(), rtol=1e-10, atol=1e-12)
+    for g, ref in ((got["gx"], xt.grad.numpy()), (got["gy"], yt.grad.numpy())):
+        assert np.max(np.abs(g - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
+def test_cheb_gradients_against_finite_differences():
+    """Central differences of L(c(x, y)) on a few inputs."""
+    rng = np.random.default_rng(31)
+    n, m = 120, 6
+    x = rng.uniform(-1.0, 1.0, n)
+    y = x ** 3 - x + 0.05 * rng.standard_normal(n)
+    gbar = rng.standard_normal(m + 1)
+    got = cheb.cheb_gradients(x, y, m, gbar)
+
+    def loss(xx, yy):
+        return float(np.dot(gbar, cheb.fit_cheb(xx, yy, m)["c"]))
+    h = 1e-6
+    for i in (0, 17, 63, 119):
+        for arr, g in ((x, got["gx"]), (y, got["gy"])):
+            up, dn = arr.copy(), arr.copy()
+            up[i] += h
+            dn[i] -= h
+            num = (loss(up, y) - loss(dn, y)) / (2 * h) if arr is x else (loss(x, up) - loss(x, dn)) / (2 * h)
+            assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, num, g[i])

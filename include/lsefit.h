@@ -117,8 +117,10 @@ typedef enum { LSEFIT_SOLVER_GEPP = 0, LSEFIT_SOLVER_CHOLESKY = 1 } lsefit_solve
  *      c_0..c_m and, when coef_stride >= m + 3, the fit's center and scale.
  *      fit_moments writes [c, s, C_0..C_2m, D_0..D_m] (same length 3m+4) and
  *      fit_solve reads that layout.  fit_residuals evaluates the fitted
- *      series by Clenshaw's recurrence; fit_backward does not take this basis
- *      (UNSUPPORTED). */
+ *      series by Clenshaw's recurrence.  fit_backward takes grad_coef =
+ *      dL/dc of the Chebyshev coefficients and needs the range given
+ *      (LSEFIT_RANGE_GIVEN; with the automatic range the coefficients also
+ *      move with the extreme x: UNSUPPORTED). */
 typedef enum { LSEFIT_BASIS_MONOMIAL = 0, LSEFIT_BASIS_CHEBYSHEV = 1 } lsefit_basis;
 
 typedef struct lsefit_options {
@@ -262,9 +264,12 @@ lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, 
  *   dL/dy_i = q(t_i),  dL/dx_i = (q'(t_i) r_i - q(t_i) f'(t_i)) / s
  * with q(t) = sum_j lambda_j t^j, f(t) = sum_j b_j t^j, r_i = y_i - f(t_i),
  * powers recomputed per point (nothing per point is stored by the forward).
- * Points of fits whose status is not OK get NaN.  `plan`/`ws` must be the ones
- * the forward call used, unchanged since (the per-fit records and the tile
- * table are read from there); lambda is written into that workspace. */
+ * Chebyshev basis (range given): lambda = G^-1 dL/dc with the forward's Gram
+ * matrix, q = sum_j lambda_j T_j and f = sum_j c_j T_j (Clenshaw's recurrence
+ * and its derivative).  Points of fits whose status is not OK get NaN.
+ * `plan`/`ws` must be the ones the forward call used, unchanged since (the
+ * per-fit records and the tile table are read from there); lambda is written
+ * into that workspace. */
 lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
                            int64_t batch, lsefit_dtype dt, const lsefit_options* opt,
                            lsefit_plan* plan, void* ws, size_t ws_bytes,

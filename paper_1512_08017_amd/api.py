@@ -380,12 +380,13 @@ def fit_batched(x, y, offsets, degrees, max_degree: int, precision: str = "f64",
 
 
 def fit_backward(x, y, offsets, degrees, max_degree, grad_coef, ws=None, plan=None, precision="f64",
-                 center=None, scale=None, solver="gepp"):
-    """dL/dx, dL/dy from dL/da (grad_coef [B, stride] float64) after fit_batched."""
+                 center=None, scale=None, solver="gepp", basis="monomial"):
+    """dL/dx, dL/dy from dL/da (grad_coef [B, stride] float64) after fit_batched; for
+    basis="chebyshev" (given center and scale) grad_coef is dL/dc of the Chebyshev coefficients."""
     _check_batch(x, y, offsets, degrees)
     L = _lib.load()
     B = degrees.numel()
-    o = options(max_degree, precision, 0, center, scale, solver)
+    o = options(max_degree, precision, 0, center, scale, solver, basis)
     grad_coef = grad_coef.to(torch.float64).contiguous()
     gx = torch.empty_like(x)
     gy = torch.empty_like(y)
@@ -398,26 +399,30 @@ def fit_backward(x, y, offsets, degrees, max_degree, grad_coef, ws=None, plan=No
 
 class LseFit(torch.autograd.Function):
     """Differentiable batched fit: coef = LseFit.apply(x, y, offsets, degrees, max_degree, precision,
-    center, scale).  The backward is the library's adjoint kernel."""
+    center, scale, basis).  The backward is the library's adjoint kernel (the Chebyshev basis
+    needs a given center and scale)."""
 
     @staticmethod
-    def forward(ctx, x, y, offsets, degrees, max_degree, precision="f64", center=None, scale=None):
-        coef, status, ws = fit_batched(x, y, offsets, degrees, max_degree, precision, 1, center, scale)
+    def forward(ctx, x, y, offsets, degrees, max_degree, precision="f64", center=None, scale=None,
+                basis="monomial"):
+        coef, status, ws = fit_batched(x, y, offsets, degrees, max_degree, precision, 1, center, scale,
+                                       basis=basis)
         ctx.save_for_backward(x, y, offsets, degrees)
         ctx.ws = ws
-        ctx.cfg = (max_degree, precision, center, scale)
+        ctx.cfg = (max_degree, precision, center, scale, basis)
         ctx.status = status
         return coef
 
     @staticmethod
     def backward(ctx, grad_coef):
         x, y, offsets, degrees = ctx.saved_tensors
-        max_degree, precision, center, scale = ctx.cfg
+        max_degree, precision, center, scale, basis = ctx.cfg
         gx, gy = fit_backward(x, y, offsets, degrees, max_degree, grad_coef, ws=ctx.ws, precision=precision,
-                              center=center, scale=scale)
-        return gx, gy, None, None, None, None, None, None
+                              center=center, scale=scale, basis=basis)
+        return gx, gy, None, None, None, None, None, None, None
 
 
-def lsefit(x, y, offsets, degrees, max_degree: int, precision: str = "f64", center=None, scale=None):
+def lsefit(x, y, offsets, degrees, max_degree: int, precision: str = "f64", center=None, scale=None,
+           basis: str = "monomial"):
     """Differentiable batched fit (autograd through the hand-written adjoint)."""
-    return LseFit.apply(x, y, offsets, degrees, max_degree, precision, center, scale)
+    return LseFit.apply(x, y, offsets, degrees, max_degree, precision, center, scale, basis)

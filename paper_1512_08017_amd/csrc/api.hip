@@ -616,7 +616,9 @@ lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets,
     if (batch == 0) return LSEFIT_OK;
     if (!x || !y || !offsets || !degrees || !grad_coef || !grad_x || !grad_y) return LSEFIT_ERR_INVALID_ARG;
     if (coef_stride < opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
-    if (chebyshev(opt)) return LSEFIT_ERR_UNSUPPORTED;
+    // the Chebyshev coefficients depend on (c, s); with the automatic range
+    // those follow the extreme x, which this adjoint holds fixed
+    if (chebyshev(opt) && opt->range_mode != LSEFIT_RANGE_GIVEN) return LSEFIT_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     const FitDesc d{offsets, degrees, 0, batch, opt->degree};
     Work w;
@@ -632,6 +634,13 @@ lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets,
         w = carve(ws, lay);
     }
     const int mis = common_mis(dt, {x, y, grad_x, grad_y});
+    if (chebyshev(opt)) {
+        LSEFIT_TRY(timed(kTimeAdjoint, st, [&] {
+            return launch_adjoint_cheb(d, w, opt->degree, opt->solver, dt, x, y, grad_coef, coef_stride, grad_x,
+                                       grad_y, to_launch(sched), mis, st);
+        }));
+        return LSEFIT_OK;
+    }
     LSEFIT_TRY(timed(kTimeAdjoint, st, [&] {
         return launch_adjoint(d, w, opt->degree, opt->solver, dt, x, y, grad_coef, coef_stride, grad_x, grad_y,
                               to_launch(sched),

@@ -785,6 +785,157 @@ hipError_t launch_solve_cheb_moments(const double* moments, const Work& w, int m
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// adjoint of a batch in the Chebyshev basis with a given range: per fit
+// lambda = G^-1 dL/dc (one wave per fit, the wave solve of the forward's Gram
+// system from its stored sums), then per point
+//   dL/dy = q(t),  dL/dx = (q'(t) (y - f(t)) - q(t) f'(t)) / s,
+// f = sum_j c_j T_j and q = sum_j lambda_j T_j with their derivatives, all by
+// Clenshaw's recurrence b_j = a_j + 2t b_(j+1) - b_(j+2) and its derivative
+// b_j' = 2 b_(j+1) + 2t b_(j+1)' - b_(j+2)'; value a_0 + t b_1 - b_2,
+// derivative b_1 + t b_1' - b_2'.
+// ---------------------------------------------------------------------------
+template <int MAXC>
+__global__ void __launch_bounds__(256)
+    k_adjoint_cheb_solve(FitDesc d, Work w, int maxm, int solver, const double* __restrict__ gcoef,
+                         int32_t coef_stride) {
+    const int wid = wave_id_in_block(), lane = lane_id();
+    for (int64_t f = (int64_t)blockIdx.x * 4 + wid; f < d.batch; f += (int64_t)gridDim.x * 4) {
+        if (w.pstatus[f] != LSEFIT_OK) continue;
+        double* r = w.rec + f * rec_len(maxm);
+        const double* S = r + rec_S(maxm);
+        auto body = [&]<int M>() {
+            constexpr int N = M + 1;
+            const bool mine = lane < N;
+            double row[M + 2];
+            bool finite = true;
+#pragma unroll
+            for (int c = 0; c <= N; ++c) row[c] = 0.0;
+            if (mine) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    const int dk = lane > c ? lane - c : c - lane;
+                    row[c] = 0.5 * (S[lane + c] + S[dk]);
+                    finite = finite && isfinite(row[c]);
+                }
+                row[N] = gcoef[f * (int64_t)coef_stride + lane];
+                finite = finite && isfinite(row[N]);
+            }
+            double lam = 0.0;
+            int st = __ballot(!finite) ? LSEFIT_ERR_NONFINITE
+                                       : (solver == LSEFIT_SOLVER_CHOLESKY ? wave_cholesky<M>(row, lam)
+                                                                           : wave_gepp<M>(row, lam));
+            if (st == LSEFIT_OK && __ballot(mine && !isfinite(lam))) st = LSEFIT_ERR_NONFINITE;
+            if (mine) r[rec_lam(maxm) + lane] = st == LSEFIT_OK ? lam : NAN;
+        };
+        dispatch_degree<MAXC>(fit_deg(d, f), body);
+    }
+}
+
+template <int M, typename In>
+struct ChebAdjointPoint {
+    double cf[M + 1], lam[M + 1];
+    double inv_s, nc;
+    __device__ inline void init(const double* r, int maxm) {
+        inv_s = 1.0 / r[1];
+        nc = -r[0] * inv_s;
+#pragma unroll
+        for (int j = 0; j <= M; ++j) {
+            cf[j] = r[rec_b(maxm) + j];
+            lam[j] = r[rec_lam(maxm) + j];
+        }
+    }
+    __device__ inline void point(double xv, double yv, In& gx, In& gy) const {
+        const double t = fma(xv, inv_s, nc);
+        const double t2 = t + t;
+        double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0;   // f's recurrence and its derivative
+        double p1 = 0.0, p2 = 0.0, e1 = 0.0, e2 = 0.0;   // q's
+#pragma unroll
+        for (int j = M; j >= 1; --j) {
+            const double b0 = fma(t2, b1, cf[j] - b2);
+            const double d0 = fma(t2, d1, 2.0 * b1 - d2);
+            const double p0 = fma(t2, p1, lam[j] - p2);
+            const double e0 = fma(t2, e1, 2.0 * p1 - e2);
+            b2 = b1;
+            b1 = b0;
+            d2 = d1;
+            d1 = d0;
+            p2 = p1;
+            p1 = p0;
+            e2 = e1;
+            e1 = e0;
+        }
+        const double f = fma(t, b1, cf[0] - b2), fp = fma(t, d1, b1 - d2);
+        const double q = fma(t, p1, lam[0] - p2), qp = fma(t, e1, p1 - e2);
+        gx = (In)((qp * (yv - f) - q * fp) * inv_s);
+        gy = (In)q;
+    }
+};
+
+template <typename In, int U, int MAXC>
+__global__ void __launch_bounds__(256)
+    k_adjoint_cheb_stream(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y,
+                          In* __restrict__ gx, In* __restrict__ gy, int64_t tile, int64_t W, int mis, int maxm) {
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    const int rl = rec_len(maxm);
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, tile, wave, W,
+                        [&](int64_t f, int64_t lo, int64_t hi, int64_t, const SegMeta& mt) {
+        if (mt.st != LSEFIT_OK) {
+            adjoint_nan(gx, gy, lo, hi);
+            return;
+        }
+        auto body = [&]<int M>() {
+            ChebAdjointPoint<M, In> P;
+            P.init(w.rec + f * rl, maxm);
+            adjoint_segment<U>(P, x, y, gx, gy, lo, hi, mis);
+        };
+        dispatch_degree<MAXC>(mt.deg, body);
+    });
+}
+
+template <typename In, int MAXC>
+hipError_t adjoint_cheb_typed(const FitDesc& d, const Work& w, int maxm, const In* x, const In* y, In* gx, In* gy,
+                              const Launch& L, int mis, hipStream_t st) {
+    const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
+    switch (L.unroll) {
+        case 1: hipLaunchKernelGGL((k_adjoint_cheb_stream<In, 1, MAXC>), grid, block, 0, st, d, w, x, y, gx, gy, L.tile, L.waves, mis, maxm); break;
+        case 2: hipLaunchKernelGGL((k_adjoint_cheb_stream<In, 2, MAXC>), grid, block, 0, st, d, w, x, y, gx, gy, L.tile, L.waves, mis, maxm); break;
+        case 4: hipLaunchKernelGGL((k_adjoint_cheb_stream<In, 4, MAXC>), grid, block, 0, st, d, w, x, y, gx, gy, L.tile, L.waves, mis, maxm); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_cheb(const FitDesc& d, const Work& w, int maxm, int solver, int dtype, const void* x,
+                               const void* y, const double* grad_coef, int32_t coef_stride, void* gx, void* gy,
+                               const Launch& L, int mis, hipStream_t st) {
+    int64_t blocks = (d.batch + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    if (maxm <= 4)
+        hipLaunchKernelGGL(k_adjoint_cheb_solve<4>, dim3(blocks), dim3(256), 0, st, d, w, maxm, solver, grad_coef,
+                           coef_stride);
+    else if (maxm <= 8)
+        hipLaunchKernelGGL(k_adjoint_cheb_solve<8>, dim3(blocks), dim3(256), 0, st, d, w, maxm, solver, grad_coef,
+                           coef_stride);
+    else
+        hipLaunchKernelGGL(k_adjoint_cheb_solve<kChebMax>, dim3(blocks), dim3(256), 0, st, d, w, maxm, solver,
+                           grad_coef, coef_stride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define LSEFIT_ADJC(T, MC) \
+    return adjoint_cheb_typed<T, MC>(d, w, maxm, (const T*)x, (const T*)y, (T*)gx, (T*)gy, L, mis, st);
+    if (dtype == LSEFIT_F32) {
+        if (maxm <= 4) LSEFIT_ADJC(float, 4)
+        if (maxm <= 8) LSEFIT_ADJC(float, 8)
+        LSEFIT_ADJC(float, kChebMax)
+    }
+    if (maxm <= 4) LSEFIT_ADJC(double, 4)
+    if (maxm <= 8) LSEFIT_ADJC(double, 8)
+    LSEFIT_ADJC(double, kChebMax)
+#undef LSEFIT_ADJC
+}
+
 template <typename In, int U>
 hipError_t residual_cheb_typed(const FitDesc& d, const Work& w, int maxm, const In* x, const In* y, In* resid,
                                double* sse, const Launch& L, int mis, hipStream_t st) {

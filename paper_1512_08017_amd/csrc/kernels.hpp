@@ -102,6 +102,11 @@ hipError_t launch_solve_cheb_moments(const double* moments, const Work& w, int m
 // (optionally stored) and sse[f] = sum e^2 (NaN for fits whose status is not OK)
 hipError_t launch_residual_cheb(const FitDesc& d, const Work& w, int maxm, int dtype, const void* x, const void* y,
                                 void* resid, double* sse, const Launch& L, int mis, hipStream_t st);
+// adjoint of a Chebyshev-basis batch with a given range: lambda = G^-1 dL/dc per
+// fit, then dL/dx and dL/dy per point (NaN for fits whose status is not OK)
+hipError_t launch_adjoint_cheb(const FitDesc& d, const Work& w, int maxm, int solver, int dtype, const void* x,
+                               const void* y, const double* grad_coef, int32_t coef_stride, void* gx, void* gy,
+                               const Launch& L, int mis, hipStream_t st);
 
 // Streaming QR of one fit (degree d.degree): per-block factors into w.part,
 // then one block merges them, solves and writes [a | b], the status and info.

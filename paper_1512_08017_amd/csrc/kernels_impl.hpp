@@ -922,67 +922,81 @@ struct AdjointPoint {
     }
 };
 
-// U vectors of x and y per lane are loaded before any is used, so that a wave
-// keeps U rounds of loads in flight (the same unroll as the power-sum pass)
+// one wave: dL/dx and dL/dy of the points [lo, hi) of one fit through the
+// point rule P (P.point(x, y, gx, gy)); U vectors of x and y per lane are
+// loaded before any is used, so that a wave keeps U rounds of loads in flight
+// (the same unroll as the power-sum pass)
+template <int U, typename In, class PT>
+__device__ inline void adjoint_segment(const PT& P, const In* __restrict__ x, const In* __restrict__ y,
+                                       In* __restrict__ gx, In* __restrict__ gy, int64_t lo, int64_t hi, int mis) {
+    constexpr int VW = VecOf<In>::W;
+    using V = typename VecOf<In>::type;
+    const int lane = lane_id();
+    if (mis >= 0) {
+        int64_t a = lo + (int64_t)((VW - (int)((lo + mis) % VW)) % VW);
+        if (a > hi) a = hi;
+        const int64_t nv = (hi - a) / VW;
+        const int64_t b = a + nv * VW;
+        if (lane < a - lo) P.point((double)x[lo + lane], (double)y[lo + lane], gx[lo + lane], gy[lo + lane]);
+        const V* xv = reinterpret_cast<const V*>(x + a);
+        const V* yv = reinterpret_cast<const V*>(y + a);
+        V* gxv = reinterpret_cast<V*>(gx + a);
+        V* gyv = reinterpret_cast<V*>(gy + a);
+        auto vec = [&](const V& xs, const V& ys, int64_t j) {
+            V ox, oy;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                In gxe, gye;
+                P.point((double)xs[e], (double)ys[e], gxe, gye);
+                ox[e] = gxe;
+                oy[e] = gye;
+            }
+            __builtin_nontemporal_store(ox, gxv + j);
+            __builtin_nontemporal_store(oy, gyv + j);
+        };
+        int64_t j = lane;
+        for (; j + (int64_t)(U - 1) * kWave < nv; j += (int64_t)U * kWave) {
+            V xs[U], ys[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                xs[u] = ld_stream(xv + j + u * kWave);
+                ys[u] = ld_stream(yv + j + u * kWave);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) vec(xs[u], ys[u], j + u * kWave);
+        }
+        for (; j < nv; j += kWave) vec(ld_stream(xv + j), ld_stream(yv + j), j);
+        if (lane < hi - b) P.point((double)x[b + lane], (double)y[b + lane], gx[b + lane], gy[b + lane]);
+    } else {
+        for (int64_t i = lo + lane; i < hi; i += kWave) P.point((double)x[i], (double)y[i], gx[i], gy[i]);
+    }
+}
+
+// fits whose status is not OK get NaN gradients
+template <typename In>
+__device__ inline void adjoint_nan(In* __restrict__ gx, In* __restrict__ gy, int64_t lo, int64_t hi) {
+    for (int64_t i = lo + lane_id(); i < hi; i += kWave) {
+        gx[i] = (In)NAN;
+        gy[i] = (In)NAN;
+    }
+}
+
 template <int MAXM, typename In, int U>
 __global__ void __launch_bounds__(256)
     k_adjoint_stream(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ gx,
                      In* __restrict__ gy, int64_t tile, int64_t W, int mis) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     constexpr int rl = rec_len(MAXM);
-    constexpr int VW = VecOf<In>::W;
-    using V = typename VecOf<In>::type;
-    const int lane = lane_id();
     walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t) {
         if (w.pstatus[f] != LSEFIT_OK) {
-            for (int64_t i = lo + lane; i < hi; i += kWave) {
-                gx[i] = (In)NAN;
-                gy[i] = (In)NAN;
-            }
+            adjoint_nan(gx, gy, lo, hi);
             return;
         }
         const double* r = w.rec + f * rl;
         auto body = [&]<int M>() {
             AdjointPoint<M, In> P;
             P.init(r, MAXM);
-            if (mis >= 0) {
-                int64_t a = lo + (int64_t)((VW - (int)((lo + mis) % VW)) % VW);
-                if (a > hi) a = hi;
-                const int64_t nv = (hi - a) / VW;
-                const int64_t b = a + nv * VW;
-                if (lane < a - lo) P.point((double)x[lo + lane], (double)y[lo + lane], gx[lo + lane], gy[lo + lane]);
-                const V* xv = reinterpret_cast<const V*>(x + a);
-                const V* yv = reinterpret_cast<const V*>(y + a);
-                V* gxv = reinterpret_cast<V*>(gx + a);
-                V* gyv = reinterpret_cast<V*>(gy + a);
-                auto vec = [&](const V& xs, const V& ys, int64_t j) {
-                    V ox, oy;
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) {
-                        In gxe, gye;
-                        P.point((double)xs[e], (double)ys[e], gxe, gye);
-                        ox[e] = gxe;
-                        oy[e] = gye;
-                    }
-                    __builtin_nontemporal_store(ox, gxv + j);
-                    __builtin_nontemporal_store(oy, gyv + j);
-                };
-                int64_t j = lane;
-                for (; j + (int64_t)(U - 1) * kWave < nv; j += (int64_t)U * kWave) {
-                    V xs[U], ys[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        xs[u] = ld_stream(xv + j + u * kWave);
-                        ys[u] = ld_stream(yv + j + u * kWave);
-                    }
-#pragma unroll
-                    for (int u = 0; u < U; ++u) vec(xs[u], ys[u], j + u * kWave);
-                }
-                for (; j < nv; j += kWave) vec(ld_stream(xv + j), ld_stream(yv + j), j);
-                if (lane < hi - b) P.point((double)x[b + lane], (double)y[b + lane], gx[b + lane], gy[b + lane]);
-            } else {
-                for (int64_t i = lo + lane; i < hi; i += kWave) P.point((double)x[i], (double)y[i], gx[i], gy[i]);
-            }
+            adjoint_segment<U>(P, x, y, gx, gy, lo, hi, mis);
         };
         dispatch_degree<MAXM>(fit_deg(d, f), body);
     });

@@ -328,3 +328,54 @@ def test_residuals_batched():
         sse_ref = float(np.sum(e_ref * e_ref))
         assert abs(sse[f] - sse_ref) <= 1e-9 * max(sse_ref, ymax * ymax * 1e-12), f
     assert status[4] != 0     # two points cannot determine a cubic
+
+
+# --- adjoint of Chebyshev-basis batches (given range) ----------------------------
+@pytest.mark.parametrize("dtype,solver,autograd", [(np.float64, "gepp", True), (np.float32, "gepp", False),
+                                                   (np.float64, "cholesky", False)])
+def test_adjoint_against_oracle(dtype, solver, autograd):
+    announce(f"chebyshev adjoint {np.dtype(dtype).name} {solver} autograd={autograd}")
+    lengths = [4096, 1000, 257, 3000, 2]
+    deg = np.array([12, 3, 1, 16, 2], dtype=np.int32)
+    bf = W.random_batch(lengths, deg, seed=40, lo=-1.5, hi=2.5, dtype=dtype)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    c0, s0 = 0.5, 2.0
+    rng = np.random.default_rng(41)
+    weights = rng.standard_normal((bf.batch, 17))
+    for f in range(bf.batch):
+        weights[f, int(deg[f]) + 1:] = 0.0
+    w = torch.from_numpy(weights).to(off.device)
+    if autograd:
+        # L = sum_f sum_j w_fj c_fj through torch's autograd and the library's adjoint
+        x = to_dev(bf.x).requires_grad_(True)
+        y = to_dev(bf.y).requires_grad_(True)
+        coef = lf.lsefit(x, y, off, dg, 16, center=c0, scale=s0, basis="chebyshev")
+        (torch.nan_to_num(coef) * w).sum().backward()
+        gx, gy = x.grad, y.grad
+    else:
+        x, y = to_dev(bf.x), to_dev(bf.y)
+        _, _, ws = lf.fit_batched(x, y, off, dg, 16, center=c0, scale=s0, basis="chebyshev", solver=solver)
+        gx, gy = lf.fit_backward(x, y, off, dg, 16, w, ws=ws, center=c0, scale=s0, solver=solver,
+                                 basis="chebyshev")
+    torch.cuda.synchronize()
+    gx, gy = gx.cpu().numpy(), gy.cpu().numpy()
+    tol = 1e-5 if dtype == np.float32 else 1e-9
+    for f in range(bf.batch):
+        lo, hi = int(bf.offsets[f]), int(bf.offsets[f + 1])
+        m = int(deg[f])
+        if hi - lo < m + 1:
+            assert np.isnan(gx[lo:hi]).all() and np.isnan(gy[lo:hi]).all()
+            continue
+        ref = cheb.cheb_gradients(bf.x[lo:hi], bf.y[lo:hi], m, weights[f, : m + 1], c0, s0)
+        assert normwise(gx[lo:hi], ref["gx"]) <= tol, f
+        assert normwise(gy[lo:hi], ref["gy"]) <= tol, f
+
+
+def test_adjoint_automatic_range_is_unsupported():
+    bf = W.random_batch([100], [3], seed=42)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    _, _, ws = lf.fit_batched(x, y, off, dg, 3, basis="chebyshev")
+    with pytest.raises(lf.LsefitError):
+        lf.fit_backward(x, y, off, dg, 3, torch.ones(1, 4, dtype=torch.float64, device=x.device), ws=ws,
+                        basis="chebyshev")

@@ -515,7 +515,21 @@ def bench_grad(args):
     per_ms = _time(per_fit, 1, 1)
     fwd_bytes = 8.0 * P
     bwd_bytes = 16.0 * P
+    # the same step in the Chebyshev basis (range given: x lies in [-1, 1])
+    cstate = {}
+
+    def fwd_bwd_cheb():
+        coef, status, ws = lf.fit_batched(x, y, off, dg, 2, ws=cstate.get("ws"), center=0.0, scale=1.0,
+                                          basis="chebyshev")
+        cstate["ws"] = ws
+        lf.fit_backward(x, y, off, dg, 2, 2.0 * (coef - target), ws=ws, center=0.0, scale=1.0, basis="chebyshev")
+
+    cheb_ms = _time(fwd_bwd_cheb, args.steps, args.warmup)
+    ckern = _instrumented(fwd_bwd_cheb, args.steps)
+    cheb = {"ms_per_step": cheb_ms, "points_per_s": P / (cheb_ms * 1e-3), "kernels": ckern,
+            "adjoint_gbps": bwd_bytes / (ckern["adjoint"]["avg_ms"] * 1e-3) / 1e9}
     return {"workload": f"grad_batch: {bf.batch} fits x 4096 float32 points, m=2, forward + adjoint",
+            "chebyshev": cheb,
             "points": P, "ms_per_step": ms, "points_per_s": P / (ms * 1e-3),
             "per_call": _cold_warm(fwd_bwd, 20),
             "step_gbps": (fwd_bytes + bwd_bytes) / (ms * 1e-3) / 1e9, "kernels": kern,

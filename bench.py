@@ -472,6 +472,13 @@ def bench_ragged(args):
     per_ms = _time(per_fit, 1, 1)
     out["per_fit_launches"] = {"fits": nfit, "points": pts, "ms": per_ms, "points_per_s": pts / (per_ms * 1e-3),
                                "ms_per_fit": per_ms / nfit}
+    # the plain-C float64 oracle over the whole batch on the host's threads
+    from oracle import c_oracle
+    t0 = time.perf_counter()
+    c_oracle.fit_batched(bf.x, bf.y, bf.offsets, bf.degrees)
+    cpu_s = time.perf_counter() - t0
+    out["cpu_baseline"] = {"value": P / cpu_s, "unit": "points/s", "cores": c_oracle.max_threads(), "kind": "oracle",
+                           "sample": f"one pass of the plain-C float64 oracle over all {bf.batch} fits, {cpu_s:.2f} s"}
     best = out["f64"]
     out["speedup_vs_per_fit"] = best["points_per_s"] / out["per_fit_launches"]["points_per_s"]
     return out
@@ -524,12 +531,23 @@ def bench_grad(args):
         cstate["ws"] = ws
         lf.fit_backward(x, y, off, dg, 2, 2.0 * (coef - target), ws=ws, center=0.0, scale=1.0, basis="chebyshev")
 
+    # the float64 adjoint oracle (NumPy, one thread) on the first 64 fits
+    from oracle import adjoint
+    coef, _, _ = lf.fit_batched(x, y, off, dg, 2)
+    gbar = (2.0 * (coef - target)).cpu().numpy()
+    nf = min(64, bf.batch)
+    t0 = time.perf_counter()
+    for f in range(nf):
+        adjoint.gradients(bf.x[f * 4096:(f + 1) * 4096], bf.y[f * 4096:(f + 1) * 4096], 2, gbar[f, :3])
+    cpu_s = time.perf_counter() - t0
+    cpu = {"value": nf * 4096 / cpu_s, "unit": "points/s", "cores": 1, "kind": "oracle",
+           "sample": f"forward fit + adjoint of the float64 oracle on {nf} fits, {cpu_s:.2f} s"}
     cheb_ms = _time(fwd_bwd_cheb, args.steps, args.warmup)
     ckern = _instrumented(fwd_bwd_cheb, args.steps)
     cheb = {"ms_per_step": cheb_ms, "points_per_s": P / (cheb_ms * 1e-3), "kernels": ckern,
             "adjoint_gbps": bwd_bytes / (ckern["adjoint"]["avg_ms"] * 1e-3) / 1e9}
     return {"workload": f"grad_batch: {bf.batch} fits x 4096 float32 points, m=2, forward + adjoint",
-            "chebyshev": cheb,
+            "chebyshev": cheb, "cpu_baseline": cpu,
             "points": P, "ms_per_step": ms, "points_per_s": P / (ms * 1e-3),
             "per_call": _cold_warm(fwd_bwd, 20),
             "step_gbps": (fwd_bytes + bwd_bytes) / (ms * 1e-3) / 1e9, "kernels": kern,

@@ -276,8 +276,49 @@ def residual_pass(runner, n, steps, warmup):
     return out
 
 
-def cpu_baseline(x_np, y_np, degree, target_s):
+# ---------------------------------------------------------------------------
+# CPU baseline leg: the oracle, timed on the host's cores; its coefficients are
+# also the reference the GPU forms are checked against (the oracle never runs
+# on the measured GPU path)
+# ---------------------------------------------------------------------------
+def cheb_cpu_baseline(x_np, y_np, m, given):
+    """One Chebyshev-basis oracle fit on [-1, 1] (given) or on the exact extent
+    of x (automatic): (oracle result, seconds, threads it used)."""
+    from oracle import c_oracle, cheb
+    c0, s0 = (0.0, 1.0) if given else cheb.cheb_range(x_np)
+    t0 = time.perf_counter()
+    ref = c_oracle.cheb_fit(x_np, y_np, m, c0, s0)
+    return ref, time.perf_counter() - t0, c_oracle.max_threads()
+
+
+def ragged_cpu_baseline(bf):
+    """The plain-C float64 oracle over the whole ragged batch on the host's threads."""
     from oracle import c_oracle
+    t0 = time.perf_counter()
+    c_oracle.fit_batched(bf.x, bf.y, bf.offsets, bf.degrees)
+    cpu_s = time.perf_counter() - t0
+    return {"value": bf.total_points / cpu_s, "unit": "points/s", "cores": c_oracle.max_threads(), "kind": "oracle",
+            "sample": f"one pass of the plain-C float64 oracle over all {bf.batch} fits, {cpu_s:.2f} s"}
+
+
+def grad_cpu_baseline(bf, gbar, nf=64):
+    """The float64 adjoint oracle (NumPy, one thread): forward fit + adjoint of
+    the first nf 4,096-point fits of the gradient batch, with upstream gbar."""
+    from oracle import adjoint
+    nf = min(nf, bf.batch)
+    t0 = time.perf_counter()
+    for f in range(nf):
+        adjoint.gradients(bf.x[f * 4096:(f + 1) * 4096], bf.y[f * 4096:(f + 1) * 4096], 2, gbar[f, :3])
+    cpu_s = time.perf_counter() - t0
+    return {"value": nf * 4096 / cpu_s, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"forward fit + adjoint of the float64 oracle on {nf} fits, {cpu_s:.2f} s"}
+
+
+def cpu_baseline(x_np, y_np, degree, target_s, timed=True):
+    """(baseline record or None, oracle result); untimed: one oracle pass for the reference only."""
+    from oracle import c_oracle
+    if not timed:
+        return None, c_oracle.fit(x_np, y_np, degree)
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     t0 = time.perf_counter()
     reps = 0
@@ -472,13 +513,7 @@ def bench_ragged(args):
     per_ms = _time(per_fit, 1, 1)
     out["per_fit_launches"] = {"fits": nfit, "points": pts, "ms": per_ms, "points_per_s": pts / (per_ms * 1e-3),
                                "ms_per_fit": per_ms / nfit}
-    # the plain-C float64 oracle over the whole batch on the host's threads
-    from oracle import c_oracle
-    t0 = time.perf_counter()
-    c_oracle.fit_batched(bf.x, bf.y, bf.offsets, bf.degrees)
-    cpu_s = time.perf_counter() - t0
-    out["cpu_baseline"] = {"value": P / cpu_s, "unit": "points/s", "cores": c_oracle.max_threads(), "kind": "oracle",
-                           "sample": f"one pass of the plain-C float64 oracle over all {bf.batch} fits, {cpu_s:.2f} s"}
+    out["cpu_baseline"] = ragged_cpu_baseline(bf)
     best = out["f64"]
     out["speedup_vs_per_fit"] = best["points_per_s"] / out["per_fit_launches"]["points_per_s"]
     return out
@@ -531,17 +566,8 @@ def bench_grad(args):
         cstate["ws"] = ws
         lf.fit_backward(x, y, off, dg, 2, 2.0 * (coef - target), ws=ws, center=0.0, scale=1.0, basis="chebyshev")
 
-    # the float64 adjoint oracle (NumPy, one thread) on the first 64 fits
-    from oracle import adjoint
     coef, _, _ = lf.fit_batched(x, y, off, dg, 2)
-    gbar = (2.0 * (coef - target)).cpu().numpy()
-    nf = min(64, bf.batch)
-    t0 = time.perf_counter()
-    for f in range(nf):
-        adjoint.gradients(bf.x[f * 4096:(f + 1) * 4096], bf.y[f * 4096:(f + 1) * 4096], 2, gbar[f, :3])
-    cpu_s = time.perf_counter() - t0
-    cpu = {"value": nf * 4096 / cpu_s, "unit": "points/s", "cores": 1, "kind": "oracle",
-           "sample": f"forward fit + adjoint of the float64 oracle on {nf} fits, {cpu_s:.2f} s"}
+    cpu = grad_cpu_baseline(bf, (2.0 * (coef - target)).cpu().numpy())
     cheb_ms = _time(fwd_bwd_cheb, args.steps, args.warmup)
     ckern = _instrumented(fwd_bwd_cheb, args.steps)
     cheb = {"ms_per_step": cheb_ms, "points_per_s": P / (cheb_ms * 1e-3), "kernels": ckern,
@@ -597,7 +623,6 @@ def bench_runge(args):
     HBM and the float64 vector roofline, and the error against the C oracle."""
     import numpy as np
     import torch
-    from oracle import c_oracle, cheb
     from paper_1512_08017_amd import workloads as W
     dev = torch.device("cuda:0")
     wl = W.runge()
@@ -610,10 +635,7 @@ def bench_runge(args):
         r = SingleFitRunner(x, y, m, "f64", basis="chebyshev", **kw)
         ms, wall, ms_inst, kern = time_steps(r, args.steps, args.warmup)
         c_gpu = r.coef[: m + 1].cpu().numpy()
-        c0, s0 = (0.0, 1.0) if mode == "given" else cheb.cheb_range(wl.x)
-        t0 = time.perf_counter()
-        ref = c_oracle.cheb_fit(wl.x, wl.y, m, c0, s0)
-        cpu_s = time.perf_counter() - t0
+        ref, cpu_s, cpu_threads = cheb_cpu_baseline(wl.x, wl.y, m, given=(mode == "given"))
         mk = kern["moments"]["avg_ms"] * 1e-3
         gbps = 8.0 * n / mk / 1e9
         tflops = cheb_flops_per_point(m) * n / mk / 1e12
@@ -622,7 +644,7 @@ def bench_runge(args):
                      "moments_fp64_tflops": tflops, "moments_fp64_frac": tflops / FP64_VECTOR_PEAK_TFLOPS,
                      "status": int(r.status.cpu()[0]),
                      "max_rel_coef_err": float(np.max(np.abs(c_gpu - ref["c"])) / np.max(np.abs(ref["c"]))),
-                     "cpu_oracle_points_per_s": n / cpu_s, "cpu_oracle_threads": c_oracle.max_threads()}
+                     "cpu_oracle_points_per_s": n / cpu_s, "cpu_oracle_threads": cpu_threads}
         log(f"runge {mode}: {json.dumps(out[mode])}")
     return out
 
@@ -732,15 +754,11 @@ def main():
                        "per_call": _cold_warm(r.step, 20)}
         log(f"{prec}: {ms:.4f} ms/step, {forms[prec]['points_per_s']:.3e} points/s, kernels {kern}")
 
-    cpu = None
-    ref = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        cpu, ref = cpu_baseline(wl.x, wl.y, args.degree, args.cpu_seconds)
+    cpu, ref = cpu_baseline(wl.x, wl.y, args.degree, args.cpu_seconds, timed=not args.no_cpu_baseline)
+    if cpu is not None:
         log(f"cpu oracle {cpu['value']:.3e} points/s on {cpu['cores']} threads")
-    else:
-        from oracle import c_oracle
-        ref = c_oracle.fit(wl.x, wl.y, args.degree)
     for prec, f in forms.items():
         a = f.pop("coef")
         f["max_rel_coef_err"] = float(np.max(np.abs(a - ref["a"])) / np.max(np.abs(ref["a"])))

@@ -11,43 +11,48 @@
 // Per point the pass forms T_2..T_m by the three-term recurrence
 // T_(k+1) = 2 t T_k - T_(k-1) and accumulates C_1..C_m, D_0..D_m and
 // E_j = sum_i T_m(t_i) T_j(t_i) (j = 1..m); the upper sums follow from the same
-// identity, C_(m+j) = 2 E_j - C_(m-j).  That is 4m+2 float64 operations per
-// point instead of the 5m+2 of running the recurrence up to T_2m.
+// identity, C_(m+j) = 2 E_j - C_(m-j).  That is 4m+1 float64 operations per
+// point instead of the 5m+2 of running the recurrence up to T_2m: the pass
+// runs the recurrence on V_k = 2 T_k, V_(k+1) = (2t) V_k - V_(k-1) with
+// V_1 = 2t and V_2 = (2t)^2 - 2, which needs 2t alone (one FMA from x) and
+// is exactly twice T_k in floating point too (scaling by two commutes with
+// rounding), so the sums come out exact multiples 2 or 4 of the T sums and
+// are scaled back once per wave.
 #include "kernels_impl.hpp"
 
 namespace lsefit {
 
 constexpr int kChebMax = LSEFIT_MAX_DEGREE_CHEBYSHEV;
 
-// partial sums of one lane: [C_1..C_M, E_1..E_M, D_0..D_M] (nacc(M) values)
+// partial sums of one lane: [2 C_1..2 C_M, 4 E_1..4 E_M, D_0, 2 D_1..2 D_M]
+// (nacc(M) values; cheb_wave_sums scales them back)
 template <int M>
 struct AccCheb {
-    double C[M];       // C_1..C_M
-    double E[M];       // E_1..E_M
-    double D[M + 1];   // D_0..D_M
-    double inv_s, nc;
+    double C[M];       // sum V_1..V_M
+    double E[M];       // sum V_M V_1..V_M V_M
+    double D[M + 1];   // sum y, sum y V_1..y V_M
+    double two_inv_s, two_nc;
     __device__ inline void init(double c, double is) {
 #pragma unroll
         for (int k = 0; k < M; ++k) C[k] = E[k] = 0.0;
 #pragma unroll
         for (int j = 0; j <= M; ++j) D[j] = 0.0;
-        inv_s = is;
-        nc = -c * is;
+        two_inv_s = 2.0 * is;
+        two_nc = -2.0 * (c * is);
     }
     __device__ inline void point(double xv, double yv) {
-        const double t = fma(xv, inv_s, nc);
-        const double t2 = t + t;
-        double T[M + 1];
-        T[0] = 1.0;
-        T[1] = t;
+        const double t2 = fma(xv, two_inv_s, two_nc);  // 2t
+        double V[M + 1];
+        V[1] = t2;
+        if constexpr (M >= 2) V[2] = fma(t2, t2, -2.0);
 #pragma unroll
-        for (int k = 2; k <= M; ++k) T[k] = fma(t2, T[k - 1], -T[k - 2]);
+        for (int k = 3; k <= M; ++k) V[k] = fma(t2, V[k - 1], -V[k - 2]);
         D[0] += yv;
 #pragma unroll
         for (int k = 1; k <= M; ++k) {
-            C[k - 1] += T[k];
-            D[k] = fma(yv, T[k], D[k]);
-            E[k - 1] = fma(T[M], T[k], E[k - 1]);
+            C[k - 1] += V[k];
+            D[k] = fma(yv, V[k], D[k]);
+            E[k - 1] = fma(V[M], V[k], E[k - 1]);
         }
     }
     template <typename V, int VW>
@@ -257,15 +262,85 @@ __device__ inline void cheb_block_partial(const Work& w, const double (&v)[K]) {
     }
 }
 
+// the wave's [C_1..C_M, E_1..E_M, D_0..D_M] (the V = 2T sums times 1/2 or 1/4: exact)
 template <int M>
 __device__ inline void cheb_wave_sums(const AccCheb<M>& acc, double (&v)[nacc(M)]) {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        v[k] = wave_sum(acc.C[k]);
-        v[M + k] = wave_sum(acc.E[k]);
+        v[k] = 0.5 * wave_sum(acc.C[k]);
+        v[M + k] = 0.25 * wave_sum(acc.E[k]);
     }
+    v[2 * M] = wave_sum(acc.D[0]);
 #pragma unroll
-    for (int j = 0; j <= M; ++j) v[2 * M + j] = wave_sum(acc.D[j]);
+    for (int j = 1; j <= M; ++j) v[2 * M + j] = 0.5 * wave_sum(acc.D[j]);
+}
+
+// the single-fit sweep of stream_strided (same points, same order per lane)
+// with two register sets of U vectors per array that take turns: while one
+// round is accumulated the next is in flight in the other set, so no loaded
+// vector is ever copied (at high degree the pass is bound by float64 issue,
+// and the copies of a single prefetch buffer cost about 3 VALU instructions
+// per point)
+template <int U, typename In, class Acc>
+__device__ inline void stream_strided_pp(const In* __restrict__ x, const In* __restrict__ y, int64_t n, int mis,
+                                         int64_t gwave, int64_t W, Acc& acc) {
+    constexpr int VW = VecOf<In>::W;
+    using V = typename VecOf<In>::type;
+    const int lane = lane_id();
+    const int64_t step = W * kWave;
+    if (mis < 0) {
+        for (int64_t i = gwave * kWave + lane; i < n; i += step) acc.scalar(ld_scalar(x + i), ld_scalar(y + i));
+        return;
+    }
+    int64_t a = (VW - mis) % VW;
+    if (a > n) a = n;
+    const int64_t nv = (n - a) / VW;
+    const int64_t b = a + nv * VW;
+    if (gwave == 0 && lane < a) acc.scalar(ld_scalar(x + lane), ld_scalar(y + lane));
+    const V* __restrict__ xv = reinterpret_cast<const V*>(x + a);
+    const V* __restrict__ yv = reinterpret_cast<const V*>(y + a);
+    const int64_t span = (int64_t)(U - 1) * step;
+    const int64_t round = (int64_t)U * step;
+    // the scheduling barrier keeps the loads where they are issued: without
+    // it the scheduler moves them next to their first use (fewer live
+    // registers, but every round then waits on its own loads)
+    auto load = [&](V (&xs)[U], V (&ys)[U], int64_t j0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xs[u] = ld_stream(xv + j0 + u * step);
+            ys[u] = ld_stream(yv + j0 + u * step);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto use = [&](const V (&xs)[U], const V (&ys)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc.template vec<V, VW>(xs[u], ys[u]);
+    };
+    // R = the rounds this lane takes (U vectors per array, all in bounds); the
+    // loop does two per pass, so that both register sets are loaded and used
+    // in one straight block, and loads the pass after next's first round
+    // unconditionally (re-reading the current one, in bounds, when there is
+    // none: behind a branch, the path without them would make the compiler
+    // wait for the fresh loads too)
+    int64_t j = gwave * kWave + lane;
+    const int64_t R = j + span < nv ? (nv - 1 - span - j) / round + 1 : 0;
+    if (R > 0) {
+        V xa[U], ya[U], xb[U], yb[U];
+        load(xa, ya, j);
+        for (int64_t r = 2; r <= R; r += 2) {
+            load(xb, yb, j + round);
+            use(xa, ya);
+            load(xa, ya, r < R ? j + 2 * round : j);
+            use(xb, yb);
+            j += 2 * round;
+        }
+        if (R & 1) {
+            use(xa, ya);
+            j += round;
+        }
+    }
+    for (; j < nv; j += step) acc.template vec<V, VW>(ld_stream(xv + j), ld_stream(yv + j));
+    if (gwave == 0 && lane < n - b) acc.scalar(ld_scalar(x + b + lane), ld_scalar(y + b + lane));
 }
 
 // single fit of degree M: grid-stride sweep, one partial per block
@@ -283,7 +358,7 @@ __global__ void __launch_bounds__(256)
     }
     AccCheb<M> acc;
     acc.init(c, inv_s);
-    stream_strided<U>(x, y, d.n_single, mis, wave, W, acc);
+    stream_strided_pp<U>(x, y, d.n_single, mis, wave, W, acc);
     double v[nacc(M)];
     cheb_wave_sums(acc, v);
     cheb_block_partial<nacc(M)>(w, v);

@@ -69,6 +69,34 @@ def test_float32_data(m):
     assert normwise(res.coef_cheb.cpu().numpy(), ref["c"]) <= TOL
 
 
+# The single-fit sweep takes two vectors per array per round, from two register
+# sets in turn.  On a 64-wave grid a round is 2 x 4096 vectors, and
+# nv = 4096 + k rounds + 2048 vectors give half the lanes of the launch k
+# rounds and the other half k + 1 (so k = 0..3 covers a lane with none, one,
+# an odd and an even number), then the per-vector tail and the ragged end;
+# offset 1 starts both arrays one element past a 16-byte boundary.
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("dtype,offset", [(np.float32, 0), (np.float32, 1), (np.float64, 1)])
+def test_sweep_rounds(k, dtype, offset):
+    vw = 16 // np.dtype(dtype).itemsize
+    nv = 4096 + k * 8192 + 2048
+    n = nv * vw + 3
+    announce(f"chebyshev sweep rounds k={k} {np.dtype(dtype).name} offset {offset}: n={n}")
+    wl = W.runge(n=n + offset, seed=900 + k, dtype=dtype)
+    old = lf.default_schedule().as_dict()
+    try:
+        lf.set_default_schedule({"waves": 64, "waves_per_block": 1, "tile": 2048, "unroll": 2})
+        res = lf.fit(to_dev(wl.x)[offset:], to_dev(wl.y)[offset:], 12, basis="chebyshev", center=0.0, scale=1.0)
+        torch.cuda.synchronize()
+    finally:
+        lf.set_default_schedule(old)
+    ref = c_oracle.cheb_fit(wl.x[offset:], wl.y[offset:], 12, 0.0, 1.0)
+    assert int(res.status.cpu()[0]) == 0
+    e = normwise(res.coef_cheb.cpu().numpy(), ref["c"])
+    announce(f"  chebyshev coefficients {e:.2e}")
+    assert e <= TOL
+
+
 @pytest.mark.parametrize("lo,hi,m,dtype", [
     (-7.25, 3.5, 9, np.float64),
     (1000.0, 1001.0, 16, np.float32),

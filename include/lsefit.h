@@ -211,7 +211,8 @@ lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype d
  * Givens rotations (Gentleman), and the factors are merged lane -> wave ->
  * block -> fit in a fixed order (a tall-skinny tree).  The error is governed by
  * cond(V), V_ik = t_i^k, not by cond(V)^2 as for the power sums; the pass costs
- * about (m+1)(m+2)/2 + 12(m+1) float64 operations per point instead of 4m+2.
+ * about (m+1)(m+2)/2 + 12(m+1) float64 operations per point instead of the
+ * 5m+1 of the power sums.
  *  x, y, n, dt, ws: as fit_single (same workspace size)
  *  opt:      degree 1..LSEFIT_MAX_DEGREE, range (as fit_single); precision
  *            must be LSEFIT_PREC_F64 and basis monomial (else UNSUPPORTED);

@@ -70,6 +70,8 @@ def parse():
                     help="a few steps of each form plus one plain device copy of known size (for --pmc runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc output folders into the traffic summary")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("DIR", "TITLE", "COMMAND"),
+                    help="turn a rocprofv3 --pmc --kernel-trace csv folder into a per-kernel counter summary")
     ap.add_argument("--out", type=str, default=None, help="where --summarize-pmc writes (default: profiles/)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "TITLE", "COMMAND"),
                     help="turn a rocprofv3 --kernel-trace --stats folder into a text summary (--out: where)")
@@ -144,6 +146,48 @@ def summarize_trace(folder, title, command, out_path=None):
     for name, calls, avg, mn, mx in sorted(rows, key=lambda r: -r[1] * r[2]):
         short = name.split("(")[0]
         lines.append(f"{short:60s} calls {calls:6d}  avg {avg:10.2f} us  min {mn:10.2f} us  max {mx:10.2f} us")
+    text = "\n".join(lines) + "\n"
+    if out_path:
+        os.makedirs(os.path.dirname(os.path.abspath(out_path)), exist_ok=True)
+        with open(out_path, "w") as fh:
+            fh.write(text)
+    print(text, end="")
+
+
+def summarize_counters(folder, title, command, out_path=None):
+    """Per-kernel dispatch count, average duration and the average of every
+    counter of a rocprofv3 --pmc --kernel-trace csv output folder (the
+    library's kernels only), as a short text summary."""
+    import csv
+    import glob
+    from collections import defaultdict
+    vals = defaultdict(lambda: defaultdict(list))
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if "lsefit" in r["Kernel_Name"]:
+                    vals[r["Kernel_Name"].split("(")[0]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    durs = defaultdict(list)
+    for path in glob.glob(os.path.join(folder, "**", "*kernel_trace.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if "lsefit" in r["Kernel_Name"]:
+                    durs[r["Kernel_Name"].split("(")[0]].append(
+                        (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = [f"# rocprofv3 counter summary: {title}",
+             "# command (on the MI355X machine, from /tmp with TMPDIR=/tmp):",
+             f"#   {command}",
+             "# summarised by: python3 /root/repo/bench.py --summarize-counters DIR TITLE COMMAND --out FILE",
+             f"#   (DIR = {folder}, TITLE and COMMAND = the two lines above, FILE = this file)",
+             "# per kernel: dispatches, average duration, then the average value of each counter per dispatch"]
+    order = sorted(vals, key=lambda k: -sum(durs.get(k, [0.0])))
+    for k in order:
+        d = durs.get(k, [])
+        avg = sum(d) / len(d) if d else float("nan")
+        lines.append(f"{k}  dispatches {len(d)}  avg {avg:.2f} us")
+        for c in sorted(vals[k]):
+            v = vals[k][c]
+            lines.append(f"    {c:28s} {sum(v) / len(v):18,.1f}")
     text = "\n".join(lines) + "\n"
     if out_path:
         os.makedirs(os.path.dirname(os.path.abspath(out_path)), exist_ok=True)
@@ -695,6 +739,9 @@ def main():
         return 0
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, out_path=args.out)
+        return 0
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, out_path=args.out)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

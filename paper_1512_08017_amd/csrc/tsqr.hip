@@ -45,8 +45,11 @@ struct GivensQR {
     // offset of Rb_(i, i+1) in r
     static constexpr int row_at(int i) { return i * N - i * (i + 1) / 2; }
 
-    // include the row (x; y) of weight w whose entries before column S are zero
-    template <int S>
+    // include the row (x; y) of weight w whose entries before column S are zero.
+    // GUARD = false when every d_i (i >= S) is already positive: then
+    // d_i' >= d_i > 0 (w x_i^2 >= 0), the zero-weight case cannot occur, and
+    // the result is the same bit for bit without its selects
+    template <int S, bool GUARD = true>
     __device__ inline void include(double w, double (&x)[N], double y) {
 #pragma unroll
         for (int i = S; i < N; ++i) {
@@ -54,7 +57,7 @@ struct GivensQR {
             const double di = d[i];
             const double wxi = w * xi;
             const double dpi = fma(wxi, xi, di);
-            const bool nz = dpi != 0.0;
+            const bool nz = !GUARD || dpi != 0.0;
             const double inv = nz ? recip(dpi) : 0.0;
             const double cb = nz ? di * inv : 1.0;
             const double sb = wxi * inv;
@@ -72,7 +75,17 @@ struct GivensQR {
         e = fma(w * y, y, e);
     }
 
+    // every d_i of columns 1.. positive (d_0 counts the rows, so it is too
+    // once one row is in): from then on data rows need no zero-weight guard
+    __device__ inline bool settled() const {
+        bool ok = true;
+#pragma unroll
+        for (int i = 1; i < N; ++i) ok = ok && d[i] > 0.0;
+        return ok;
+    }
+
     // a data row: x_0 = 1 and weight 1, so the first column needs no products
+    template <bool GUARD = true>
     __device__ inline void include_data(double (&x)[N], double y) {
         const double dp = d[0] + 1.0;
         const double inv = recip(dp);
@@ -86,10 +99,11 @@ struct GivensQR {
         }
         y -= th[0];
         th[0] = fma(inv, y, th[0]);
-        include_from1(w, x, y);
+        include_from1<GUARD>(w, x, y);
     }
+    template <bool GUARD = true>
     __device__ inline void include_from1(double w, double (&x)[N], double y) {
-        if constexpr (N > 1) include<1>(w, x, y);
+        if constexpr (N > 1) include<1, GUARD>(w, x, y);
         else e = fma(w * y, y, e);
     }
 
@@ -140,18 +154,26 @@ struct AccQR {
         inv_s = is;
         nc = -c * is;
     }
+    template <bool GUARD = true>
     __device__ inline void point(double xv, double yv) {
         const double t = fma(xv, inv_s, nc);
         double row[N];
         row[0] = 1.0;
 #pragma unroll
         for (int k = 1; k < N; ++k) row[k] = row[k - 1] * t;
-        q.include_data(row, yv);
+        q.template include_data<GUARD>(row, yv);
     }
+    // a lane whose factor has settled (after its first N rows or so, unless
+    // its t stay at 0) takes the rows without the zero-weight selects
     template <typename V, int VW>
     __device__ inline void vec(const V& xv, const V& yv) {
+        if (q.settled()) {
 #pragma unroll
-        for (int e = 0; e < VW; ++e) point((double)xv[e], (double)yv[e]);
+            for (int e = 0; e < VW; ++e) point<false>((double)xv[e], (double)yv[e]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) point<true>((double)xv[e], (double)yv[e]);
+        }
     }
     __device__ inline void scalar(double xv, double yv) { point(xv, yv); }
 };

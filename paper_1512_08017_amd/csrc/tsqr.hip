@@ -84,11 +84,16 @@ struct GivensQR {
         return ok;
     }
 
-    // a data row: x_0 = 1 and weight 1, so the first column needs no products
-    template <bool GUARD = true>
-    __device__ inline void include_data(double (&x)[N], double y) {
+    // a data row: x_0 = 1 and weight 1, so the first column needs no products.
+    // With TABLE, 1/(d_0 + 1) is read from tab (tab[j] = recip(j + 1), the same
+    // value): d_0 counts the data rows exactly, and the caller has checked that
+    // it is below the table's length
+    template <bool GUARD = true, bool TABLE = false>
+    __device__ inline void include_data(double (&x)[N], double y, const double* tab = nullptr) {
         const double dp = d[0] + 1.0;
-        const double inv = recip(dp);
+        double inv;
+        if constexpr (TABLE) inv = tab[(int)d[0]];
+        else inv = recip(dp);
         const double w = d[0] * inv;
         d[0] = dp;
 #pragma unroll
@@ -143,36 +148,55 @@ struct GivensQR {
     }
 };
 
+// 1/(j+1) for j < kRecipRows, by recip() once per block into LDS: a factor of
+// k data rows has d_0 = k exactly, so the first-column reciprocal of its next
+// row is entry k, read instead of recomputed (the float64 reciprocal issues at
+// a quarter of the rate and needs two Newton steps)
+constexpr int kRecipRows = 1024;
+
+__device__ inline void fill_recip_rows(double* tab) {
+    for (int j = threadIdx.x; j < kRecipRows; j += blockDim.x) tab[j] = recip((double)(j + 1));
+    __syncthreads();
+}
+
 // one point of the streaming pass: the row (1, t, .., t^m; y), weight 1
 template <int M>
 struct AccQR {
     static constexpr int N = M + 1;
     GivensQR<N> q;
     double inv_s, nc;
-    __device__ inline void init(double c, double is) {
+    const double* tab;   // kRecipRows reciprocals 1/(j+1) in LDS (fill_recip_rows)
+    __device__ inline void init(double c, double is, const double* t) {
         q.zero();
         inv_s = is;
         nc = -c * is;
+        tab = t;
     }
-    template <bool GUARD = true>
+    template <bool GUARD = true, bool TABLE = false>
     __device__ inline void point(double xv, double yv) {
         const double t = fma(xv, inv_s, nc);
         double row[N];
         row[0] = 1.0;
 #pragma unroll
         for (int k = 1; k < N; ++k) row[k] = row[k - 1] * t;
-        q.template include_data<GUARD>(row, yv);
+        q.template include_data<GUARD, TABLE>(row, yv, tab);
+    }
+    template <bool GUARD, bool TABLE, typename V, int VW>
+    __device__ inline void rows(const V& xv, const V& yv) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) point<GUARD, TABLE>((double)xv[e], (double)yv[e]);
     }
     // a lane whose factor has settled (after its first N rows or so, unless
-    // its t stay at 0) takes the rows without the zero-weight selects
+    // its t stay at 0) takes the rows without the zero-weight selects, and
+    // while its row count stays inside the table, the first column's
+    // reciprocals from it
     template <typename V, int VW>
     __device__ inline void vec(const V& xv, const V& yv) {
         if (q.settled()) {
-#pragma unroll
-            for (int e = 0; e < VW; ++e) point<false>((double)xv[e], (double)yv[e]);
+            if (q.d[0] <= (double)(kRecipRows - VW)) rows<false, true, V, VW>(xv, yv);
+            else rows<false, false, V, VW>(xv, yv);
         } else {
-#pragma unroll
-            for (int e = 0; e < VW; ++e) point<true>((double)xv[e], (double)yv[e]);
+            rows<true, false, V, VW>(xv, yv);
         }
     }
     __device__ inline void scalar(double xv, double yv) { point(xv, yv); }
@@ -239,8 +263,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(qr_wav
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     double c, inv_s;
     single_range(d, w, x, ra, &c, &inv_s);
+    __shared__ double tab[kRecipRows];
+    fill_recip_rows(tab);
     AccQR<M> acc;
-    acc.init(c, inv_s);
+    acc.init(c, inv_s, tab);
     stream_strided<U>(x, y, d.n_single, mis, wave, W, acc);
     block_merge_store<M + 1>(w, acc.q);
 }
@@ -340,6 +366,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(qr_wav
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     const int stride = qr_len(maxm);
     const int rl = rec_len(maxm);
+    __shared__ double tab[kRecipRows];
+    fill_recip_rows(tab);
     walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
         if (w.pstatus[f] != LSEFIT_OK) return;
         const double c = w.rec[f * rl + 0];
@@ -347,7 +375,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(qr_wav
         double* __restrict__ out = w.part + slot * stride;
         auto body = [&]<int M>() {
             AccQR<M> acc;
-            acc.init(c, inv_s);
+            acc.init(c, inv_s, tab);
             stream_segment<1>(x, y, lo, hi, mis, acc);
             wave_merge(acc.q);
             if (lane_id() == 0) {

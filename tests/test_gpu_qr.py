@@ -52,6 +52,31 @@ def test_every_degree_given_range(m):
     assert res.center == 0.0 and res.scale == 1.0
 
 
+# A lane takes the first-column reciprocal of a data row from a 1024-entry
+# table while its factor holds fewer rows, and computes it past that.  On a
+# 64-wave grid (4,096 lanes) these sizes give every lane about 1,000 and about
+# 1,150 rows: the lanes cross the table's end inside the sweep, at degrees 3 and 8.
+@pytest.mark.parametrize("m,rows", [(3, 1000), (3, 1150), (8, 1150)])
+def test_rows_past_reciprocal_table(m, rows):
+    n = 4096 * rows + 7
+    announce(f"qr m={m}: n={n} on 64 waves ({rows} rows per lane)")
+    wl = W.random_small(n + 1, m, seed=870 + m + rows, dtype=np.float32)
+    x, y = wl.x[1:], wl.y[1:]
+    old = lf.default_schedule().as_dict()
+    try:
+        lf.set_default_schedule({"waves": 64, "waves_per_block": 1, "tile": 2048, "unroll": 1})
+        res = lf.fit_qr(to_dev(wl.x)[1:], to_dev(wl.y)[1:], m, center=0.0, scale=1.0)
+        torch.cuda.synchronize()
+    finally:
+        lf.set_default_schedule(old)
+    b_ref = qr.lstsq_qr(x, y, m, 0.0, 1.0)
+    tol, kappa = qr_bound(x, y, m, 0.0, 1.0, b_ref)
+    assert int(res.status.cpu()[0]) == 0
+    e = normwise(res.coef_t.cpu().numpy(), b_ref)
+    announce(f"  t-basis error {e:.2e} (gate {tol:.1e}, cond(V) {kappa:.1e})")
+    assert e <= tol
+
+
 @pytest.mark.parametrize("n,dtype", [(2, np.float64), (9, np.float64), (4097, np.float32), (1_000_003, np.float32)])
 def test_sizes_automatic_range(n, dtype):
     m = 1 if n < 4 else 3

@@ -825,7 +825,7 @@ def main():
         ceiling = measured_ceiling_gbps()
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 4), "traffic_unit": "GB per launch",
                 "kernel": "k_moments", "avg_launch_ms": round(mk["avg_ms"], 5),
                 "algorithmic_bytes_per_launch": int(bytes_per_launch),
                 "measured_read_ceiling": ceiling,

@@ -530,6 +530,17 @@ def bench_ragged(args):
     out["chebyshev"] = {"eager_default_ms": cheb_ms, "points_per_s": P / (cheb_ms * 1e-3), "kernels": kern,
                         "all_ok": bool((status.cpu().numpy() == 0).all()),
                         "moments_gbps": 8.0 * P / (kern["moments"]["avg_ms"] * 1e-3) / 1e9}
+    # and with a plan tuned for it, replayed as a graph
+    cplan = lf.Plan(bf.batch, 3)
+    cplan.tune(x, y, off, dg, reps=3, basis="chebyshev")
+    cplan_fn = lambda: lf.fit_batched(x, y, off, dg, 3, plan=cplan, out=(coef, status), basis="chebyshev")
+    cgraph_ms = _time(cplan_fn, args.steps, args.warmup)
+    cplan.set_graph(False)
+    ckern = _instrumented(cplan_fn, args.steps)
+    out["chebyshev"].update({"tuned_graph_ms": cgraph_ms, "tuned_schedule": cplan.schedule,
+                             "tuned_points_per_s": P / (cgraph_ms * 1e-3), "tuned_kernels": ckern,
+                             "tuned_all_ok": bool((status.cpu().numpy() == 0).all())})
+    cplan.close()
     log(f"ragged chebyshev: {out['chebyshev']}")
     # per-fit baseline: one fit_single call per fit on the same stream
     L = _lib.load()

@@ -251,10 +251,13 @@ __device__ inline void block_merge_store(const Work& w, GivensQR<N>& q) {
 }
 
 // Every point updates the same factor, so the rounds carry no parallel work
-// worth registers: one vector per round and a register budget (128 VGPRs,
-// 4 waves per SIMD, up to m = 4; 256 above) keep the compiler from hoisting
-// across points.
-constexpr int qr_waves_per_eu(int M) { return M <= 4 ? 4 : 2; }
+// worth registers: one vector per round and a register budget (96 VGPRs,
+// 5 waves per SIMD, up to m = 3; 128 and 4 at m = 4; 256 above) keep the
+// compiler from hoisting across points, and the extra waves cover the
+// dependence chain through each column's reciprocal.  (The batched kernel
+// takes the budget of its largest degree, 4 or 8: at 5 waves per SIMD its
+// degree-3 form was slower.)
+constexpr int qr_waves_per_eu(int M) { return M <= 3 ? 5 : (M <= 4 ? 4 : 2); }
 
 template <typename In, int U, int M>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(qr_waves_per_eu(M))))

@@ -65,58 +65,57 @@ def gradients(x, y, m: int, gbar, center: float = 0.0, scale: float = 1.0) -> di
     return {"dx": (dq * r - q * df) / scale, "dy": q, "a": res["a"], "b": b, "lam": np.array(lam)}
 
 
-def _fit_from_sums(S, T, m):
-    A, B = fp64.assemble(list(S), list(T), m)
-    b, status = fp64.gepp(A, B)
-    if status != fp64.OK:
-        raise ValueError(status)
-    return np.array(b)
-
-
 def fd_gradients(x, y, m: int, loss_of_a, h: float = 1e-6, center: float = 0.0,
                  scale: float = 1.0, which: str = "both") -> dict:
     """Central differences of loss_of_a(fit(x, y)) w.r.t. every x_i and y_i.
 
-    A perturbation of one point changes each power sum by one term, so each
-    perturbed fit is solved from S +- (new term - old term) with the old and
-    new terms taken from the point itself; the sums are then eliminated by
-    ``fp64.gepp`` and mapped back with ``fp64.unscale``.
+    ``loss_of_a`` maps coefficient vectors to losses row-wise: an array of
+    shape (K, m+1) of x-basis coefficients to K losses.  A perturbation of one
+    point changes each power sum by one term, so each perturbed fit is solved
+    from S +- (new term - old term), with the old and new terms taken from the
+    point itself; the perturbed systems of all points are assembled as Hankel
+    matrices, eliminated by ``fp64.gepp_many`` (the steps of ``fp64.gepp`` for
+    each system) and mapped back to the x-basis with the sums of
+    ``fp64.unscale``.
     """
     res = fp64.fit(x, y, m, center, scale)
     S0, T0 = np.array(res["S"]), np.array(res["T"])
     t = fp64.change_of_variable(x, center, scale)
     yv = np.asarray(y, dtype=np.float64)
-    n = t.shape[0]
-
-    def loss_at(S, T):
-        b = _fit_from_sums(S, T, m)
-        return loss_of_a(np.array(fp64.unscale(list(b), center, scale)))
+    xv = np.asarray(x, dtype=np.float64)
+    Mb = basis_map(m, center, scale)
 
     def terms(tv, yvv):
-        S = np.array([tv ** p for p in range(2 * m + 1)])
-        T = np.array([tv ** j * yvv for j in range(m + 1)])
+        """Per-point terms t^p (p = 0..2m) and t^j y (j = 0..m): arrays [n, .]."""
+        S = np.stack([tv ** p for p in range(2 * m + 1)], axis=1)
+        T = np.stack([tv ** j * yvv for j in range(m + 1)], axis=1)
         return S, T
 
+    def losses(S, T):
+        A = np.stack([np.stack([S[:, j + k] for k in range(m + 1)], axis=1) for j in range(m + 1)], axis=1)
+        b, ok = fp64.gepp_many(A, T)
+        if not ok.all():
+            raise ValueError("a perturbed fit is singular")
+        # a_k = sum_(j>=k) b_j M_kj, the terms of fp64.unscale in the same order
+        a = np.zeros_like(b)
+        for k in range(m + 1):
+            for j in range(k, m + 1):
+                a[:, k] += b[:, j] * Mb[k, j]
+        return np.asarray(loss_of_a(a), dtype=np.float64)
+
+    s_old, t_old = terms(t, yv)
     out = {}
     if which in ("both", "x"):
-        dx = np.empty(n)
-        for i in range(n):
-            s_old, t_old = terms(t[i], yv[i])
-            vals = []
-            for sgn in (1.0, -1.0):
-                tp = (float(x[i]) + sgn * h - center) / scale
-                s_new, t_new = terms(tp, yv[i])
-                vals.append(loss_at(S0 + (s_new - s_old), T0 + (t_new - t_old)))
-            dx[i] = (vals[0] - vals[1]) / (2.0 * h)
-        out["dx"] = dx
+        vals = []
+        for sgn in (1.0, -1.0):
+            tp = (xv + sgn * h - center) / scale
+            s_new, t_new = terms(tp, yv)
+            vals.append(losses(S0 + (s_new - s_old), T0 + (t_new - t_old)))
+        out["dx"] = (vals[0] - vals[1]) / (2.0 * h)
     if which in ("both", "y"):
-        dy = np.empty(n)
-        for i in range(n):
-            _, t_old = terms(t[i], yv[i])
-            vals = []
-            for sgn in (1.0, -1.0):
-                _, t_new = terms(t[i], yv[i] + sgn * h)
-                vals.append(loss_at(S0, T0 + (t_new - t_old)))
-            dy[i] = (vals[0] - vals[1]) / (2.0 * h)
-        out["dy"] = dy
+        vals = []
+        for sgn in (1.0, -1.0):
+            _, t_new = terms(t, yv + sgn * h)
+            vals.append(losses(np.broadcast_to(S0, s_old.shape), T0 + (t_new - t_old)))
+        out["dy"] = (vals[0] - vals[1]) / (2.0 * h)
     return out

@@ -90,6 +90,46 @@ def gepp(A, B, singular_rel: float = SINGULAR_REL):
     return X, OK
 
 
+def gepp_many(A, B, singular_rel: float = SINGULAR_REL):
+    """``gepp`` applied to K independent systems at once (A: K x n x n, B: K x n).
+
+    Each system goes through the same steps as ``gepp`` -- first row of
+    largest |entry| as pivot, elimination of the rows below, back
+    substitution -- so every system gets the bits ``gepp`` gives it; only the
+    loop over systems is vectorised.  Returns (X [K, n], ok [K]); rows of X
+    for singular or non-finite systems are NaN.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    K, n = B.shape
+    M = np.concatenate([A, B[:, :, None]], axis=2).copy()
+    finite = np.isfinite(M).all(axis=(1, 2))
+    amax = np.where(finite, np.abs(np.where(np.isfinite(A), A, 0.0)).max(axis=(1, 2)), 0.0)
+    ok = finite.copy()
+    rows = np.arange(K)
+    for k in range(n):
+        p = k + np.argmax(np.abs(M[:, k:, k]), axis=1)      # argmax keeps the first maximum
+        ok &= np.abs(M[rows, p, k]) > singular_rel * amax
+        pk = M[rows, p, :].copy()
+        M[rows, p, :] = M[:, k, :]
+        M[:, k, :] = pk
+        with np.errstate(divide="ignore", invalid="ignore"):
+            for r in range(k + 1, n):
+                l = M[:, r, k] / M[:, k, k]
+                for c in range(k, n + 1):
+                    M[:, r, c] -= l * M[:, k, c]
+    X = np.zeros((K, n))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for i in range(n - 1, -1, -1):
+            acc = M[:, i, n].copy()
+            for c in range(i + 1, n):
+                acc -= M[:, i, c] * X[:, c]
+            X[:, i] = acc / M[:, i, i]
+    ok &= np.isfinite(X).all(axis=1)
+    X[~ok] = np.nan
+    return X, ok
+
+
 def unscale(b, center: float = 0.0, scale: float = 1.0):
     """t-basis coefficients b (t = (x-c)/s) -> x-basis a, both ascending."""
     m = len(b) - 1

@@ -217,7 +217,7 @@ def test_adjoint_against_finite_differences():
     coef = lf.lsefit(x, y, off, dg, 2)
     loss = ((coef[0] - torch.from_numpy(target).to(x.device)) ** 2).sum()
     loss.backward()
-    fd = adjoint.fd_gradients(bf.x, bf.y, 2, lambda a: float(np.sum((a - target) ** 2)), h=1e-6)
+    fd = adjoint.fd_gradients(bf.x, bf.y, 2, lambda a: np.sum((a - target) ** 2, axis=-1), h=1e-6)
     assert normwise(x.grad.cpu().numpy(), fd["dx"]) <= 1e-4
     assert normwise(y.grad.cpu().numpy(), fd["dy"]) <= 1e-4
 

@@ -186,13 +186,16 @@ def test_grad_batch_full():
         worst = max(worst, normwise(gx[lo:hi], g["dx"]), normwise(gy[lo:hi], g["dy"]))
     announce(f"  adjoint vs closed form (64 fits): {worst:.2e}")
     assert worst <= 1e-5
-    for f in sample[:4]:
+    # float64 central differences (h = 1e-6) on every input of all 64 sampled fits
+    worst_fd = 0.0
+    for f in sample:
         lo, hi = bf.offsets[f], bf.offsets[f + 1]
         tgt = bf.target[f]
-        fd = adjoint.fd_gradients(bf.x[lo:hi], bf.y[lo:hi], 2, lambda av: float(np.sum((av - tgt) ** 2)), h=1e-6)
+        fd = adjoint.fd_gradients(bf.x[lo:hi], bf.y[lo:hi], 2, lambda av: np.sum((av - tgt) ** 2, axis=-1), h=1e-6)
         e = max(normwise(gx[lo:hi], fd["dx"]), normwise(gy[lo:hi], fd["dy"]))
-        announce(f"  adjoint vs finite differences, fit {f}: {e:.2e}")
-        assert e <= 1e-4
+        worst_fd = max(worst_fd, e)
+        assert e <= 1e-4, f
+    announce(f"  adjoint vs finite differences (64 fits): {worst_fd:.2e}")
 
 
 @pytest.fixture(scope="module")

@@ -10,7 +10,9 @@ import numpy as np
 import pytest
 
 from conftest import read_golden
-from oracle import fp64
+from fractions import Fraction
+
+from oracle import exact, fp64
 from paper_1512_08017_amd import workloads as W
 
 
@@ -106,3 +108,53 @@ ORIG_POWER_SUMS = fp64.power_sums
 def test_planted_mistake_is_caught(monkeypatch, target, replacement):
     monkeypatch.setattr(fp64, target, replacement)
     assert not _pins_hold()
+
+
+# --- V^T r (the first-order conditions of Sec. II) ---------------------------
+
+def _normal_residual_pins_hold() -> bool:
+    rows, _ = read_golden("table_i.txt")
+    xs = [r[0] for r in rows]
+    ys = [r[1] for r in rows]
+    if exact.normal_residual([0, 1, 2], [1, 2, 2], [1, 1, 0]) != [-1, -2, -4]:
+        return False
+    for m in (1, 2, 3):
+        a, _ = exact.fit_exact(xs, ys, m)
+        if any(v != 0 for v in exact.normal_residual(xs, ys, a)):
+            return False
+        S, _ = exact.power_sums_exact(xs, ys, m)
+        for k in range(m + 1):
+            ap = list(a)
+            ap[k] += Fraction(3, 7)
+            if exact.normal_residual(xs, ys, ap) != [-Fraction(3, 7) * S[j + k] for j in range(m + 1)]:
+                return False
+    return True
+
+
+def _normal_residual_drops_power(xs, ys, a):
+    m = len(a) - 1
+    r = [exact.frac(y) - exact.polyval_exact(a, x) for x, y in zip(xs, ys)]
+    return [sum(r, Fraction(0)) for _ in range(m + 1)]
+
+
+def _normal_residual_wrong_sign(xs, ys, a):
+    m = len(a) - 1
+    r = [exact.polyval_exact(a, x) - exact.frac(y) for x, y in zip(xs, ys)]
+    return [sum((exact.frac(x) ** k * ri for x, ri in zip(xs, r)), Fraction(0)) for k in range(m + 1)]
+
+
+def _normal_residual_shifted_power(xs, ys, a):
+    m = len(a) - 1
+    r = [exact.frac(y) - exact.polyval_exact(a, x) for x, y in zip(xs, ys)]
+    return [sum((exact.frac(x) ** (k + 1) * ri for x, ri in zip(xs, r)), Fraction(0)) for k in range(m + 1)]
+
+
+def test_unmodified_normal_residual_passes():
+    assert _normal_residual_pins_hold()
+
+
+@pytest.mark.parametrize("replacement", [_normal_residual_drops_power, _normal_residual_wrong_sign,
+                                         _normal_residual_shifted_power])
+def test_planted_normal_residual_mistake_is_caught(monkeypatch, replacement):
+    monkeypatch.setattr(exact, "normal_residual", replacement)
+    assert not _normal_residual_pins_hold()

@@ -106,6 +106,48 @@ def test_exact_normal_residual_is_zero(m):
     assert all(v == 0 for v in exact.normal_residual(xs, ys, a))
 
 
+def test_normal_residual_hand_worked():
+    """V^T r on three points, worked by hand: (x, y) = (0, 1), (1, 2), (2, 2).
+    At a = 0, r = y: [sum y, sum x y, sum x^2 y] = [5, 6, 10].  At a = (1, 1),
+    r = y - 1 - x = (0, 0, -1): [-1, -2, -4]."""
+    xs, ys = [0, 1, 2], [1, 2, 2]
+    assert exact.normal_residual(xs, ys, [0, 0, 0]) == [5, 6, 10]
+    assert exact.normal_residual(xs, ys, [1, 1, 0]) == [-1, -2, -4]
+
+
+@pytest.mark.parametrize("m,k", [(m, k) for m in (1, 2, 3) for k in range(m + 1)])
+def test_normal_residual_off_the_minimiser(m, k):
+    """Away from the minimiser: with a = a* + delta e_k, r = r* - delta x^k, so
+    V^T r = -delta V^T V e_k = -delta (S_k, S_(k+1), .., S_(k+m)), the k-th
+    column of the Hankel matrix of Sec. II, exactly (Table I points)."""
+    xs, ys = table_i()
+    a, _ = exact.fit_exact(xs, ys, m)
+    S, _ = exact.power_sums_exact(xs, ys, m)
+    delta = Fraction(3, 7)
+    ap = list(a)
+    ap[k] += delta
+    assert exact.normal_residual(xs, ys, ap) == [-delta * S[j + k] for j in range(m + 1)]
+
+
+def test_gepp_many_is_gepp_per_system():
+    """The batched elimination gives every system the bits of fp64.gepp (same
+    pivots, same operations), singular systems included."""
+    rng = np.random.default_rng(44)
+    for n in (1, 2, 3, 5):
+        A = rng.standard_normal((40, n, n))
+        B = rng.standard_normal((40, n))
+        A[3] = 0.0                      # singular
+        if n > 1:
+            A[5, 1] = A[5, 0]           # singular (two equal rows)
+            A[7, :, 0] = 1.0            # ties in the first column: first row wins
+        X, ok = fp64.gepp_many(A, B)
+        for i in range(40):
+            x1, st = fp64.gepp(A[i].tolist(), B[i].tolist())
+            assert ok[i] == (st == fp64.OK)
+            if ok[i]:
+                assert np.array_equal(X[i], np.array(x1))
+
+
 def test_printed_matrix_a00_reading():
     """The printed A_00 = 1 does not reproduce Table II; A_00 = n does (reading of Sec. II)."""
     xs, ys = table_i()
@@ -386,7 +428,7 @@ def test_c_oracle_batched_equals_single():
 # --- adjoint --------------------------------------------------------------------
 
 def _loss_factory(target):
-    return lambda a: float(np.sum((a - target) ** 2))
+    return lambda a: np.sum((a - target) ** 2, axis=-1)
 
 
 @pytest.mark.parametrize("center,scale", [(0.0, 1.0), (0.25, 0.5)])

@@ -123,6 +123,22 @@ typedef enum { LSEFIT_SOLVER_GEPP = 0, LSEFIT_SOLVER_CHOLESKY = 1 } lsefit_solve
  *      move with the extreme x: UNSUPPORTED). */
 typedef enum { LSEFIT_BASIS_MONOMIAL = 0, LSEFIT_BASIS_CHEBYSHEV = 1 } lsefit_basis;
 
+/* What fit_batched writes per fit in the monomial basis.
+ *  LSEFIT_OUTPUT_X:       a_0..a_m (x-basis) at coef[f * coef_stride], the
+ *                         rest of the row untouched.
+ *  LSEFIT_OUTPUT_X_AND_T: also the t-basis solution b_0..b_m from
+ *                         coef[f * coef_stride + M + 1] on and the fit's c, s
+ *                         at coef[f * coef_stride + 2M + 2] and + 2M + 3
+ *                         (M = opt->degree, the largest degree of the call;
+ *                         needs coef_stride >= 2M + 4).  For data far from 0
+ *                         (x near 1000, say) the x-basis coefficients are
+ *                         large and cancel when f(x) is evaluated in float64;
+ *                         f(x) = sum_j b_j ((x - c)/s)^j does not.
+ * Single-fit calls always write a and then b, and report (c, s) in their
+ * moments; the Chebyshev basis writes its own coefficients (see above); both
+ * ignore this field. */
+typedef enum { LSEFIT_OUTPUT_X = 0, LSEFIT_OUTPUT_X_AND_T = 1 } lsefit_output_basis;
+
 typedef struct lsefit_options {
     int32_t degree;        /* single fit: m in 1..LSEFIT_MAX_DEGREE (Chebyshev basis:
                               1..LSEFIT_MAX_DEGREE_CHEBYSHEV); batched: the
@@ -134,6 +150,7 @@ typedef struct lsefit_options {
     double scale;          /* s for LSEFIT_RANGE_GIVEN, > 0 */
     int32_t solver;        /* lsefit_solver */
     int32_t basis;         /* lsefit_basis */
+    int32_t output_basis;  /* lsefit_output_basis (fit_batched, monomial basis) */
 } lsefit_options;
 
 /* Launch schedule of the streaming kernels.  Any valid schedule gives the
@@ -245,7 +262,9 @@ lsefit_status fit_qr_batched(const void* x, const void* y, const int64_t* offset
  *  offsets:   device int64 [B+1], non-decreasing, offsets[0] = 0
  *  degrees:   device int32 [B], each in 1..opt->degree
  *  coef:      output, device float64 [B * coef_stride]: a_0..a_m of fit f at
- *             f*coef_stride; coef_stride >= opt->degree + 1; entries past m untouched
+ *             f*coef_stride; coef_stride >= opt->degree + 1; entries past m
+ *             untouched (LSEFIT_OUTPUT_X_AND_T: also b and (c, s), see
+ *             lsefit_output_basis; coef_stride >= 2 opt->degree + 4)
  *  status:    output, device int32 [B]
  *  plan:      NULL -> the default schedule and the caller's workspace `ws`;
  *             otherwise the plan's tuned schedule and its own workspace (ws
@@ -270,7 +289,10 @@ lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, 
  * and its derivative).  Points of fits whose status is not OK get NaN.
  * `plan`/`ws` must be the ones the forward call used, unchanged since (the
  * per-fit records and the tile table are read from there); lambda is written
- * into that workspace. */
+ * into that workspace.  The tile table carries the tile size it was built
+ * with, so the default schedule may change between the two calls (the pass
+ * cuts every fit where the forward did); `ws_bytes` must still cover the
+ * workspace size of the schedule in force (else WORKSPACE). */
 lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
                            int64_t batch, lsefit_dtype dt, const lsefit_options* opt,
                            lsefit_plan* plan, void* ws, size_t ws_bytes,
@@ -335,15 +357,30 @@ const char* lsefit_status_string(lsefit_status s);
 lsefit_status lsefit_read_probe(const float* x, const float* y, int64_t n, const lsefit_schedule* schedule,
                                 int32_t pattern, int32_t nontemporal, float* out, size_t out_count, void* stream);
 
-/* Kernel timing for profiling.  While enabled, every launch of a streaming
- * kernel made by the calls above (outside graph capture) is bracketed by a
- * pair of HIP events recorded on the call's stream.  lsefit_timing_read waits
- * for the recorded events of one kernel kind and returns the summed duration
- * in milliseconds and the number of launches since the last reset.
- *  kind: 0 = power-sum pass, 1 = refinement pass, 2 = adjoint pass,
- *        3 = per-fit combine and solve, 4 = read-bandwidth probe,
- *        5 = residual pass, 6 = range pass (Chebyshev basis, automatic
- *        range; with its per-fit fold).
+/* Copy probe, for measurement only (no part of the fit): reads two float32
+ * arrays x, y of n elements (n rounded down to a multiple of 4) and writes
+ * them to ox, oy with 16-byte loads and stores -- 8 bytes read and 8 written
+ * per point, the traffic of the adjoint pass of fit_backward.  All four
+ * pointers 16-byte aligned; pattern and nontemporal as lsefit_read_probe
+ * (nontemporal applies to the loads and the stores).  Timed as kind 4. */
+lsefit_status lsefit_copy_probe(const float* x, const float* y, float* ox, float* oy, int64_t n,
+                                const lsefit_schedule* schedule, int32_t pattern, int32_t nontemporal,
+                                void* stream);
+
+/* Kernel timing for profiling.  While enabled, the main kernel of every
+ * streaming launch made by the calls above (outside graph capture) is
+ * dispatched with a pair of HIP events (hipExtLaunchKernelGGL) that take the
+ * start and end timestamps of that kernel's own dispatch, so the durations
+ * are those of the kernel itself, without event packets between kernels.
+ * lsefit_timing_read waits for the events of one kernel kind and returns the
+ * summed duration in milliseconds and the number of launches since the last
+ * reset.
+ *  kind: 0 = power-sum pass (k_moments, or the Chebyshev / QR streaming pass),
+ *        1 = refinement pass, 2 = adjoint streaming pass (not its per-fit
+ *        solve), 3 = per-fit combine and solve (the finish kernel of a single
+ *        fit), 4 = read or copy probe, 5 = residual pass (not its per-fit
+ *        fold), 6 = range pass (Chebyshev basis, automatic range; not its
+ *        per-fit fold).
  * Not synchronised with calls on other host threads. */
 lsefit_status lsefit_timing_enable(int32_t enable);
 lsefit_status lsefit_timing_reset(void);

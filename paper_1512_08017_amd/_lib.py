@@ -15,6 +15,7 @@ SOLVER_GEPP, SOLVER_CHOLESKY = 0, 1
 BASIS_MONOMIAL, BASIS_CHEBYSHEV = 0, 1
 LSEFIT_MAX_DEGREE_CHEBYSHEV = 16
 RANGE_GIVEN, RANGE_AUTO = 0, 1
+OUTPUT_X, OUTPUT_X_AND_T = 0, 1
 
 STATUS_NAMES = {OK: "ok", INVALID_ARG: "invalid_arg", SINGULAR: "singular", NONFINITE: "nonfinite",
                 WORKSPACE: "workspace", DEVICE: "device", UNSUPPORTED: "unsupported"}
@@ -26,14 +27,14 @@ EXPORTS = (
     "fit_residuals",
     "fit_plan_create", "fit_plan_tune", "fit_plan_set_tune_cache", "fit_plan_set_schedule", "fit_plan_get_schedule",
     "fit_plan_set_graph", "fit_plan_destroy", "lsefit_status_string", "lsefit_device_cus",
-    "lsefit_timing_enable", "lsefit_timing_reset", "lsefit_timing_read", "lsefit_read_probe",
+    "lsefit_timing_enable", "lsefit_timing_reset", "lsefit_timing_read", "lsefit_read_probe", "lsefit_copy_probe",
 )
 
 
 class Options(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
                 ("range_mode", ctypes.c_int32), ("center", ctypes.c_double), ("scale", ctypes.c_double),
-                ("solver", ctypes.c_int32), ("basis", ctypes.c_int32)]
+                ("solver", ctypes.c_int32), ("basis", ctypes.c_int32), ("output_basis", ctypes.c_int32)]
 
 
 class Schedule(ctypes.Structure):
@@ -91,13 +92,14 @@ def load():
     L.lsefit_device_cus.restype = i32
     L.lsefit_timing_enable.argtypes = [i32]
     L.lsefit_read_probe.argtypes = [vp, vp, i64, SchP, i32, i32, vp, sz, vp]
+    L.lsefit_copy_probe.argtypes = [vp, vp, vp, vp, i64, SchP, i32, i32, vp]
     L.lsefit_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     for name in ("lsefit_default_schedule", "lsefit_set_default_schedule", "fit_moments", "fit_solve", "fit_single",
                  "fit_qr", "fit_qr_batched", "fit_residuals",
                  "fit_batched", "fit_backward", "fit_plan_create", "fit_plan_tune", "fit_plan_set_tune_cache",
                  "fit_plan_set_schedule",
                  "fit_plan_get_schedule", "fit_plan_set_graph", "lsefit_timing_enable", "lsefit_timing_reset",
-                 "lsefit_timing_read", "lsefit_read_probe"):
+                 "lsefit_timing_read", "lsefit_read_probe", "lsefit_copy_probe"):
         getattr(L, name).restype = i32
     _lib = L
     return L

@@ -21,6 +21,7 @@ _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
 _PREC = {"f64": _lib.PREC_F64, "f32c": _lib.PREC_F32C}
 _SOLVER = {"gepp": _lib.SOLVER_GEPP, "cholesky": _lib.SOLVER_CHOLESKY}
 _BASIS = {"monomial": _lib.BASIS_MONOMIAL, "chebyshev": _lib.BASIS_CHEBYSHEV}
+_OUTPUT = {"x": _lib.OUTPUT_X, "x_and_t": _lib.OUTPUT_X_AND_T}
 
 
 def _ptr(t):
@@ -32,14 +33,17 @@ def _stream(dev):
 
 
 def options(degree: int, precision: str = "f64", refine: int = 1, center=None, scale=None,
-            solver: str = "gepp", basis: str = "monomial") -> Options:
+            solver: str = "gepp", basis: str = "monomial", output_basis: str = "x") -> Options:
     if precision not in _PREC:
         raise ValueError(f"precision must be one of {sorted(_PREC)}")
     if solver not in _SOLVER:
         raise ValueError(f"solver must be one of {sorted(_SOLVER)}")
     if basis not in _BASIS:
         raise ValueError(f"basis must be one of {sorted(_BASIS)}")
+    if output_basis not in _OUTPUT:
+        raise ValueError(f"output_basis must be one of {sorted(_OUTPUT)}")
     o = Options()
+    o.output_basis = _OUTPUT[output_basis]
     o.solver = _SOLVER[solver]
     o.basis = _BASIS[basis]
     o.degree = int(degree)
@@ -356,13 +360,19 @@ def _check_batch(x, y, offsets, degrees):
 
 def fit_batched(x, y, offsets, degrees, max_degree: int, precision: str = "f64", refine: int = 1,
                 center=None, scale=None, plan: Plan | None = None, coef_stride: int | None = None,
-                ws: torch.Tensor | None = None, out=None, solver: str = "gepp", basis: str = "monomial"):
-    """Independent fits over CSR segments; returns (coef [B, stride], status [B], ws)."""
+                ws: torch.Tensor | None = None, out=None, solver: str = "gepp", basis: str = "monomial",
+                output_basis: str = "x"):
+    """Independent fits over CSR segments; returns (coef [B, stride], status [B], ws).
+
+    output_basis="x_and_t" (monomial basis): each row is [a_0..a_M | b_0..b_M | c | s]
+    (M = max_degree, stride 2M + 4 by default): the x-basis coefficients, the
+    t-basis coefficients of t = (x - c)/s and the fit's c and s."""
     _check_batch(x, y, offsets, degrees)
     L = _lib.load()
     B = degrees.numel()
-    o = options(max_degree, precision, refine, center, scale, solver, basis)
-    stride = coef_stride or (max_degree + 1)
+    o = options(max_degree, precision, refine, center, scale, solver, basis, output_basis)
+    t_out = output_basis == "x_and_t" and basis == "monomial"
+    stride = coef_stride or (2 * max_degree + 4 if t_out else max_degree + 1)
     if out is None:
         coef = torch.zeros((B, stride), dtype=torch.float64, device=x.device)
         status = torch.empty(B, dtype=torch.int32, device=x.device)

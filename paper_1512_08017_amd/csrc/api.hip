@@ -23,6 +23,13 @@
 
 using namespace lsefit;
 
+namespace lsefit {
+TimingSlot& timing_slot() {
+    static thread_local TimingSlot slot;
+    return slot;
+}
+}  // namespace lsefit
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -38,7 +45,7 @@ Layout layout(int64_t B, int maxM, int64_t W) {
     Layout L{};
     size_t off = 0;
     L.tile_start = off;
-    off = align_up(off + sizeof(int64_t) * (size_t)(B + 1));
+    off = align_up(off + sizeof(int64_t) * (size_t)(B + 2));
     L.pstatus = off;
     off = align_up(off + sizeof(int32_t) * (size_t)B);
     L.rec = off;
@@ -140,8 +147,17 @@ bool opts_ok(const lsefit_options* o, int dt, bool batched) {
         return false;
     if (dt != LSEFIT_F32 && dt != LSEFIT_F64) return false;
     if (o->solver != LSEFIT_SOLVER_GEPP && o->solver != LSEFIT_SOLVER_CHOLESKY) return false;
+    if (o->output_basis != LSEFIT_OUTPUT_X && o->output_basis != LSEFIT_OUTPUT_X_AND_T) return false;
     (void)batched;
     return true;
+}
+
+// batched monomial fits that also return b and (c, s)
+bool t_output(const lsefit_options* o) { return o->output_basis == LSEFIT_OUTPUT_X_AND_T && !chebyshev(o); }
+
+// the coefficient row of a batched call holds what the options ask for
+bool stride_ok(const lsefit_options* o, int32_t coef_stride) {
+    return coef_stride >= (t_output(o) ? 2 * o->degree + 4 : o->degree + 1);
 }
 
 bool refining(const lsefit_options* o) {
@@ -161,7 +177,8 @@ bool unsupported(const lsefit_options* o, int dt) {
     } while (0)
 
 // ---------------------------------------------------------------------------
-// optional kernel timing: event pairs around streaming launches
+// optional kernel timing: the first kernel of a timed launcher carries a pair
+// of events that record its own dispatch's start and end (launch_timed)
 // ---------------------------------------------------------------------------
 enum TimedKind {
     kTimeMoments = 0,
@@ -197,11 +214,13 @@ hipEvent_t take_event() {
         return e;
     }
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    // no system-scope release at the timed kernel's end: the events only carry timestamps
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
-// runs `launch` on `st`, bracketed by events when timing is on
+// runs `launch` on `st`; when timing is on, its first kernel started through
+// launch_timed records its own start and end into a fresh event pair
 template <class F>
 hipError_t timed(int kind, hipStream_t st, F&& launch) {
     bool on;
@@ -217,15 +236,21 @@ hipError_t timed(int kind, hipStream_t st, F&& launch) {
         b = take_event();
     }
     if (!a || !b) return launch();
-    hipError_t e = hipEventRecord(a, st);
-    if (e != hipSuccess) return e;
-    e = launch();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(b, st);
-    if (e != hipSuccess) return e;
+    TimingSlot& slot = timing_slot();
+    slot.start = a;
+    slot.stop = b;
+    slot.used = false;
+    const hipError_t e = launch();
+    const bool used = slot.used;
+    slot = TimingSlot{};
     std::lock_guard<std::mutex> lk(g_timing.mu);
-    g_timing.pending[kind].push_back({a, b});
-    return hipSuccess;
+    if (e == hipSuccess && used) {
+        g_timing.pending[kind].push_back({a, b});
+    } else {
+        g_timing.pool.push_back(a);
+        g_timing.pool.push_back(b);
+    }
+    return e;
 }
 
 // the whole batched forward on one stream
@@ -237,8 +262,13 @@ lsefit_status enqueue_batched(const FitDesc& d, const Work& w, const lsefit_opti
     const bool given = o->range_mode == LSEFIT_RANGE_GIVEN;
     const int mis = common_mis(dt, {x, y});
     const bool by_block = L.waves >= 64 * d.batch;
-    const Finish solve{kSolve, coef, coef_stride, 0, status, nullptr, o->solver};
-    const Finish refine{kRefine, coef, coef_stride, 0, status, nullptr, o->solver};
+    Finish solve{kSolve, coef, coef_stride, 0, status, nullptr, o->solver};
+    if (t_output(o)) {
+        solve.b_at = maxM + 1;
+        solve.cs_at = 2 * maxM + 2;
+    }
+    Finish refine = solve;
+    refine.mode = kRefine;
     if (chebyshev(o)) {
         // the plan takes the given (c, s), or a placeholder the range pass replaces
         LSEFIT_TRY(launch_plan(d, w, maxM, L.tile, true, given ? o->center : 0.0, given ? o->scale : 1.0, dt, x,
@@ -567,7 +597,7 @@ lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, 
     if (batch < 0 || !opts_ok(opt, dt, true)) return LSEFIT_ERR_INVALID_ARG;
     if (batch == 0) return LSEFIT_OK;
     if (!x || !y || !offsets || !degrees || !coef || !status) return LSEFIT_ERR_INVALID_ARG;
-    if (coef_stride < opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
+    if (!stride_ok(opt, coef_stride)) return LSEFIT_ERR_INVALID_ARG;
     if (unsupported(opt, dt)) return LSEFIT_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     const FitDesc d{offsets, degrees, 0, batch, opt->degree};
@@ -756,7 +786,7 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
                             int32_t coef_stride, int32_t* status, void* stream, int32_t reps, double* best_ms_out) {
     if (!plan || !opts_ok(opt, plan->dtype, true) || batch < 1 || batch > plan->batch) return LSEFIT_ERR_INVALID_ARG;
     if (!x || !y || !offsets || !degrees || !coef || !status) return LSEFIT_ERR_INVALID_ARG;
-    if (opt->degree > plan->max_degree || coef_stride < opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
+    if (opt->degree > plan->max_degree || !stride_ok(opt, coef_stride)) return LSEFIT_ERR_INVALID_ARG;
     if (unsupported(opt, plan->dtype)) return LSEFIT_ERR_UNSUPPORTED;
     if (reps < 1) reps = 3;
     hipStream_t st = (hipStream_t)stream;
@@ -850,6 +880,19 @@ lsefit_status lsefit_read_probe(const float* x, const float* y, int64_t n, const
     hipStream_t st = (hipStream_t)stream;
     LSEFIT_TRY(timed(kTimeProbe, st,
                      [&] { return launch_read_probe(x, y, n / 4, L, pattern, nontemporal != 0, out, st); }));
+    return LSEFIT_OK;
+}
+
+lsefit_status lsefit_copy_probe(const float* x, const float* y, float* ox, float* oy, int64_t n,
+                               const lsefit_schedule* schedule, int32_t pattern, int32_t nontemporal, void* stream) {
+    if (!x || !y || !ox || !oy || n < 4 || (pattern != 0 && pattern != 1)) return LSEFIT_ERR_INVALID_ARG;
+    if (((uintptr_t)x | (uintptr_t)y | (uintptr_t)ox | (uintptr_t)oy) % 16) return LSEFIT_ERR_INVALID_ARG;
+    const lsefit_schedule s = schedule ? *schedule : current_default();
+    if (!schedule_ok(s)) return LSEFIT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    LSEFIT_TRY(timed(kTimeProbe, st, [&] {
+        return launch_copy_probe(x, y, ox, oy, n / 4, to_launch(s), pattern, nontemporal != 0, st);
+    }));
     return LSEFIT_OK;
 }
 

@@ -212,9 +212,9 @@ __global__ void __launch_bounds__(256) k_range_fold_single(Work w, int64_t G) {
 // batch: one (min, max) pair per (wave, fit) slot
 template <typename In>
 __global__ void __launch_bounds__(256)
-    k_range_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, int64_t tile, int64_t W, int mis, int maxm) {
+    k_range_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, int64_t W, int mis, int maxm) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
-    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rec_len(maxm), tile, wave, W,
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rec_len(maxm), wave, W,
                         [&](int64_t, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
         if (mt.st != LSEFIT_OK) return;
         MinMax<In> r;
@@ -368,12 +368,12 @@ __global__ void __launch_bounds__(256)
 // slot per (wave, fit) segment
 template <typename In, int U, int MAXC>
 __global__ void __launch_bounds__(256)
-    k_moments_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t tile,
+    k_moments_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y,
                          int64_t W, int mis, int maxm) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     const int stride = nacc(maxm);
     const int rl = rec_len(maxm);
-    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, tile, wave, W,
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, wave, W,
                         [&](int64_t, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
         if (mt.st != LSEFIT_OK) return;
         const double c = mt.c;
@@ -721,10 +721,10 @@ __global__ void __launch_bounds__(256)
 template <typename In, int U, int MAXC>
 __global__ void __launch_bounds__(256)
     k_residual_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y,
-                          In* __restrict__ resid, int64_t tile, int64_t W, int mis, int maxm) {
+                          In* __restrict__ resid, int64_t W, int mis, int maxm) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     const int rl = rec_len(maxm);
-    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, tile, wave, W,
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, wave, W,
                         [&](int64_t f, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
         if (mt.st != LSEFIT_OK) {
             if (resid)
@@ -805,17 +805,17 @@ hipError_t moments_cheb_typed(const FitDesc& d, const Work& w, int maxm, const I
     const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
     if (is_single(d)) {
         auto body = [&]<int M>() {
-            hipLaunchKernelGGL((k_moments_cheb_single<In, 2, M>), grid, block, 0, st, d, w, x, y, L.waves, mis, ra);
+            launch_timed((k_moments_cheb_single<In, 2, M>), grid, block, st, d, w, x, y, L.waves, mis, ra);
         };
         dispatch_degree<kChebMax>(d.degree, body);
     } else if (maxm <= 4) {
-        hipLaunchKernelGGL((k_moments_cheb_batch<In, 2, 4>), grid, block, 0, st, d, w, x, y, L.tile, L.waves, mis,
+        launch_timed((k_moments_cheb_batch<In, 2, 4>), grid, block, st, d, w, x, y, L.waves, mis,
                            maxm);
     } else if (maxm <= 8) {
-        hipLaunchKernelGGL((k_moments_cheb_batch<In, 2, 8>), grid, block, 0, st, d, w, x, y, L.tile, L.waves, mis,
+        launch_timed((k_moments_cheb_batch<In, 2, 8>), grid, block, st, d, w, x, y, L.waves, mis,
                            maxm);
     } else {
-        hipLaunchKernelGGL((k_moments_cheb_batch<In, 2, kChebMax>), grid, block, 0, st, d, w, x, y, L.tile, L.waves,
+        launch_timed((k_moments_cheb_batch<In, 2, kChebMax>), grid, block, st, d, w, x, y, L.waves,
                            mis, maxm);
     }
     return hipGetLastError();
@@ -826,17 +826,17 @@ hipError_t range_cheb_typed(const FitDesc& d, const Work& w, int maxm, const In*
                             hipStream_t st) {
     const int64_t G = L.waves / L.wpb;
     if (is_single(d)) {
-        hipLaunchKernelGGL((k_range_cheb_single<In>), dim3(G), dim3(L.wpb * kWave), 0, st, d, w, x, L.waves, mis);
+        launch_timed((k_range_cheb_single<In>), dim3(G), dim3(L.wpb * kWave), st, d, w, x, L.waves, mis);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_range_fold_single, dim3(1), dim3(256), 0, st, w, G);
+        launch_timed(k_range_fold_single, dim3(1), dim3(256), st, w, G);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_range_cheb_batch<In>), dim3(G), dim3(L.wpb * kWave), 0, st, d, w, x, L.tile, L.waves,
+    launch_timed((k_range_cheb_batch<In>), dim3(G), dim3(L.wpb * kWave), st, d, w, x, L.waves,
                        mis, maxm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_range_fold_batch, dim3((d.batch + 255) / 256), dim3(256), 0, st, d, w, L.waves, maxm);
+    launch_timed(k_range_fold_batch, dim3((d.batch + 255) / 256), dim3(256), st, d, w, L.waves, maxm);
     return hipGetLastError();
 }
 
@@ -855,7 +855,7 @@ hipError_t launch_moments_cheb(const FitDesc& d, const Work& w, int maxm, int dt
 
 hipError_t launch_solve_cheb_moments(const double* moments, const Work& w, int m, const Finish& fz,
                                     hipStream_t st) {
-    auto body = [&]<int M>() { hipLaunchKernelGGL(k_solve_cheb_moments<M>, dim3(1), dim3(kWave), 0, st, moments, w, fz); };
+    auto body = [&]<int M>() { launch_timed(k_solve_cheb_moments<M>, dim3(1), dim3(kWave), st, moments, w, fz); };
     dispatch_degree<kChebMax>(m, body);
     return hipGetLastError();
 }
@@ -950,10 +950,10 @@ struct ChebAdjointPoint {
 template <typename In, int U, int MAXC>
 __global__ void __launch_bounds__(256)
     k_adjoint_cheb_stream(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y,
-                          In* __restrict__ gx, In* __restrict__ gy, int64_t tile, int64_t W, int mis, int maxm) {
+                          In* __restrict__ gx, In* __restrict__ gy, int64_t W, int mis, int maxm) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     const int rl = rec_len(maxm);
-    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, tile, wave, W,
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, wave, W,
                         [&](int64_t f, int64_t lo, int64_t hi, int64_t, const SegMeta& mt) {
         if (mt.st != LSEFIT_OK) {
             adjoint_nan(gx, gy, lo, hi);
@@ -973,9 +973,9 @@ hipError_t adjoint_cheb_typed(const FitDesc& d, const Work& w, int maxm, const I
                               const Launch& L, int mis, hipStream_t st) {
     const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
     switch (L.unroll) {
-        case 1: hipLaunchKernelGGL((k_adjoint_cheb_stream<In, 1, MAXC>), grid, block, 0, st, d, w, x, y, gx, gy, L.tile, L.waves, mis, maxm); break;
-        case 2: hipLaunchKernelGGL((k_adjoint_cheb_stream<In, 2, MAXC>), grid, block, 0, st, d, w, x, y, gx, gy, L.tile, L.waves, mis, maxm); break;
-        case 4: hipLaunchKernelGGL((k_adjoint_cheb_stream<In, 4, MAXC>), grid, block, 0, st, d, w, x, y, gx, gy, L.tile, L.waves, mis, maxm); break;
+        case 1: launch_timed((k_adjoint_cheb_stream<In, 1, MAXC>), grid, block, st, d, w, x, y, gx, gy, L.waves, mis, maxm); break;
+        case 2: launch_timed((k_adjoint_cheb_stream<In, 2, MAXC>), grid, block, st, d, w, x, y, gx, gy, L.waves, mis, maxm); break;
+        case 4: launch_timed((k_adjoint_cheb_stream<In, 4, MAXC>), grid, block, st, d, w, x, y, gx, gy, L.waves, mis, maxm); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1018,27 +1018,27 @@ hipError_t residual_cheb_typed(const FitDesc& d, const Work& w, int maxm, const 
     const dim3 grid(G), block(L.wpb * kWave);
     if (is_single(d)) {
         auto body = [&]<int M>() {
-            hipLaunchKernelGGL((k_residual_cheb_single<In, U, M>), grid, block, 0, st, d, w, x, y, resid, L.waves,
+            launch_timed((k_residual_cheb_single<In, U, M>), grid, block, st, d, w, x, y, resid, L.waves,
                                mis, maxm);
         };
         dispatch_degree<kChebMax>(d.degree, body);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_sse_fold_single, dim3(1), dim3(256), 0, st, w, G, sse);
+        launch_timed(k_sse_fold_single, dim3(1), dim3(256), st, w, G, sse);
         return hipGetLastError();
     }
     if (maxm <= 4)
-        hipLaunchKernelGGL((k_residual_cheb_batch<In, U, 4>), grid, block, 0, st, d, w, x, y, resid, L.tile, L.waves,
+        launch_timed((k_residual_cheb_batch<In, U, 4>), grid, block, st, d, w, x, y, resid, L.waves,
                            mis, maxm);
     else if (maxm <= 8)
-        hipLaunchKernelGGL((k_residual_cheb_batch<In, U, 8>), grid, block, 0, st, d, w, x, y, resid, L.tile, L.waves,
+        launch_timed((k_residual_cheb_batch<In, U, 8>), grid, block, st, d, w, x, y, resid, L.waves,
                            mis, maxm);
     else
-        hipLaunchKernelGGL((k_residual_cheb_batch<In, U, kChebMax>), grid, block, 0, st, d, w, x, y, resid, L.tile,
+        launch_timed((k_residual_cheb_batch<In, U, kChebMax>), grid, block, st, d, w, x, y, resid,
                            L.waves, mis, maxm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sse_fold_batch, dim3((d.batch + 255) / 256), dim3(256), 0, st, d, w, L.waves, sse);
+    launch_timed(k_sse_fold_batch, dim3((d.batch + 255) / 256), dim3(256), st, d, w, L.waves, sse);
     return hipGetLastError();
 }
 
@@ -1055,24 +1055,24 @@ hipError_t launch_finish_cheb(const FitDesc& d, const Work& w, int maxm, int64_t
                               hipStream_t st) {
     if (is_single(d)) {
         auto body = [&]<int M>() {
-            hipLaunchKernelGGL(k_finish_cheb_single<M>, dim3(1), dim3(finish_threads(W)), 0, st, d, w, W, maxm, fz);
+            launch_timed(k_finish_cheb_single<M>, dim3(1), dim3(finish_threads(W)), st, d, w, W, maxm, fz);
         };
         dispatch_degree<kChebMax>(d.degree, body);
         return hipGetLastError();
     }
     if (maxm <= 4 && !fz.write_b && !fz.moments_out) {
-        hipLaunchKernelGGL(k_finish_cheb_lane<4>, dim3((d.batch + 255) / 256), dim3(256), 0, st, d, w, W, maxm, fz);
+        launch_timed(k_finish_cheb_lane<4>, dim3((d.batch + 255) / 256), dim3(256), st, d, w, W, maxm, fz);
         return hipGetLastError();
     }
     int64_t blocks = (d.batch + 3) / 4;
     if (blocks > 65536) blocks = 65536;
     const dim3 grid(blocks), block(256);
     if (maxm <= 4)
-        hipLaunchKernelGGL(k_finish_cheb_batch<4>, grid, block, 0, st, d, w, W, maxm, fz);
+        launch_timed(k_finish_cheb_batch<4>, grid, block, st, d, w, W, maxm, fz);
     else if (maxm <= 8)
-        hipLaunchKernelGGL(k_finish_cheb_batch<8>, grid, block, 0, st, d, w, W, maxm, fz);
+        launch_timed(k_finish_cheb_batch<8>, grid, block, st, d, w, W, maxm, fz);
     else
-        hipLaunchKernelGGL(k_finish_cheb_batch<kChebMax>, grid, block, 0, st, d, w, W, maxm, fz);
+        launch_timed(k_finish_cheb_batch<kChebMax>, grid, block, st, d, w, W, maxm, fz);
     return hipGetLastError();
 }
 

@@ -50,7 +50,8 @@ __device__ inline int fit_deg(const FitDesc& d, int64_t f) { return d.degrees ? 
 
 // Workspace regions (device pointers carved out of the caller's buffer).
 struct Work {
-    int64_t* tile_start;  // [B+1] first tile of each fit; tile_start[B] = number of tiles
+    int64_t* tile_start;  // [B+2] first tile of each fit; tile_start[B] = number of tiles,
+                          // tile_start[B+1] = points per tile
     int32_t* pstatus;     // [B] status found while building the tile table
     double* rec;          // [B * rec_len(M)]
     double* part;         // [(W + B) * nacc(M)] per-(wave, fit) partial sums (batched) or
@@ -148,12 +149,16 @@ __device__ inline void snap_range(double lo, double hi, double* c_out, double* s
 // tile_start[f] .. tile_start[f+1]-1 (tile points each, the last one ragged);
 // wave w owns tiles floor(w NT / W) .. floor((w+1) NT / W) - 1 and streams the
 // part of each fit inside that range as one segment.  (w, f) pairs that share
-// a tile map one-to-one onto partial slots w + f.
+// a tile map one-to-one onto partial slots w + f.  NT = tile_start[B] and the
+// tile size the table was built with, tile_start[B+1], are read from the table
+// itself, so a later pass over the same workspace (the adjoint, the residuals)
+// cuts every fit where the forward pass did, whatever its own launch shape.
 // ---------------------------------------------------------------------------
 template <class Fn>
-__device__ inline void walk_segments(const FitDesc& d, const int64_t* __restrict__ tile_start, int64_t tile,
-                                     int64_t wave, int64_t W, Fn&& fn) {
+__device__ inline void walk_segments(const FitDesc& d, const int64_t* __restrict__ tile_start, int64_t wave,
+                                     int64_t W, Fn&& fn) {
     const int64_t NT = tile_start[d.batch];
+    const int64_t tile = tile_start[d.batch + 1];
     const int64_t t0 = wave * NT / W;
     const int64_t t1 = (wave + 1) * NT / W;
     if (t0 >= t1) return;
@@ -211,8 +216,9 @@ __device__ inline SegMeta load_meta(const FitDesc& d, const int64_t* __restrict_
 template <class Fn>
 __device__ inline void walk_segments_ahead(const FitDesc& d, const int64_t* __restrict__ tile_start,
                                            const int32_t* __restrict__ pstatus, const double* __restrict__ rec,
-                                           int rl, int64_t tile, int64_t wave, int64_t W, Fn&& fn) {
+                                           int rl, int64_t wave, int64_t W, Fn&& fn) {
     const int64_t NT = tile_start[d.batch];
+    const int64_t tile = tile_start[d.batch + 1];
     const int64_t t0 = wave * NT / W;
     const int64_t t1 = (wave + 1) * NT / W;
     if (t0 >= t1) return;

@@ -14,7 +14,8 @@ namespace lsefit {
 // points -> SINGULAR), writes (c, s) (given, or from the first 8 and the last
 // 8 points of its x, all of a shorter fit, loaded in one round), and
 // scans the tile counts of its block.  Pass B adds the tile totals of the
-// blocks before it.  Integer sums: the result does not depend on the order.
+// blocks before it and stores the number of tiles and the tile size after the
+// last fit's entry.  Integer sums: the result does not depend on the order.
 // ---------------------------------------------------------------------------
 constexpr int kRangeBatchSamples = 16;
 
@@ -78,7 +79,7 @@ __global__ void __launch_bounds__(kPlanThreads)
 }
 
 __global__ void __launch_bounds__(kPlanThreads)
-    k_plan_offsets(FitDesc d, Work w, const int64_t* __restrict__ block_tot, int64_t nblocks) {
+    k_plan_offsets(FitDesc d, Work w, const int64_t* __restrict__ block_tot, int64_t nblocks, int64_t tile) {
     __shared__ int64_t sh[kPlanThreads];
     const int tid = threadIdx.x;
     int64_t part = 0;
@@ -92,7 +93,10 @@ __global__ void __launch_bounds__(kPlanThreads)
     const int64_t base = sh[0];
     const int64_t f = (int64_t)blockIdx.x * kPlanThreads + tid;
     if (f < d.batch) w.tile_start[f] += base;
-    if (blockIdx.x == nblocks - 1 && tid == 0) w.tile_start[d.batch] = base + block_tot[blockIdx.x];
+    if (blockIdx.x == nblocks - 1 && tid == 0) {
+        w.tile_start[d.batch] = base + block_tot[blockIdx.x];
+        w.tile_start[d.batch + 1] = tile;   // the table's own tile size, for every later pass over it
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -151,8 +155,71 @@ hipError_t launch_read_probe(const float* x, const float* y, int64_t nvec, const
     const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
 #define LSEFIT_PROBE(UU, PP, NN)                                                                                  \
     if (L.unroll == UU && pattern == PP && nt == NN) {                                                            \
-        hipLaunchKernelGGL((k_read_probe<UU, PP, NN>), grid, block, 0, st, x, y, nvec, L.waves, out);             \
+        launch_timed((k_read_probe<UU, PP, NN>), grid, block, st, x, y, nvec, L.waves, out);             \
         return hipGetLastError();                                                                                 \
+    }
+    LSEFIT_PROBE(1, 0, false) LSEFIT_PROBE(2, 0, false) LSEFIT_PROBE(4, 0, false)
+    LSEFIT_PROBE(1, 0, true) LSEFIT_PROBE(2, 0, true) LSEFIT_PROBE(4, 0, true)
+    LSEFIT_PROBE(1, 1, false) LSEFIT_PROBE(2, 1, false) LSEFIT_PROBE(4, 1, false)
+    LSEFIT_PROBE(1, 1, true) LSEFIT_PROBE(2, 1, true) LSEFIT_PROBE(4, 1, true)
+#undef LSEFIT_PROBE
+    return hipErrorInvalidValue;
+}
+
+// copy probe (measurement only): reads x and y and writes them to ox and oy
+// with 16-byte loads and stores, the traffic of the adjoint pass (8 bytes read
+// and 8 bytes written per float32 point); load patterns as the read probe
+template <int U, int PATTERN, bool NT>
+__global__ void __launch_bounds__(256)
+    k_copy_probe(const float* __restrict__ x, const float* __restrict__ y, float* __restrict__ ox,
+                 float* __restrict__ oy, int64_t nvec, int64_t W) {
+    typedef float V __attribute__((ext_vector_type(4)));
+    const V* xv = reinterpret_cast<const V*>(x);
+    const V* yv = reinterpret_cast<const V*>(y);
+    V* oxv = reinterpret_cast<V*>(ox);
+    V* oyv = reinterpret_cast<V*>(oy);
+    const int lane = lane_id();
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    int64_t j, end, step;
+    if (PATTERN == 0) {
+        j = wave * nvec / W + lane;
+        end = (wave + 1) * nvec / W;
+        step = kWave;
+    } else {
+        j = wave * kWave + lane;
+        end = nvec;
+        step = W * kWave;
+    }
+    auto store = [](V* p, const V& v) {
+        if constexpr (NT) __builtin_nontemporal_store(v, p);
+        else *p = v;
+    };
+    for (; j + (int64_t)(U - 1) * step < end; j += (int64_t)U * step) {
+        V a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = probe_load<NT>(xv + j + u * step);
+            b[u] = probe_load<NT>(yv + j + u * step);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            store(oxv + j + u * step, a[u]);
+            store(oyv + j + u * step, b[u]);
+        }
+    }
+    for (; j < end; j += step) {
+        store(oxv + j, probe_load<NT>(xv + j));
+        store(oyv + j, probe_load<NT>(yv + j));
+    }
+}
+
+hipError_t launch_copy_probe(const float* x, const float* y, float* ox, float* oy, int64_t nvec, const Launch& L,
+                             int pattern, bool nt, hipStream_t st) {
+    const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
+#define LSEFIT_PROBE(UU, PP, NN)                                                                 \
+    if (L.unroll == UU && pattern == PP && nt == NN) {                                           \
+        launch_timed((k_copy_probe<UU, PP, NN>), grid, block, st, x, y, ox, oy, nvec, L.waves);  \
+        return hipGetLastError();                                                                \
     }
     LSEFIT_PROBE(1, 0, false) LSEFIT_PROBE(2, 0, false) LSEFIT_PROBE(4, 0, false)
     LSEFIT_PROBE(1, 0, true) LSEFIT_PROBE(2, 0, true) LSEFIT_PROBE(4, 0, true)
@@ -192,7 +259,7 @@ hipError_t launch_plan(const FitDesc& d, const Work& w, int maxM, int64_t tile, 
                            range_given ? 1 : 0, c, s, (const double*)x, block_tot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_offsets, dim3(nb), dim3(kPlanThreads), 0, st, d, w, block_tot, nb);
+    hipLaunchKernelGGL(k_plan_offsets, dim3(nb), dim3(kPlanThreads), 0, st, d, w, block_tot, nb, tile);
     return hipGetLastError();
 }
 

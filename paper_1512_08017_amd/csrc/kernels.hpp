@@ -2,12 +2,36 @@
 // dispatch.hip; Chebyshev basis: cheb.hip; streaming QR: tsqr.hip).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "device.hpp"
 
 namespace lsefit {
+
+// Kernel timing (lsefit_timing_*).  The host side arms a pair of events on its
+// thread before it calls a launcher; the first kernel that launcher starts
+// through launch_timed goes out through hipExtLaunchKernelGGL with that pair,
+// so that the events take the start and end timestamps of that kernel's own
+// dispatch (no separate event packets on the stream).  With nothing armed,
+// launch_timed is a plain launch.
+struct TimingSlot {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+TimingSlot& timing_slot();   // this host thread's slot (api.hip)
+
+template <typename K, typename... Args>
+inline void launch_timed(K kernel, const dim3& grid, const dim3& block, hipStream_t st, Args... args) {
+    TimingSlot& t = timing_slot();
+    if (t.start && !t.used) {
+        t.used = true;
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, t.start, t.stop, 0, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    }
+}
 
 struct Launch {
     int64_t waves;        // total waves of the persistent grid
@@ -30,6 +54,9 @@ struct Finish {
     int32_t* status;       // [B]
     double* moments_out;   // nullable: [3m+4] = c, s, S_0..S_2m, T_0..T_m
     int solver;            // lsefit_solver
+    int32_t b_at = -1;     // >= 0: batched t-basis output, b_0..b_m of fit f from
+                           // coef[f * coef_stride + b_at] on
+    int32_t cs_at = -1;    // >= 0: the fit's c and s at coef[f * coef_stride + cs_at] and + 1
 };
 
 // Range of a single fit: given (c, s), or derived by the streaming kernel itself.
@@ -83,6 +110,10 @@ hipError_t launch_residual(const FitDesc& d, const Work& w, int maxM, int dtype,
 // one float per block into out.
 hipError_t launch_read_probe(const float* x, const float* y, int64_t nvec, const Launch& L, int pattern, bool nt,
                              float* out, hipStream_t st);
+// Copy probe: x, y -> ox, oy over nvec 16-byte vectors each (8 B read and 8 B
+// written per float32 point, the traffic of the adjoint pass).
+hipError_t launch_copy_probe(const float* x, const float* y, float* ox, float* oy, int64_t nvec, const Launch& L,
+                             int pattern, bool nt, hipStream_t st);
 
 // Chebyshev basis (degree up to LSEFIT_MAX_DEGREE_CHEBYSHEV, float64 sums):
 // streaming pass, per-fit finish (single fit: W = number of block partials),

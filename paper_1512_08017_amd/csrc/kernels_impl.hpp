@@ -393,6 +393,11 @@ __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, co
         r[rec_b(MAXM) + k] = b[0][k];
         a_out[k] = a[k];
         if (fz.write_b) a_out[N + k] = b[0][k];
+        if (fz.b_at >= 0) a_out[fz.b_at + k] = b[0][k];
+    }
+    if (fz.cs_at >= 0) {
+        a_out[fz.cs_at] = c;
+        a_out[fz.cs_at + 1] = s;
     }
     w.pstatus[f] = st;
     fz.status[f] = st;
@@ -413,6 +418,12 @@ __device__ inline void fail_fit(const FitDesc& d, const Work& w, int64_t f, cons
     for (int k = 0; k < n; ++k) a_out[k] = NAN;
     if (fz.write_b && valid)
         for (int k = 0; k < n; ++k) a_out[n + k] = NAN;
+    if (fz.b_at >= 0 && valid)
+        for (int k = 0; k < n; ++k) a_out[fz.b_at + k] = NAN;
+    if (fz.cs_at >= 0) {   // the range the plan recorded for the fit
+        a_out[fz.cs_at] = w.rec[f * rec_len(MAXM)];
+        a_out[fz.cs_at + 1] = w.rec[f * rec_len(MAXM) + 1];
+    }
     fz.status[f] = st;
 }
 
@@ -500,12 +511,14 @@ __device__ inline void finish_fit_wave(const FitDesc& d, const Work& w, int64_t 
         if (__ballot(mine && !isfinite(a))) st = LSEFIT_ERR_NONFINITE;
     }
     if (st != LSEFIT_OK) a = b = NAN;
+    double* a_out = fz.coef + f * (int64_t)fz.coef_stride;
     if (mine) {
-        double* a_out = fz.coef + f * (int64_t)fz.coef_stride;
         r[rec_b(MAXM) + lane] = b;
         a_out[lane] = a;
         if (fz.write_b) a_out[N + lane] = b;
+        if (fz.b_at >= 0) a_out[fz.b_at + lane] = b;
     }
+    if (fz.cs_at >= 0 && lane < 2) a_out[fz.cs_at + lane] = lane == 0 ? c : s;
     if (lane == 0) {
         w.pstatus[f] = st;
         fz.status[f] = st;
@@ -693,7 +706,7 @@ __device__ inline void single_block_partial(const Work& w, const double (&v)[K])
 // ---------------------------------------------------------------------------
 template <int MAXM, int PREC, typename In, int U>
 __global__ void __launch_bounds__(256)
-    k_moments(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t tile, int64_t W,
+    k_moments(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t W,
               int mis, RangeArg ra) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     constexpr int stride = nacc(MAXM);
@@ -715,7 +728,7 @@ __global__ void __launch_bounds__(256)
         dispatch_degree<MAXM>(d.degree, body);
         return;
     }
-    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, tile, wave, W,
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, wave, W,
                         [&](int64_t f, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
         if (mt.st != LSEFIT_OK) return;
         const double inv_s = 1.0 / mt.s;
@@ -740,7 +753,7 @@ __global__ void __launch_bounds__(256)
 
 template <int MAXM, typename In, int U>
 __global__ void __launch_bounds__(256)
-    k_refine(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t tile, int64_t W,
+    k_refine(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t W,
              int mis) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     constexpr int stride = nacc(MAXM);
@@ -766,7 +779,7 @@ __global__ void __launch_bounds__(256)
         dispatch_degree<MAXM>(d.degree, body);
         return;
     }
-    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, tile, wave, W,
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, wave, W,
                         [&](int64_t f, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
         if (mt.st != LSEFIT_OK) return;
         const double* r = w.rec + f * rl;
@@ -984,10 +997,10 @@ __device__ inline void adjoint_nan(In* __restrict__ gx, In* __restrict__ gy, int
 template <int MAXM, typename In, int U>
 __global__ void __launch_bounds__(256)
     k_adjoint_stream(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ gx,
-                     In* __restrict__ gy, int64_t tile, int64_t W, int mis) {
+                     In* __restrict__ gy, int64_t W, int mis) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     constexpr int rl = rec_len(MAXM);
-    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t) {
+    walk_segments(d, w.tile_start, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t) {
         if (w.pstatus[f] != LSEFIT_OK) {
             adjoint_nan(gx, gy, lo, hi);
             return;
@@ -1083,7 +1096,7 @@ __device__ inline void resid_points(const In* __restrict__ x, const In* __restri
 template <int MAXM, typename In, int U>
 __global__ void __launch_bounds__(256)
     k_residual(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ resid,
-               int64_t tile, int64_t W, int mis) {
+               int64_t W, int mis) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     constexpr int stride = nacc(MAXM);
     constexpr int rl = rec_len(MAXM);
@@ -1104,7 +1117,7 @@ __global__ void __launch_bounds__(256)
         dispatch_degree<MAXM>(d.degree, body);
         return;
     }
-    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
+    walk_segments(d, w.tile_start, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
         if (w.pstatus[f] != LSEFIT_OK) {
             if (resid)
                 for (int64_t i = lo + lane_id(); i < hi; i += kWave) resid[i] = (In)NAN;
@@ -1135,9 +1148,9 @@ hipError_t Launchers<MAXM>::moments_t(const FitDesc& d, const Work& w, const voi
     const In* xx = (const In*)x;
     const In* yy = (const In*)y;
     switch (L.unroll) {
-        case 1: hipLaunchKernelGGL((k_moments<MAXM, PREC, In, 1>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis, ra); break;
-        case 2: hipLaunchKernelGGL((k_moments<MAXM, PREC, In, 2>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis, ra); break;
-        case 4: hipLaunchKernelGGL((k_moments<MAXM, PREC, In, 4>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis, ra); break;
+        case 1: launch_timed((k_moments<MAXM, PREC, In, 1>), grid, block, st, d, w, xx, yy, L.waves, mis, ra); break;
+        case 2: launch_timed((k_moments<MAXM, PREC, In, 2>), grid, block, st, d, w, xx, yy, L.waves, mis, ra); break;
+        case 4: launch_timed((k_moments<MAXM, PREC, In, 4>), grid, block, st, d, w, xx, yy, L.waves, mis, ra); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1161,17 +1174,17 @@ hipError_t Launchers<MAXM>::combine(const FitDesc& d, const Work& w, const Launc
     if (by_block) {
         int64_t blocks = d.batch < 65536 ? d.batch : 65536;
         if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL(k_combine_block<MAXM>, dim3(blocks), dim3(kCombineThreads), 0, st, d, w, L.waves, fz);
+        launch_timed(k_combine_block<MAXM>, dim3(blocks), dim3(kCombineThreads), st, d, w, L.waves, fz);
     } else {
         const int64_t blocks = (d.batch + 255) / 256;
-        hipLaunchKernelGGL(k_combine_lane<MAXM>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, d, w, L.waves, fz);
+        launch_timed(k_combine_lane<MAXM>, dim3(blocks > 0 ? blocks : 1), dim3(256), st, d, w, L.waves, fz);
     }
     return hipGetLastError();
 }
 
 template <int MAXM>
 hipError_t Launchers<MAXM>::finish_single(const FitDesc& d, const Work& w, int64_t G, const Finish& fz, hipStream_t st) {
-    hipLaunchKernelGGL(k_finish_single<MAXM>, dim3(1), dim3(finish_threads(G)), 0, st, d, w, G, fz);
+    launch_timed(k_finish_single<MAXM>, dim3(1), dim3(finish_threads(G)), st, d, w, G, fz);
     return hipGetLastError();
 }
 
@@ -1182,7 +1195,7 @@ hipError_t Launchers<MAXM>::solve_moments(const double* moments, const Work& w, 
 #define LSEFIT_SOLVE_CASE(MV)                                                                                   \
     case MV:                                                                                                    \
         if constexpr (MV <= MAXM) {                                                                             \
-            hipLaunchKernelGGL((k_solve_moments<MV, MAXM>), dim3(1), dim3(64), 0, st, moments, w, solver, coef, status); \
+            launch_timed((k_solve_moments<MV, MAXM>), dim3(1), dim3(64), st, moments, w, solver, coef, status); \
             return hipGetLastError();                                                                           \
         }                                                                                                       \
         break;
@@ -1208,9 +1221,9 @@ hipError_t Launchers<MAXM>::refine_t(const FitDesc& d, const Work& w, const void
     const In* xx = (const In*)x;
     const In* yy = (const In*)y;
     switch (L.unroll) {
-        case 1: hipLaunchKernelGGL((k_refine<MAXM, In, 1>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis); break;
-        case 2: hipLaunchKernelGGL((k_refine<MAXM, In, 2>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis); break;
-        case 4: hipLaunchKernelGGL((k_refine<MAXM, In, 4>), grid, block, 0, st, d, w, xx, yy, L.tile, L.waves, mis); break;
+        case 1: launch_timed((k_refine<MAXM, In, 1>), grid, block, st, d, w, xx, yy, L.waves, mis); break;
+        case 2: launch_timed((k_refine<MAXM, In, 2>), grid, block, st, d, w, xx, yy, L.waves, mis); break;
+        case 4: launch_timed((k_refine<MAXM, In, 4>), grid, block, st, d, w, xx, yy, L.waves, mis); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1234,11 +1247,11 @@ hipError_t Launchers<MAXM>::adjoint(const FitDesc& d, const Work& w, int solver,
     const dim3 grid(blocks_for(L)), block(L.wpb * kWave);
 #define LSEFIT_ADJ(UU)                                                                                           \
     if (dtype == LSEFIT_F32)                                                                                     \
-        hipLaunchKernelGGL((k_adjoint_stream<MAXM, float, UU>), grid, block, 0, st, d, w, (const float*)x,      \
-                           (const float*)y, (float*)gx, (float*)gy, L.tile, L.waves, mis);                       \
+        launch_timed((k_adjoint_stream<MAXM, float, UU>), grid, block, st, d, w, (const float*)x,      \
+                           (const float*)y, (float*)gx, (float*)gy, L.waves, mis);                       \
     else                                                                                                         \
-        hipLaunchKernelGGL((k_adjoint_stream<MAXM, double, UU>), grid, block, 0, st, d, w, (const double*)x,    \
-                           (const double*)y, (double*)gx, (double*)gy, L.tile, L.waves, mis);
+        launch_timed((k_adjoint_stream<MAXM, double, UU>), grid, block, st, d, w, (const double*)x,    \
+                           (const double*)y, (double*)gx, (double*)gy, L.waves, mis);
     switch (L.unroll) {
         case 1: LSEFIT_ADJ(1) break;
         case 2: LSEFIT_ADJ(2) break;
@@ -1255,11 +1268,11 @@ hipError_t Launchers<MAXM>::residual(const FitDesc& d, const Work& w, int dtype,
     const dim3 grid(blocks_for(L)), block(L.wpb * kWave);
 #define LSEFIT_RES(UU)                                                                                           \
     if (dtype == LSEFIT_F32)                                                                                     \
-        hipLaunchKernelGGL((k_residual<MAXM, float, UU>), grid, block, 0, st, d, w, (const float*)x,            \
-                           (const float*)y, (float*)resid, L.tile, L.waves, mis);                                \
+        launch_timed((k_residual<MAXM, float, UU>), grid, block, st, d, w, (const float*)x,            \
+                           (const float*)y, (float*)resid, L.waves, mis);                                \
     else                                                                                                         \
-        hipLaunchKernelGGL((k_residual<MAXM, double, UU>), grid, block, 0, st, d, w, (const double*)x,          \
-                           (const double*)y, (double*)resid, L.tile, L.waves, mis);
+        launch_timed((k_residual<MAXM, double, UU>), grid, block, st, d, w, (const double*)x,          \
+                           (const double*)y, (double*)resid, L.waves, mis);
     switch (L.unroll) {
         case 1: LSEFIT_RES(1) break;
         case 2: LSEFIT_RES(2) break;

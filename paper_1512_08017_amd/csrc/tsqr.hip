@@ -364,14 +364,14 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 template <typename In, int MAXC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(qr_waves_per_eu(MAXC))))
-    k_qr_batch(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t tile, int64_t W,
+    k_qr_batch(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t W,
                int mis, int maxm) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     const int stride = qr_len(maxm);
     const int rl = rec_len(maxm);
     __shared__ double tab[kRecipRows];
     fill_recip_rows(tab);
-    walk_segments(d, w.tile_start, tile, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
+    walk_segments(d, w.tile_start, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t slot) {
         if (w.pstatus[f] != LSEFIT_OK) return;
         const double c = w.rec[f * rl + 0];
         const double inv_s = 1.0 / w.rec[f * rl + 1];
@@ -431,10 +431,10 @@ hipError_t launch_qr_single(const FitDesc& d, const Work& w, int dtype, const vo
     const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
     auto body = [&]<int M>() {
         if (dtype == LSEFIT_F32)
-            hipLaunchKernelGGL((k_qr_single<float, 1, M>), grid, block, 0, st, d, w, (const float*)x,
+            launch_timed((k_qr_single<float, 1, M>), grid, block, st, d, w, (const float*)x,
                                (const float*)y, L.waves, mis, ra);
         else
-            hipLaunchKernelGGL((k_qr_single<double, 1, M>), grid, block, 0, st, d, w, (const double*)x,
+            launch_timed((k_qr_single<double, 1, M>), grid, block, st, d, w, (const double*)x,
                                (const double*)y, L.waves, mis, ra);
     };
     dispatch_degree<LSEFIT_MAX_DEGREE>(d.degree, body);
@@ -446,11 +446,11 @@ hipError_t launch_qr_batch(const FitDesc& d, const Work& w, int maxm, int dtype,
     const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
     auto go = [&]<int MAXC>() {
         if (dtype == LSEFIT_F32)
-            hipLaunchKernelGGL((k_qr_batch<float, MAXC>), grid, block, 0, st, d, w, (const float*)x, (const float*)y,
-                               L.tile, L.waves, mis, maxm);
+            launch_timed((k_qr_batch<float, MAXC>), grid, block, st, d, w, (const float*)x, (const float*)y,
+                               L.waves, mis, maxm);
         else
-            hipLaunchKernelGGL((k_qr_batch<double, MAXC>), grid, block, 0, st, d, w, (const double*)x,
-                               (const double*)y, L.tile, L.waves, mis, maxm);
+            launch_timed((k_qr_batch<double, MAXC>), grid, block, st, d, w, (const double*)x,
+                               (const double*)y, L.waves, mis, maxm);
     };
     if (maxm <= 4) go.template operator()<4>();
     else go.template operator()<LSEFIT_MAX_DEGREE>();
@@ -461,10 +461,10 @@ hipError_t launch_qr_combine(const FitDesc& d, const Work& w, int maxm, int64_t 
                              int32_t* status, double* sse, hipStream_t st) {
     const int64_t blocks = (d.batch + 255) / 256;
     if (maxm <= 4)
-        hipLaunchKernelGGL(k_qr_combine<4>, dim3(blocks), dim3(256), 0, st, d, w, W, maxm, coef, coef_stride, status,
+        launch_timed(k_qr_combine<4>, dim3(blocks), dim3(256), st, d, w, W, maxm, coef, coef_stride, status,
                            sse);
     else
-        hipLaunchKernelGGL(k_qr_combine<LSEFIT_MAX_DEGREE>, dim3(blocks), dim3(256), 0, st, d, w, W, maxm, coef,
+        launch_timed(k_qr_combine<LSEFIT_MAX_DEGREE>, dim3(blocks), dim3(256), st, d, w, W, maxm, coef,
                            coef_stride, status, sse);
     return hipGetLastError();
 }
@@ -472,7 +472,7 @@ hipError_t launch_qr_combine(const FitDesc& d, const Work& w, int maxm, int64_t 
 hipError_t launch_qr_finish(const FitDesc& d, const Work& w, int64_t G, double* coef, int32_t* status, double* info,
                             hipStream_t st) {
     auto body = [&]<int M>() {
-        hipLaunchKernelGGL(k_qr_finish<M>, dim3(1), dim3(256), 0, st, d, w, G, d.degree, coef, status, info);
+        launch_timed(k_qr_finish<M>, dim3(1), dim3(256), st, d, w, G, d.degree, coef, status, info);
     };
     dispatch_degree<LSEFIT_MAX_DEGREE>(d.degree, body);
     return hipGetLastError();

@@ -146,7 +146,17 @@ def test_null_pointers_rejected():
 @pytest.mark.gpu
 def test_plan_tune_validates_against_the_plan():
     """A degree above the plan's, a short stride or a null pointer never reaches
-    the kernels (the plan's workspace is sized for its own maximum degree)."""
+    the kernels (the plan's workspace is sized for its own maximum degree).
+    Every pointer is a real device buffer of the call's shape."""
+    import torch
+    dev = torch.device("cuda:0")
+    x = torch.zeros(100, dtype=torch.float32, device=dev)
+    y = torch.zeros(100, dtype=torch.float32, device=dev)
+    off = torch.arange(0, 101, 10, dtype=torch.int64, device=dev)
+    deg = torch.full((10,), 2, dtype=torch.int32, device=dev)
+    coef = torch.zeros(10 * 4, dtype=torch.float64, device=dev)
+    status = torch.zeros(10, dtype=torch.int32, device=dev)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
     L = _lib.load()
     h = ctypes.c_void_p()
     assert L.fit_plan_create(ctypes.byref(h), 10, 2, _lib.F32, 0) == _lib.OK
@@ -154,14 +164,39 @@ def test_plan_tune_validates_against_the_plan():
         best = ctypes.c_double(0.0)
         o3 = _opt(degree=3)
         o2 = _opt(degree=2)
-        assert L.fit_plan_tune(h, FAKE, FAKE, FAKE, FAKE, 10, ctypes.byref(o3), FAKE, 4, FAKE, None, 1,
+        assert L.fit_plan_tune(h, p(x), p(y), p(off), p(deg), 10, ctypes.byref(o3), p(coef), 4, p(status), None, 1,
                                ctypes.byref(best)) == _lib.INVALID_ARG
-        assert L.fit_plan_tune(h, FAKE, FAKE, FAKE, FAKE, 10, ctypes.byref(o2), FAKE, 2, FAKE, None, 1,
+        assert L.fit_plan_tune(h, p(x), p(y), p(off), p(deg), 10, ctypes.byref(o2), p(coef), 2, p(status), None, 1,
                                ctypes.byref(best)) == _lib.INVALID_ARG
-        assert L.fit_plan_tune(h, None, FAKE, FAKE, FAKE, 10, ctypes.byref(o2), FAKE, 3, FAKE, None, 1,
+        assert L.fit_plan_tune(h, None, p(y), p(off), p(deg), 10, ctypes.byref(o2), p(coef), 3, p(status), None, 1,
                                ctypes.byref(best)) == _lib.INVALID_ARG
+        torch.cuda.synchronize()
     finally:
         L.fit_plan_destroy(h)
+
+
+def test_output_basis_validation():
+    """The t-basis output of batched fits needs its option value known and a
+    coefficient row of 2M + 4 entries; both are checked before any device work."""
+    L = _lib.load()
+    args = (FAKE, FAKE, FAKE, FAKE, 10, _lib.F32)
+    assert L.fit_batched(*args, ctypes.byref(_opt(output_basis=2)), None, FAKE, 1 << 30, FAKE, 10,
+                         FAKE, None) == _lib.INVALID_ARG
+    assert L.fit_batched(*args, ctypes.byref(_opt(output_basis=1)), None, FAKE, 1 << 30, FAKE, 9,
+                         FAKE, None) == _lib.INVALID_ARG            # needs 2 * 3 + 4 = 10
+    assert L.fit_batched(*args, ctypes.byref(_opt(output_basis=1)), None, FAKE, 8, FAKE, 10,
+                         FAKE, None) == _lib.WORKSPACE              # stride accepted, then the workspace
+    assert L.fit_batched(*args, ctypes.byref(_opt(output_basis=1, basis=1)), None, FAKE, 8, FAKE, 4,
+                         FAKE, None) == _lib.WORKSPACE              # ignored in the Chebyshev basis
+
+
+def test_copy_probe_validation():
+    L = _lib.load()
+    odd = ctypes.c_void_p(0x1004)
+    assert L.lsefit_copy_probe(FAKE, FAKE, None, FAKE, 1024, None, 0, 1, None) == _lib.INVALID_ARG
+    assert L.lsefit_copy_probe(FAKE, FAKE, odd, FAKE, 1024, None, 0, 1, None) == _lib.INVALID_ARG
+    assert L.lsefit_copy_probe(FAKE, FAKE, FAKE, FAKE, 1024, None, 2, 1, None) == _lib.INVALID_ARG
+    assert L.lsefit_copy_probe(FAKE, FAKE, FAKE, FAKE, 3, None, 0, 1, None) == _lib.INVALID_ARG
 
 
 def test_default_schedule_setter_validates():

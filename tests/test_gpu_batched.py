@@ -208,6 +208,96 @@ def test_adjoint_against_oracle(dtype):
         assert normwise(gy[lo:hi], ref["dy"]) <= tol, f
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-9), ("f32c", 1e-6)])
+def test_batched_t_basis_output(precision, tol):
+    """output_basis="x_and_t": rows [a | b | c | s]; b is the fit in t = (x - c)/s
+    (the oracle's fit with the same c and s), a is the plain call's output bit
+    for bit, and a fit with too few points has NaN a and b but its (c, s)."""
+    announce(f"batched t-basis output {precision}")
+    from oracle import fp64
+    bf = W.random_batch([5000, 20_000, 2, 777, 65_537], [5, 3, 2, 4, 5], seed=33, lo=1000.0, hi=1001.0)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    M = 5
+    coef, status, _ = lf.fit_batched(x, y, off, dg, M, precision=precision, output_basis="x_and_t")
+    plain, pstatus, _ = lf.fit_batched(x, y, off, dg, M, precision=precision)
+    torch.cuda.synchronize()
+    coef, status = coef.cpu().numpy(), status.cpu().numpy()
+    plain = plain.cpu().numpy()
+    assert coef.shape == (bf.batch, 2 * M + 4)
+    assert np.array_equal(status, pstatus.cpu().numpy())
+    for f in range(bf.batch):
+        m = int(bf.degrees[f])
+        lo, hi = bf.offsets[f], bf.offsets[f + 1]
+        c, s = coef[f, 2 * M + 2], coef[f, 2 * M + 3]
+        assert np.isfinite(c) and s > 0 and abs(c - 1000.5) <= 0.5
+        a, b = coef[f, : m + 1], coef[f, M + 1: M + 2 + m]
+        assert np.array_equal(a, plain[f, : m + 1], equal_nan=True)
+        if status[f] != 0:
+            assert np.isnan(a).all() and np.isnan(b).all()
+            continue
+        ref = fp64.fit(bf.x[lo:hi], bf.y[lo:hi], m, float(c), float(s))
+        assert normwise(b, ref["b"]) <= tol, f
+    assert status[2] == 2
+
+
+def test_adjoint_after_compensated_forward():
+    """Backward after a compensated-float32 forward: the adjoint solves with the
+    sums and refined coefficients that forward left in the workspace."""
+    announce("adjoint after an f32c forward")
+    bf = W.random_batch([4096, 1000, 257, 3000], [2, 3, 1, 3], seed=31, lo=-2.0, hi=3.0, with_target=True)
+    x = to_dev(bf.x).requires_grad_(True)
+    y = to_dev(bf.y).requires_grad_(True)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    target = torch.from_numpy(bf.target).to(x.device)
+    coef = lf.lsefit(x, y, off, dg, 3, precision="f32c")
+    mask = torch.zeros_like(coef)
+    for f in range(bf.batch):
+        mask[f, : int(bf.degrees[f]) + 1] = 1.0
+    (((coef - target) * mask) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    gx, gy = x.grad.cpu().numpy(), y.grad.cpu().numpy()
+    a_all = coef.detach().cpu().numpy()
+    for f in range(bf.batch):
+        lo, hi = bf.offsets[f], bf.offsets[f + 1]
+        m = int(bf.degrees[f])
+        ref = adjoint.gradients(bf.x[lo:hi], bf.y[lo:hi], m, 2.0 * (a_all[f, : m + 1] - bf.target[f, : m + 1]))
+        assert normwise(gx[lo:hi], ref["dx"]) <= 1e-5, f
+        assert normwise(gy[lo:hi], ref["dy"]) <= 1e-5, f
+
+
+def test_backward_and_residuals_after_schedule_change():
+    """The adjoint and the residual pass read the tile size from the forward's
+    tile table, so a default schedule changed between forward and backward
+    (other tile, other grid) gives the same gradients, bit for bit, and the
+    same sums of squared residuals up to their summation order."""
+    announce("schedule change between forward and backward")
+    bf = W.random_batch([5000, 70_001, 3, 12_345, 999], [2, 3, 1, 2, 3], seed=32, with_target=True)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    g = torch.from_numpy(np.nan_to_num(bf.target)).to(x.device)
+    base = lf.default_schedule().as_dict()
+    other = {"waves": 1024, "waves_per_block": 2, "tile": 256, "unroll": 1}
+    assert other["tile"] != base["tile"] and other["waves"] != base["waves"]
+    coef, status, ws = lf.fit_batched(x, y, off, dg, 3)
+    gx0, gy0 = lf.fit_backward(x, y, off, dg, 3, g, ws=ws)
+    sse0, _ = lf.residuals_batched(x, y, off, dg, 3, ws=ws)
+    torch.cuda.synchronize()
+    try:
+        lf.set_default_schedule(other)
+        gx1, gy1 = lf.fit_backward(x, y, off, dg, 3, g, ws=ws)
+        sse1, _ = lf.residuals_batched(x, y, off, dg, 3, ws=ws)
+        torch.cuda.synchronize()
+    finally:
+        lf.set_default_schedule(None)
+    assert torch.equal(gx0, gx1) and torch.equal(gy0, gy1)
+    st = status.cpu().numpy()
+    s0, s1 = sse0.cpu().numpy(), sse1.cpu().numpy()
+    ok = st == 0
+    assert np.isnan(s1[~ok]).all() and np.isfinite(s1[ok]).all()
+    assert np.max(np.abs(s1[ok] - s0[ok]) / s0[ok]) <= 1e-12
+
+
 def test_adjoint_against_finite_differences():
     bf = W.random_batch([300], [2], seed=13, dtype=np.float64, with_target=True)
     x = to_dev(bf.x).requires_grad_(True)

@@ -221,6 +221,29 @@ lsefit_status fit_solve(const double* moments, const lsefit_options* opt,
 lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
                          void* ws, size_t ws_bytes, double* coef, int32_t* status, double* moments, void* stream);
 
+/* fit_single for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and launches as fit_single, with the workspace in a static
+ * device array of LSEFIT_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends.  The call itself allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine; its launches
+ * are never timed by lsefit_timing_*, whose events are created on demand).
+ *  x, y, n, dt, opt, coef, status, moments, stream: as fit_single
+ * The array is shared by every call on one GPU and keeps the last call's
+ * contents; nothing in it needs to start at zero (every call writes what it
+ * reads).  Calls that overlap on one GPU -- on different streams, or from
+ * different host threads -- race on it and give undefined results; serialise
+ * them (one stream per GPU).  A fit_residuals call on this workspace is not
+ * possible (the array is not exposed).
+ * Errors as fit_single, plus WORKSPACE when the workspace of this call
+ * (lsefit_workspace_bytes(1, opt->degree, NULL), which grows with the default
+ * schedule's wave count) exceeds LSEFIT_NOALLOC_SCRATCH_BYTES, and DEVICE when
+ * the array's address cannot be resolved on the current device. */
+#define LSEFIT_NOALLOC_SCRATCH_BYTES (4u << 20)
+lsefit_status fit_single_noalloc(const void* x, const void* y, int64_t n, lsefit_dtype dt,
+                                 const lsefit_options* opt, double* coef, int32_t* status, double* moments,
+                                 void* stream);
+
 /* One fit through an orthogonal factorisation instead of the normal equations
  * (the QR route of Sec. III, which Sec. V's "methods other than Gaussian
  * elimination" points to): every lane of the streaming pass keeps a triangular

@@ -14,6 +14,7 @@ PREC_F64, PREC_F32C = 0, 1
 SOLVER_GEPP, SOLVER_CHOLESKY = 0, 1
 BASIS_MONOMIAL, BASIS_CHEBYSHEV = 0, 1
 LSEFIT_MAX_DEGREE_CHEBYSHEV = 16
+NOALLOC_SCRATCH_BYTES = 4 << 20   # LSEFIT_NOALLOC_SCRATCH_BYTES
 RANGE_GIVEN, RANGE_AUTO = 0, 1
 OUTPUT_X, OUTPUT_X_AND_T = 0, 1
 
@@ -23,7 +24,7 @@ STATUS_NAMES = {OK: "ok", INVALID_ARG: "invalid_arg", SINGULAR: "singular", NONF
 # C-ABI symbols the library must export (one per declaration in include/lsefit.h)
 EXPORTS = (
     "lsefit_workspace_bytes", "lsefit_default_schedule", "lsefit_set_default_schedule",
-    "fit_moments", "fit_solve", "fit_single", "fit_qr", "fit_qr_batched", "fit_batched", "fit_backward",
+    "fit_moments", "fit_solve", "fit_single", "fit_single_noalloc", "fit_qr", "fit_qr_batched", "fit_batched", "fit_backward",
     "fit_residuals",
     "fit_plan_create", "fit_plan_tune", "fit_plan_set_tune_cache", "fit_plan_set_schedule", "fit_plan_get_schedule",
     "fit_plan_set_graph", "fit_plan_destroy", "lsefit_status_string", "lsefit_device_cus",
@@ -74,6 +75,7 @@ def load():
     L.fit_moments.argtypes = [vp, vp, i64, i32, OptP, vp, sz, vp, vp]
     L.fit_solve.argtypes = [vp, OptP, vp, vp, i64, i32, vp, sz, vp, vp, vp]
     L.fit_single.argtypes = [vp, vp, i64, i32, OptP, vp, sz, vp, vp, vp, vp]
+    L.fit_single_noalloc.argtypes = [vp, vp, i64, i32, OptP, vp, vp, vp, vp]
     L.fit_qr.argtypes = [vp, vp, i64, i32, OptP, vp, sz, vp, vp, vp, vp]
     L.fit_qr_batched.argtypes = [vp, vp, vp, vp, i64, i32, OptP, vp, sz, vp, i32, vp, vp, vp]
     L.fit_batched.argtypes = [vp, vp, vp, vp, i64, i32, OptP, vp, vp, sz, vp, i32, vp, vp]
@@ -95,6 +97,7 @@ def load():
     L.lsefit_copy_probe.argtypes = [vp, vp, vp, vp, i64, SchP, i32, i32, vp]
     L.lsefit_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     for name in ("lsefit_default_schedule", "lsefit_set_default_schedule", "fit_moments", "fit_solve", "fit_single",
+                 "fit_single_noalloc",
                  "fit_qr", "fit_qr_batched", "fit_residuals",
                  "fit_batched", "fit_backward", "fit_plan_create", "fit_plan_tune", "fit_plan_set_tune_cache",
                  "fit_plan_set_schedule",

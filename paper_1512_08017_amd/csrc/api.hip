@@ -201,6 +201,14 @@ struct Timing {
 };
 Timing g_timing;
 
+// while a NoTiming guard lives on a host thread, its launches are never timed
+thread_local bool t_no_timing = false;
+struct NoTiming {
+    bool prev;
+    NoTiming() : prev(t_no_timing) { t_no_timing = true; }
+    ~NoTiming() { t_no_timing = prev; }
+};
+
 bool capturing(hipStream_t st) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
@@ -228,7 +236,7 @@ hipError_t timed(int kind, hipStream_t st, F&& launch) {
         std::lock_guard<std::mutex> lk(g_timing.mu);
         on = g_timing.enabled;
     }
-    if (!on || capturing(st)) return launch();
+    if (!on || t_no_timing || capturing(st)) return launch();
     hipEvent_t a, b;
     {
         std::lock_guard<std::mutex> lk(g_timing.mu);
@@ -526,14 +534,13 @@ lsefit_status fit_solve(const double* moments, const lsefit_options* opt, const 
     return single_pass(true, d, w, opt, dt, x, y, to_launch(sched), common_mis(dt, {x, y}), fz, st);
 }
 
-lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
-                         void* ws, size_t ws_bytes, double* coef, int32_t* status, double* moments, void* stream) {
-    if (!coef || !status) return LSEFIT_ERR_INVALID_ARG;
-    Layout lay;
-    lsefit_schedule sched;
-    const lsefit_status v = check_single(x, y, n, dt, opt, ws, ws_bytes, &lay, &sched);
-    if (v != LSEFIT_OK) return v;
-    hipStream_t st = (hipStream_t)stream;
+namespace {
+
+// the launches of one single fit (fit_single, fit_single_noalloc) on a
+// validated workspace
+lsefit_status enqueue_single(const void* x, const void* y, int64_t n, int dt, const lsefit_options* opt, void* ws,
+                             const Layout& lay, const lsefit_schedule& sched, double* coef, int32_t* status,
+                             double* moments, hipStream_t st) {
     const FitDesc d{nullptr, nullptr, n, 1, opt->degree};
     const Work w = carve(ws, lay);
     const Launch L = to_launch(sched);
@@ -544,6 +551,64 @@ lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype d
     if (r != LSEFIT_OK || !refining(opt)) return r;
     const Finish fz{kRefine, coef, stride, 1, status, nullptr, opt->solver};
     return single_pass(true, d, w, opt, dt, x, y, L, mis, fz, st);
+}
+
+}  // namespace
+
+lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
+                         void* ws, size_t ws_bytes, double* coef, int32_t* status, double* moments, void* stream) {
+    if (!coef || !status) return LSEFIT_ERR_INVALID_ARG;
+    Layout lay;
+    lsefit_schedule sched;
+    const lsefit_status v = check_single(x, y, n, dt, opt, ws, ws_bytes, &lay, &sched);
+    if (v != LSEFIT_OK) return v;
+    return enqueue_single(x, y, n, dt, opt, ws, lay, sched, coef, status, moments, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// fit_single_noalloc: the workspace of fit_single in a static device array.
+// Each GPU the library runs on holds its own copy (a module global is
+// instantiated per device); its address on the current device is taken once,
+// with hipGetSymbolAddress, and kept per device ordinal.  The array's name is
+// a host-side stand-in and is never passed to a kernel or a copy.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[LSEFIT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the scratch array's device address on the current device (taken on the first
+// call there), or nullptr when the device or the symbol cannot be resolved
+void* scratch_on_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+lsefit_status fit_single_noalloc(const void* x, const void* y, int64_t n, lsefit_dtype dt,
+                                 const lsefit_options* opt, double* coef, int32_t* status, double* moments,
+                                 void* stream) {
+    if (!coef || !status || !x || !y || !opts_ok(opt, dt, false)) return LSEFIT_ERR_INVALID_ARG;
+    if (n < (int64_t)opt->degree + 1) return LSEFIT_ERR_INVALID_ARG;
+    if (unsupported(opt, dt)) return LSEFIT_ERR_UNSUPPORTED;
+    const lsefit_schedule sched = current_default();
+    const Layout lay = layout(1, opt->degree, to_launch(sched).waves);
+    if (lay.total > (size_t)LSEFIT_NOALLOC_SCRATCH_BYTES) return LSEFIT_ERR_WORKSPACE;
+    void* ws = scratch_on_current_device();
+    if (!ws) return LSEFIT_ERR_DEVICE;
+    NoTiming quiet;   // the timing events of lsefit_timing_* may be created on demand: not here
+    return enqueue_single(x, y, n, dt, opt, ws, lay, sched, coef, status, moments, (hipStream_t)stream);
 }
 
 lsefit_status fit_qr(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt, void* ws,

@@ -143,6 +143,29 @@ def test_null_pointers_rejected():
     L.fit_plan_destroy(None)
 
 
+def test_fit_single_noalloc_host_validation():
+    """The entry point without a workspace argument validates like fit_single
+    and refuses a call whose workspace would not fit its static array (here: a
+    default schedule of 65,536 waves) before touching any device."""
+    L = _lib.load()
+    o = _opt()
+    assert L.fit_single_noalloc(None, FAKE, 100, _lib.F32, ctypes.byref(o), FAKE, FAKE, None, None) == _lib.INVALID_ARG
+    assert L.fit_single_noalloc(FAKE, FAKE, 100, _lib.F32, ctypes.byref(o), None, FAKE, None, None) == _lib.INVALID_ARG
+    assert L.fit_single_noalloc(FAKE, FAKE, 3, _lib.F32, ctypes.byref(o), FAKE, FAKE, None, None) == _lib.INVALID_ARG
+    assert L.fit_single_noalloc(FAKE, FAKE, 100, _lib.F64, ctypes.byref(_opt(precision=1)), FAKE, FAKE, None,
+                                None) == _lib.UNSUPPORTED
+    big = _lib.Schedule(1 << 16, 4, 2048, 2)
+    assert L.lsefit_workspace_bytes(1, 3, ctypes.byref(big)) > _lib.NOALLOC_SCRATCH_BYTES
+    assert L.lsefit_workspace_bytes(1, 8, None) <= _lib.NOALLOC_SCRATCH_BYTES      # the default schedule fits
+    assert L.lsefit_workspace_bytes(1, 16, None) <= _lib.NOALLOC_SCRATCH_BYTES
+    assert L.lsefit_set_default_schedule(ctypes.byref(big)) == _lib.OK
+    try:
+        assert L.fit_single_noalloc(FAKE, FAKE, 100, _lib.F32, ctypes.byref(o), FAKE, FAKE, None,
+                                    None) == _lib.WORKSPACE
+    finally:
+        assert L.lsefit_set_default_schedule(None) == _lib.OK
+
+
 @pytest.mark.gpu
 def test_plan_tune_validates_against_the_plan():
     """A degree above the plan's, a short stride or a null pointer never reaches

@@ -374,7 +374,9 @@ const char* lsefit_status_string(lsefit_status s);
  * 16-byte aligned) with the schedule's grid and 16-byte loads and writes one
  * float per block into out[out_count >= number of blocks].  pattern 0: each
  * wave reads one contiguous share (the layout of the power-sum pass);
- * pattern 1: the grid strides over 16-byte vectors.  nontemporal: 1 uses
+ * pattern 1: the grid strides over 16-byte vectors; pattern 2: each block
+ * reads one contiguous share and its waves take turns over its 16-byte
+ * vectors (the waves of a block together walk one stream).  nontemporal: 1 uses
  * non-temporal loads.  Timed as kind 4 by lsefit_timing_read.  Serves to
  * measure the read bandwidth the device attains with each load pattern. */
 lsefit_status lsefit_read_probe(const float* x, const float* y, int64_t n, const lsefit_schedule* schedule,
@@ -391,13 +393,20 @@ lsefit_status lsefit_copy_probe(const float* x, const float* y, float* ox, float
                                 void* stream);
 
 /* Kernel timing for profiling.  While enabled, the main kernel of every
- * streaming launch made by the calls above (outside graph capture) is
- * dispatched with a pair of HIP events (hipExtLaunchKernelGGL) that take the
- * start and end timestamps of that kernel's own dispatch, so the durations
- * are those of the kernel itself, without event packets between kernels.
- * lsefit_timing_read waits for the events of one kernel kind and returns the
- * summed duration in milliseconds and the number of launches since the last
- * reset.
+ * streaming launch made by the calls above (outside graph capture; never by
+ * fit_single_noalloc) carries a clock slot: the first thread of block 0 (the
+ * first block to start) stores the device's constant-rate wall clock
+ * (hipDeviceAttributeWallClockRate) when it starts, and every wave folds the
+ * clock into one of 32 separate lines of the slot with an atomic maximum when
+ * it leaves; a launch's duration is the span from that start to the latest
+ * end, taken by the kernel itself.  No event or marker is enqueued, so timed
+ * launches run back to back like untimed ones; the cost is one atomic per
+ * wave, spread over 32 memory lines.  The first enable allocates a device
+ * pool of 16,384 slots (2 KiB each, kept until the process ends); launches
+ * past the pool are not timed.  lsefit_timing_reset waits for the device and
+ * clears the totals and the pool; lsefit_timing_read waits for the device and
+ * returns the summed duration of one kernel kind in milliseconds and the
+ * number of timed launches since the last reset.
  *  kind: 0 = power-sum pass (k_moments, or the Chebyshev / QR streaming pass),
  *        1 = refinement pass, 2 = adjoint streaming pass (not its per-fit
  *        solve), 3 = per-fit combine and solve (the finish kernel of a single

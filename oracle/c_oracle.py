@@ -11,6 +11,7 @@ from . import build as _build
 _lib = None
 _dbl_p = ctypes.POINTER(ctypes.c_double)
 STATUS = {0: "ok", 1: "invalid", 2: "singular", 3: "nonfinite"}
+BUILD_NOTE = _build.BUILD_NOTE
 
 
 def lib():

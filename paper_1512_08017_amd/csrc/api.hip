@@ -68,6 +68,7 @@ Work carve(void* ws, const Layout& L) {
     w.rec = (double*)(base + L.rec);
     w.part = (double*)(base + L.part);
     w.block_tot = (int64_t*)(base + L.block_tot);
+    w.clock = nullptr;   // armed per launch by launch_timed only
     return w;
 }
 
@@ -191,11 +192,19 @@ enum TimedKind {
     kTimeKinds = 7
 };
 
+// the launches of each kind get one clock slot each (kClockWords uint64
+// words: the start, and the last end of each group of waves) from a device
+// pool taken when timing is first enabled; reading copies the used slots back
+// and turns their spans into milliseconds at the device's wall-clock rate
+constexpr int kClockSlots = 1 << 14;
+
 struct Timing {
     std::mutex mu;
     bool enabled = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kTimeKinds];
-    std::vector<hipEvent_t> pool;
+    uint64_t* slots = nullptr;   // device [kClockWords * kClockSlots]
+    double khz = 0.0;            // wall-clock rate
+    int used = 0;                // slots handed out since the last reset
+    std::vector<std::pair<int, int>> pending;   // (kind, slot) not read yet
     double total_ms[kTimeKinds] = {};
     int64_t launches[kTimeKinds] = {};
 };
@@ -215,48 +224,40 @@ bool capturing(hipStream_t st) {
     return cs != hipStreamCaptureStatusNone;
 }
 
-hipEvent_t take_event() {
-    if (!g_timing.pool.empty()) {
-        hipEvent_t e = g_timing.pool.back();
-        g_timing.pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    // no system-scope release at the timed kernel's end: the events only carry timestamps
-    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
-    return e;
+// slots [lo, hi) back to (start = max, ends = 0), so that an unwritten start
+// is seen and the kernels' atomic maxima take their first values; the device
+// is idle when called
+hipError_t clear_slots(int lo, int hi) {
+    if (hi <= lo) return hipSuccess;
+    std::vector<uint64_t> init(kClockWords * (size_t)(hi - lo), 0);
+    for (size_t i = 0; i < init.size(); i += kClockWords) init[i] = ~(uint64_t)0;
+    return hipMemcpy(g_timing.slots + kClockWords * (size_t)lo, init.data(), init.size() * sizeof(uint64_t),
+                     hipMemcpyHostToDevice);
 }
 
 // runs `launch` on `st`; when timing is on, its first kernel started through
-// launch_timed records its own start and end into a fresh event pair
+// launch_timed stamps its start and end into a fresh clock slot
 template <class F>
 hipError_t timed(int kind, hipStream_t st, F&& launch) {
-    bool on;
+    int idx = -1;
     {
         std::lock_guard<std::mutex> lk(g_timing.mu);
-        on = g_timing.enabled;
+        if (g_timing.enabled && g_timing.slots && !t_no_timing && g_timing.used < kClockSlots) idx = g_timing.used;
     }
-    if (!on || t_no_timing || capturing(st)) return launch();
-    hipEvent_t a, b;
+    if (idx < 0 || capturing(st)) return launch();
     {
         std::lock_guard<std::mutex> lk(g_timing.mu);
-        a = take_event();
-        b = take_event();
+        idx = g_timing.used++;
     }
-    if (!a || !b) return launch();
     TimingSlot& slot = timing_slot();
-    slot.start = a;
-    slot.stop = b;
+    slot.slot = g_timing.slots + kClockWords * (size_t)idx;
     slot.used = false;
     const hipError_t e = launch();
     const bool used = slot.used;
     slot = TimingSlot{};
-    std::lock_guard<std::mutex> lk(g_timing.mu);
     if (e == hipSuccess && used) {
-        g_timing.pending[kind].push_back({a, b});
-    } else {
-        g_timing.pool.push_back(a);
-        g_timing.pool.push_back(b);
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        g_timing.pending.push_back({kind, idx});
     }
     return e;
 }
@@ -936,7 +937,7 @@ lsefit_status fit_plan_set_tune_cache(lsefit_plan* plan, const char* path) {
 
 lsefit_status lsefit_read_probe(const float* x, const float* y, int64_t n, const lsefit_schedule* schedule,
                                 int32_t pattern, int32_t nontemporal, float* out, size_t out_count, void* stream) {
-    if (!x || !y || !out || n < 4 || (pattern != 0 && pattern != 1)) return LSEFIT_ERR_INVALID_ARG;
+    if (!x || !y || !out || n < 4 || pattern < 0 || pattern > 2) return LSEFIT_ERR_INVALID_ARG;
     if (((uintptr_t)x | (uintptr_t)y) % 16) return LSEFIT_ERR_INVALID_ARG;
     const lsefit_schedule s = schedule ? *schedule : current_default();
     if (!schedule_ok(s)) return LSEFIT_ERR_INVALID_ARG;
@@ -950,7 +951,7 @@ lsefit_status lsefit_read_probe(const float* x, const float* y, int64_t n, const
 
 lsefit_status lsefit_copy_probe(const float* x, const float* y, float* ox, float* oy, int64_t n,
                                const lsefit_schedule* schedule, int32_t pattern, int32_t nontemporal, void* stream) {
-    if (!x || !y || !ox || !oy || n < 4 || (pattern != 0 && pattern != 1)) return LSEFIT_ERR_INVALID_ARG;
+    if (!x || !y || !ox || !oy || n < 4 || pattern < 0 || pattern > 2) return LSEFIT_ERR_INVALID_ARG;
     if (((uintptr_t)x | (uintptr_t)y | (uintptr_t)ox | (uintptr_t)oy) % 16) return LSEFIT_ERR_INVALID_ARG;
     const lsefit_schedule s = schedule ? *schedule : current_default();
     if (!schedule_ok(s)) return LSEFIT_ERR_INVALID_ARG;
@@ -963,38 +964,66 @@ lsefit_status lsefit_copy_probe(const float* x, const float* y, float* ox, float
 
 lsefit_status lsefit_timing_enable(int32_t enable) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (enable && !g_timing.slots) {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return LSEFIT_ERR_DEVICE;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            return LSEFIT_ERR_DEVICE;
+        void* p = nullptr;
+        if (hipMalloc(&p, kClockWords * sizeof(uint64_t) * (size_t)kClockSlots) != hipSuccess)
+            return LSEFIT_ERR_DEVICE;
+        g_timing.slots = (uint64_t*)p;
+        g_timing.khz = (double)khz;
+        g_timing.used = 0;
+        if (hipDeviceSynchronize() != hipSuccess || clear_slots(0, kClockSlots) != hipSuccess) return LSEFIT_ERR_DEVICE;
+    }
     g_timing.enabled = enable != 0;
     return LSEFIT_OK;
 }
 
+namespace {
+
+// spans of the pending slots into the per-kind totals (waits for the device)
+lsefit_status collect_pending() {
+    if (g_timing.pending.empty()) return LSEFIT_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return LSEFIT_ERR_DEVICE;
+    std::vector<uint64_t> host(kClockWords * (size_t)g_timing.used);
+    if (hipMemcpy(host.data(), g_timing.slots, host.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return LSEFIT_ERR_DEVICE;
+    for (const auto& p : g_timing.pending) {
+        const uint64_t* sl = host.data() + kClockWords * (size_t)p.second;
+        uint64_t end = 0;
+        for (int j = 0; j < kClockLines; ++j) end = sl[8 * j + 1] > end ? sl[8 * j + 1] : end;
+        if (sl[0] == ~(uint64_t)0 || end < sl[0]) continue;   // the kernel never ran
+        g_timing.total_ms[p.first] += (double)(end - sl[0]) / g_timing.khz;
+        g_timing.launches[p.first] += 1;
+    }
+    g_timing.pending.clear();
+    return LSEFIT_OK;
+}
+
+}  // namespace
+
 lsefit_status lsefit_timing_reset(void) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.pending.clear();
     for (int k = 0; k < kTimeKinds; ++k) {
-        for (auto& p : g_timing.pending[k]) {
-            hipEventSynchronize(p.second);
-            g_timing.pool.push_back(p.first);
-            g_timing.pool.push_back(p.second);
-        }
-        g_timing.pending[k].clear();
         g_timing.total_ms[k] = 0.0;
         g_timing.launches[k] = 0;
     }
+    if (g_timing.slots && g_timing.used > 0) {
+        if (hipDeviceSynchronize() != hipSuccess || clear_slots(0, g_timing.used) != hipSuccess)
+            return LSEFIT_ERR_DEVICE;
+    }
+    g_timing.used = 0;
     return LSEFIT_OK;
 }
 
 lsefit_status lsefit_timing_read(int32_t kind, double* total_ms, int64_t* launches) {
     if (kind < 0 || kind >= kTimeKinds || !total_ms || !launches) return LSEFIT_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_timing.mu);
-    for (auto& p : g_timing.pending[kind]) {
-        if (hipEventSynchronize(p.second) != hipSuccess) return LSEFIT_ERR_DEVICE;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess) return LSEFIT_ERR_DEVICE;
-        g_timing.total_ms[kind] += ms;
-        g_timing.launches[kind] += 1;
-        g_timing.pool.push_back(p.first);
-        g_timing.pool.push_back(p.second);
-    }
-    g_timing.pending[kind].clear();
+    const lsefit_status st = collect_pending();
+    if (st != LSEFIT_OK) return st;
     *total_ms = g_timing.total_ms[kind];
     *launches = g_timing.launches[kind];
     return LSEFIT_OK;

@@ -163,6 +163,7 @@ __device__ inline void minmax_segment(const In* __restrict__ x, int64_t lo, int6
 template <typename In>
 __global__ void __launch_bounds__(256)
     k_range_cheb_single(FitDesc d, Work w, const In* __restrict__ x, int64_t W, int mis) {
+    const KernelClock kclock_(w.clock);
     __shared__ double slo[4], shi[4];
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     MinMax<In> r;
@@ -186,6 +187,7 @@ __global__ void __launch_bounds__(256)
 
 // single fit: fold the G block pairs, set (c, s) and the fit's status
 __global__ void __launch_bounds__(256) k_range_fold_single(Work w, int64_t G) {
+    const KernelClock kclock_(w.clock);
     __shared__ double slo[4], shi[4];
     double lo = INFINITY, hi = -INFINITY;
     for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
@@ -213,6 +215,7 @@ __global__ void __launch_bounds__(256) k_range_fold_single(Work w, int64_t G) {
 template <typename In>
 __global__ void __launch_bounds__(256)
     k_range_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, int64_t W, int mis, int maxm) {
+    const KernelClock kclock_(w.clock);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rec_len(maxm), wave, W,
                         [&](int64_t, int64_t lo, int64_t hi, int64_t slot, const SegMeta& mt) {
@@ -229,6 +232,7 @@ __global__ void __launch_bounds__(256)
 
 // batch: one thread per fit folds the slots of the waves that streamed it
 __global__ void __launch_bounds__(256) k_range_fold_batch(FitDesc d, Work w, int64_t W, int maxm) {
+    const KernelClock kclock_(w.clock);
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.batch || w.pstatus[f] != LSEFIT_OK) return;
     const int64_t NT = w.tile_start[d.batch];
@@ -348,6 +352,7 @@ template <typename In, int U, int M>
 __global__ void __launch_bounds__(256)
     k_moments_cheb_single(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t W, int mis,
                           RangeArg ra) {
+    const KernelClock kclock_(w.clock);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     double c, inv_s;
     if (ra.mode == kRangeFromRecord) {
@@ -370,6 +375,7 @@ template <typename In, int U, int MAXC>
 __global__ void __launch_bounds__(256)
     k_moments_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y,
                          int64_t W, int mis, int maxm) {
+    const KernelClock kclock_(w.clock);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     const int stride = nacc(maxm);
     const int rl = rec_len(maxm);
@@ -523,6 +529,7 @@ __device__ __forceinline__ void cheb_store_sums(const Work& w, int64_t f, int ma
 template <int M>
 __global__ void __launch_bounds__(kFinishMaxThreads)
     k_finish_cheb_single(FitDesc d, Work w, int64_t W, int maxm, Finish fz) {
+    const KernelClock kclock_(w.clock);
     constexpr int K = nacc(M);
     __shared__ double sh[kFinishMaxThreads / kWave][K];
     __shared__ double S[3 * M + 2];
@@ -557,6 +564,7 @@ __global__ void __launch_bounds__(kFinishMaxThreads)
 // streamed each.
 template <int MAXC>
 __global__ void __launch_bounds__(256) k_finish_cheb_batch(FitDesc d, Work w, int64_t W, int maxm, Finish fz) {
+    const KernelClock kclock_(w.clock);
     __shared__ double S[4][3 * MAXC + 2];
     const int wid = wave_id_in_block(), lane = lane_id();
     const int stride = nacc(maxm);
@@ -601,6 +609,7 @@ __global__ void __launch_bounds__(256) k_finish_cheb_batch(FitDesc d, Work w, in
 // them.
 template <int MAXC>
 __global__ void __launch_bounds__(256) k_finish_cheb_lane(FitDesc d, Work w, int64_t W, int maxm, Finish fz) {
+    const KernelClock kclock_(w.clock);
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.batch) return;
     const int pst = w.pstatus[f];
@@ -698,6 +707,7 @@ template <typename In, int U, int M>
 __global__ void __launch_bounds__(256)
     k_residual_cheb_single(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y,
                            In* __restrict__ resid, int64_t W, int mis, int maxm) {
+    const KernelClock kclock_(w.clock);
     __shared__ double sh[4];
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     double acc = 0.0;
@@ -722,6 +732,7 @@ template <typename In, int U, int MAXC>
 __global__ void __launch_bounds__(256)
     k_residual_cheb_batch(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y,
                           In* __restrict__ resid, int64_t W, int mis, int maxm) {
+    const KernelClock kclock_(w.clock);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     const int rl = rec_len(maxm);
     walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, wave, W,
@@ -745,6 +756,7 @@ __global__ void __launch_bounds__(256)
 
 // sse of a single fit: one block sums the G block partials in a fixed order
 __global__ void __launch_bounds__(256) k_sse_fold_single(Work w, int64_t G, double* __restrict__ sse) {
+    const KernelClock kclock_(w.clock);
     __shared__ double sh[4];
     double t = 0.0;
     for (int64_t g = threadIdx.x; g < G; g += blockDim.x) t += w.part[g];
@@ -760,6 +772,7 @@ __global__ void __launch_bounds__(256) k_sse_fold_single(Work w, int64_t G, doub
 
 // sse of each fit of a batch: one thread per fit sums its slots in wave order
 __global__ void __launch_bounds__(256) k_sse_fold_batch(FitDesc d, Work w, int64_t W, double* __restrict__ sse) {
+    const KernelClock kclock_(w.clock);
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.batch) return;
     if (w.pstatus[f] != LSEFIT_OK) {
@@ -778,6 +791,7 @@ __global__ void __launch_bounds__(256) k_sse_fold_batch(FitDesc d, Work w, int64
 // one fit of degree M from caller-provided sums [c, s, C_0..C_2m, D_0..D_m], one wave
 template <int M>
 __global__ void __launch_bounds__(64) k_solve_cheb_moments(const double* __restrict__ mom, Work w, Finish fz) {
+    const KernelClock kclock_(w.clock);
     __shared__ double S[3 * M + 2];
     const int lane = lane_id();
     const double c0 = mom[0], s0 = mom[1];
@@ -874,6 +888,7 @@ template <int MAXC>
 __global__ void __launch_bounds__(256)
     k_adjoint_cheb_solve(FitDesc d, Work w, int maxm, int solver, const double* __restrict__ gcoef,
                          int32_t coef_stride) {
+    const KernelClock kclock_(w.clock);
     const int wid = wave_id_in_block(), lane = lane_id();
     for (int64_t f = (int64_t)blockIdx.x * 4 + wid; f < d.batch; f += (int64_t)gridDim.x * 4) {
         if (w.pstatus[f] != LSEFIT_OK) continue;
@@ -951,18 +966,24 @@ template <typename In, int U, int MAXC>
 __global__ void __launch_bounds__(256)
     k_adjoint_cheb_stream(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y,
                           In* __restrict__ gx, In* __restrict__ gy, int64_t W, int mis, int maxm) {
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
+    const KernelClock kclock_(w.clock);
+    (void)W;
     const int rl = rec_len(maxm);
-    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, wave, W,
+    // tiles go to blocks and the waves of a block stream each segment together
+    // (no per-wave partial sums here), as in the power-basis adjoint pass
+    const int64_t first = (int64_t)wave_id_in_block() * kWave + lane_id();
+    const int64_t step = (int64_t)(blockDim.x / kWave) * kWave;
+    const bool edge = wave_id_in_block() == 0;
+    walk_segments_ahead(d, w.tile_start, w.pstatus, w.rec, rl, (int64_t)blockIdx.x, (int64_t)gridDim.x,
                         [&](int64_t f, int64_t lo, int64_t hi, int64_t, const SegMeta& mt) {
         if (mt.st != LSEFIT_OK) {
-            adjoint_nan(gx, gy, lo, hi);
+            adjoint_nan(gx, gy, lo, hi, first, step);
             return;
         }
         auto body = [&]<int M>() {
             ChebAdjointPoint<M, In> P;
             P.init(w.rec + f * rl, maxm);
-            adjoint_segment<U>(P, x, y, gx, gy, lo, hi, mis);
+            adjoint_segment<U>(P, x, y, gx, gy, lo, hi, mis, first, step, edge);
         };
         dispatch_degree<MAXC>(mt.deg, body);
     });

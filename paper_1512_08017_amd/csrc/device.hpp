@@ -50,13 +50,15 @@ __device__ inline int fit_deg(const FitDesc& d, int64_t f) { return d.degrees ? 
 
 // Workspace regions (device pointers carved out of the caller's buffer).
 struct Work {
-    int64_t* tile_start;  // [B+2] first tile of each fit; tile_start[B] = number of tiles,
-                          // tile_start[B+1] = points per tile
-    int32_t* pstatus;     // [B] status found while building the tile table
-    double* rec;          // [B * rec_len(M)]
-    double* part;         // [(W + B) * nacc(M)] per-(wave, fit) partial sums (batched) or
-                          // per-block partial sums (single fit; [W * max(nacc, qr_len)])
-    int64_t* block_tot;   // [ceil(B / kPlanThreads)] tile totals of the tile-table blocks
+    int64_t* tile_start = nullptr;  // [B+2] first tile of each fit; tile_start[B] = number of tiles,
+                                    // tile_start[B+1] = points per tile
+    int32_t* pstatus = nullptr;     // [B] status found while building the tile table
+    double* rec = nullptr;          // [B * rec_len(M)]
+    double* part = nullptr;         // [(W + B) * nacc(M)] per-(wave, fit) partial sums (batched) or
+                                    // per-block partial sums (single fit; [W * max(nacc, qr_len)])
+    int64_t* block_tot = nullptr;   // [ceil(B / kPlanThreads)] tile totals of the tile-table blocks
+    uint64_t* clock = nullptr;      // [2] start and end of this launch (KernelClock); null unless
+                                    // launch_timed arms the launch
 };
 
 // threads per block of the tile-table kernels (one thread per fit); the
@@ -117,6 +119,41 @@ __device__ inline double wave_max(double v) { return wave_extreme<true>(v); }
 
 __device__ inline int wave_id_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// ---------------------------------------------------------------------------
+// kernel clock (lsefit_timing_*): when a launch carries a clock slot, the first
+// thread of block 0 (the first block the dispatcher starts) stores the
+// device's constant-rate wall clock into slot[0] when it starts, and the first
+// active lane of every wave folds the clock into one of kClockLines separate
+// 64-byte lines with an atomic maximum when it leaves the kernel (wave w uses
+// line w mod kClockLines, word 1, so that no line takes more than
+// 1/kClockLines of the atomics); the launch's duration is then the largest
+// end over the lines minus the start.  Without a slot (the normal case) it
+// costs one uniform branch at each end.
+// ---------------------------------------------------------------------------
+constexpr int kClockLines = 32;
+constexpr int kClockWords = 8 * kClockLines;   // uint64 words per slot
+
+struct KernelClock {
+    uint64_t* slot;
+    __device__ explicit KernelClock(uint64_t* s) : slot(s) {
+        if (slot && blockIdx.x == 0 && threadIdx.x == 0) slot[0] = wall_clock64();
+    }
+    __device__ ~KernelClock() {
+        if (slot) {
+            const uint64_t active = __ballot(1);
+            if (lane_id() == __ffsll((unsigned long long)active) - 1) {
+                const unsigned w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+                atomicMax((unsigned long long*)(slot + 8 * (w % kClockLines) + 1),
+                          (unsigned long long)wall_clock64());
+            }
+        }
+    }
+};
+// the clock slot of kernels that take no workspace (the bandwidth probes)
+struct KClock {
+    uint64_t* slot;
+};
 
 // ---------------------------------------------------------------------------
 // range map: (c, s) from the sampled extremes of x.  s is the power of two at

@@ -23,6 +23,7 @@ template <typename In>
 __global__ void __launch_bounds__(kPlanThreads)
     k_plan_count(FitDesc d, Work w, int maxM, int64_t tile, int range_given, double c, double s,
                  const In* __restrict__ x, int64_t* __restrict__ block_tot) {
+    const KernelClock kclock_(w.clock);
     __shared__ int64_t sh[kPlanThreads];
     const int tid = threadIdx.x;
     const int64_t f = (int64_t)blockIdx.x * kPlanThreads + tid;
@@ -80,6 +81,7 @@ __global__ void __launch_bounds__(kPlanThreads)
 
 __global__ void __launch_bounds__(kPlanThreads)
     k_plan_offsets(FitDesc d, Work w, const int64_t* __restrict__ block_tot, int64_t nblocks, int64_t tile) {
+    const KernelClock kclock_(w.clock);
     __shared__ int64_t sh[kPlanThreads];
     const int tid = threadIdx.x;
     int64_t part = 0;
@@ -112,10 +114,33 @@ __device__ inline V probe_load(const V* p) {
     else return *p;
 }
 
+// first vector, end and stride of one lane under each load pattern (pattern 2:
+// each block reads one contiguous share and its waves take turns over the
+// 16-byte vectors of that share)
+template <int PATTERN>
+__device__ inline void probe_range(int64_t nvec, int64_t W, int64_t wave, int lane, int64_t* j, int64_t* end,
+                                   int64_t* step) {
+    if (PATTERN == 0) {
+        *j = wave * nvec / W + lane;
+        *end = (wave + 1) * nvec / W;
+        *step = kWave;
+    } else if (PATTERN == 1) {
+        *j = wave * kWave + lane;
+        *end = nvec;
+        *step = W * kWave;
+    } else {
+        const int64_t nb = gridDim.x, wpb = blockDim.x / kWave;
+        *j = (int64_t)blockIdx.x * nvec / nb + (int64_t)wave_id_in_block() * kWave + lane;
+        *end = ((int64_t)blockIdx.x + 1) * nvec / nb;
+        *step = wpb * kWave;
+    }
+}
+
 template <int U, int PATTERN, bool NT>
 __global__ void __launch_bounds__(256)
     k_read_probe(const float* __restrict__ x, const float* __restrict__ y, int64_t nvec, int64_t W,
-                 float* __restrict__ out) {
+                 float* __restrict__ out, KClock kc) {
+    const KernelClock kclock_(kc.slot);
     typedef float V __attribute__((ext_vector_type(4)));
     const V* xv = reinterpret_cast<const V*>(x);
     const V* yv = reinterpret_cast<const V*>(y);
@@ -123,15 +148,7 @@ __global__ void __launch_bounds__(256)
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     float acc = 0.0f;
     int64_t j, end, step;
-    if (PATTERN == 0) {
-        j = wave * nvec / W + lane;
-        end = (wave + 1) * nvec / W;
-        step = kWave;
-    } else {
-        j = wave * kWave + lane;
-        end = nvec;
-        step = W * kWave;
-    }
+    probe_range<PATTERN>(nvec, W, wave, lane, &j, &end, &step);
     for (; j + (int64_t)(U - 1) * step < end; j += (int64_t)U * step) {
         V a[U], b[U];
 #pragma unroll
@@ -155,13 +172,15 @@ hipError_t launch_read_probe(const float* x, const float* y, int64_t nvec, const
     const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
 #define LSEFIT_PROBE(UU, PP, NN)                                                                                  \
     if (L.unroll == UU && pattern == PP && nt == NN) {                                                            \
-        launch_timed((k_read_probe<UU, PP, NN>), grid, block, st, x, y, nvec, L.waves, out);             \
+        launch_timed((k_read_probe<UU, PP, NN>), grid, block, st, x, y, nvec, L.waves, out, KClock{}); \
         return hipGetLastError();                                                                                 \
     }
     LSEFIT_PROBE(1, 0, false) LSEFIT_PROBE(2, 0, false) LSEFIT_PROBE(4, 0, false)
     LSEFIT_PROBE(1, 0, true) LSEFIT_PROBE(2, 0, true) LSEFIT_PROBE(4, 0, true)
     LSEFIT_PROBE(1, 1, false) LSEFIT_PROBE(2, 1, false) LSEFIT_PROBE(4, 1, false)
     LSEFIT_PROBE(1, 1, true) LSEFIT_PROBE(2, 1, true) LSEFIT_PROBE(4, 1, true)
+    LSEFIT_PROBE(1, 2, false) LSEFIT_PROBE(2, 2, false) LSEFIT_PROBE(4, 2, false)
+    LSEFIT_PROBE(1, 2, true) LSEFIT_PROBE(2, 2, true) LSEFIT_PROBE(4, 2, true)
 #undef LSEFIT_PROBE
     return hipErrorInvalidValue;
 }
@@ -172,7 +191,8 @@ hipError_t launch_read_probe(const float* x, const float* y, int64_t nvec, const
 template <int U, int PATTERN, bool NT>
 __global__ void __launch_bounds__(256)
     k_copy_probe(const float* __restrict__ x, const float* __restrict__ y, float* __restrict__ ox,
-                 float* __restrict__ oy, int64_t nvec, int64_t W) {
+                 float* __restrict__ oy, int64_t nvec, int64_t W, KClock kc) {
+    const KernelClock kclock_(kc.slot);
     typedef float V __attribute__((ext_vector_type(4)));
     const V* xv = reinterpret_cast<const V*>(x);
     const V* yv = reinterpret_cast<const V*>(y);
@@ -181,15 +201,7 @@ __global__ void __launch_bounds__(256)
     const int lane = lane_id();
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     int64_t j, end, step;
-    if (PATTERN == 0) {
-        j = wave * nvec / W + lane;
-        end = (wave + 1) * nvec / W;
-        step = kWave;
-    } else {
-        j = wave * kWave + lane;
-        end = nvec;
-        step = W * kWave;
-    }
+    probe_range<PATTERN>(nvec, W, wave, lane, &j, &end, &step);
     auto store = [](V* p, const V& v) {
         if constexpr (NT) __builtin_nontemporal_store(v, p);
         else *p = v;
@@ -218,13 +230,15 @@ hipError_t launch_copy_probe(const float* x, const float* y, float* ox, float* o
     const dim3 grid(L.waves / L.wpb), block(L.wpb * kWave);
 #define LSEFIT_PROBE(UU, PP, NN)                                                                 \
     if (L.unroll == UU && pattern == PP && nt == NN) {                                           \
-        launch_timed((k_copy_probe<UU, PP, NN>), grid, block, st, x, y, ox, oy, nvec, L.waves);  \
+        launch_timed((k_copy_probe<UU, PP, NN>), grid, block, st, x, y, ox, oy, nvec, L.waves, KClock{}); \
         return hipGetLastError();                                                                \
     }
     LSEFIT_PROBE(1, 0, false) LSEFIT_PROBE(2, 0, false) LSEFIT_PROBE(4, 0, false)
     LSEFIT_PROBE(1, 0, true) LSEFIT_PROBE(2, 0, true) LSEFIT_PROBE(4, 0, true)
     LSEFIT_PROBE(1, 1, false) LSEFIT_PROBE(2, 1, false) LSEFIT_PROBE(4, 1, false)
     LSEFIT_PROBE(1, 1, true) LSEFIT_PROBE(2, 1, true) LSEFIT_PROBE(4, 1, true)
+    LSEFIT_PROBE(1, 2, false) LSEFIT_PROBE(2, 2, false) LSEFIT_PROBE(4, 2, false)
+    LSEFIT_PROBE(1, 2, true) LSEFIT_PROBE(2, 2, true) LSEFIT_PROBE(4, 2, true)
 #undef LSEFIT_PROBE
     return hipErrorInvalidValue;
 }

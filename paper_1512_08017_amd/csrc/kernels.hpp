@@ -2,7 +2,6 @@
 // dispatch.hip; Chebyshev basis: cheb.hip; streaming QR: tsqr.hip).
 #pragma once
 
-#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -10,24 +9,36 @@
 
 namespace lsefit {
 
-// Kernel timing (lsefit_timing_*).  The host side arms a pair of events on its
+// Kernel timing (lsefit_timing_*).  The host side arms a clock slot on its
 // thread before it calls a launcher; the first kernel that launcher starts
-// through launch_timed goes out through hipExtLaunchKernelGGL with that pair,
-// so that the events take the start and end timestamps of that kernel's own
-// dispatch (no separate event packets on the stream).  With nothing armed,
-// launch_timed is a plain launch.
+// through launch_timed gets the slot in its workspace argument (Work::clock,
+// or KClock for the probes), and the kernel itself stamps its start and end
+// there (KernelClock).  Nothing else is enqueued, so timed launches run back
+// to back as untimed ones do.  With nothing armed, launch_timed is a plain
+// launch.
 struct TimingSlot {
-    hipEvent_t start = nullptr, stop = nullptr;
+    uint64_t* slot = nullptr;
     bool used = false;
 };
 TimingSlot& timing_slot();   // this host thread's slot (api.hip)
 
+template <typename T>
+inline T with_clock(const T& v, uint64_t*) {
+    return v;
+}
+inline Work with_clock(const Work& w, uint64_t* slot) {
+    Work c = w;
+    c.clock = slot;
+    return c;
+}
+inline KClock with_clock(const KClock&, uint64_t* slot) { return KClock{slot}; }
+
 template <typename K, typename... Args>
 inline void launch_timed(K kernel, const dim3& grid, const dim3& block, hipStream_t st, Args... args) {
     TimingSlot& t = timing_slot();
-    if (t.start && !t.used) {
+    if (t.slot && !t.used) {
         t.used = true;
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, t.start, t.stop, 0, args...);
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, with_clock(args, t.slot)...);
     } else {
         hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
     }

@@ -624,6 +624,7 @@ __host__ __device__ inline int finish_threads(int64_t G) {
 
 template <int MAXM>
 __global__ void __launch_bounds__(kFinishMaxThreads) k_finish_single(FitDesc d, Work w, int64_t G, Finish fz) {
+    const KernelClock kclock_(w.clock);
     finish_single_block<MAXM>(d, w, G, fz);
 }
 
@@ -708,6 +709,7 @@ template <int MAXM, int PREC, typename In, int U>
 __global__ void __launch_bounds__(256)
     k_moments(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t W,
               int mis, RangeArg ra) {
+    const KernelClock kclock_(w.clock);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     constexpr int stride = nacc(MAXM);
     constexpr int rl = rec_len(MAXM);
@@ -755,6 +757,7 @@ template <int MAXM, typename In, int U>
 __global__ void __launch_bounds__(256)
     k_refine(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t W,
              int mis) {
+    const KernelClock kclock_(w.clock);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     constexpr int stride = nacc(MAXM);
     constexpr int rl = rec_len(MAXM);
@@ -804,6 +807,7 @@ __global__ void __launch_bounds__(256)
 
 template <int MAXM>
 __global__ void __launch_bounds__(256) k_combine_lane(FitDesc d, Work w, int64_t W, Finish fz) {
+    const KernelClock kclock_(w.clock);
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.batch) return;
     const int pst = w.pstatus[f];
@@ -837,11 +841,13 @@ constexpr int kCombineThreads = 256;
 
 template <int MAXM>
 __global__ void __launch_bounds__(kCombineThreads) k_combine_block(FitDesc d, Work w, int64_t W, Finish fz) {
+    const KernelClock kclock_(w.clock);
     for (int64_t f = blockIdx.x; f < d.batch; f += gridDim.x) block_combine_fit<MAXM>(d, w, f, W, fz);
 }
 
 template <int M, int MAXM>
 __global__ void k_solve_moments(const double* __restrict__ mom, Work w, int solver, double* coef, int32_t* status) {
+    const KernelClock kclock_(w.clock);
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     constexpr int N = M + 1;
     constexpr int rl = rec_len(MAXM);
@@ -886,6 +892,7 @@ __global__ void k_solve_moments(const double* __restrict__ mom, Work w, int solv
 template <int MAXM>
 __global__ void __launch_bounds__(256)
     k_adjoint_solve(FitDesc d, Work w, int solver, const double* __restrict__ gcoef, int32_t coef_stride) {
+    const KernelClock kclock_(w.clock);
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.batch) return;
     if (w.pstatus[f] != LSEFIT_OK) return;
@@ -910,13 +917,14 @@ template <int M, typename In>
 struct AdjointPoint {
     double b[M + 1], lam[M + 1];
     double inv_s, nc;
-    __device__ inline void init(const double* r, int MAXM_) {
-        inv_s = 1.0 / r[1];
-        nc = -r[0] * inv_s;
+    template <int MAXM_>
+    __device__ inline void init(double c, double s, const double (&bb)[MAXM_ + 1], const double (&ll)[MAXM_ + 1]) {
+        inv_s = 1.0 / s;
+        nc = -c * inv_s;
 #pragma unroll
         for (int j = 0; j <= M; ++j) {
-            b[j] = r[rec_b(MAXM_) + j];
-            lam[j] = r[rec_lam(MAXM_) + j];
+            b[j] = bb[j];
+            lam[j] = ll[j];
         }
     }
     __device__ inline void point(double xv, double yv, In& gx, In& gy) const {
@@ -935,13 +943,17 @@ struct AdjointPoint {
     }
 };
 
-// one wave: dL/dx and dL/dy of the points [lo, hi) of one fit through the
-// point rule P (P.point(x, y, gx, gy)); U vectors of x and y per lane are
-// loaded before any is used, so that a wave keeps U rounds of loads in flight
-// (the same unroll as the power-sum pass)
+// dL/dx and dL/dy of the points [lo, hi) of one fit through the point rule P
+// (P.point(x, y, gx, gy)), streamed by the waves of one block together: lane
+// `first` (in 16-byte vectors: wave-in-block * 64 + lane) takes every
+// `step`-th vector (waves per block * 64), so that the block walks one
+// contiguous stream; U vectors of x and y per lane are loaded before any is
+// used.  The unaligned head and the ragged tail go to the block's first wave
+// (edge).
 template <int U, typename In, class PT>
 __device__ inline void adjoint_segment(const PT& P, const In* __restrict__ x, const In* __restrict__ y,
-                                       In* __restrict__ gx, In* __restrict__ gy, int64_t lo, int64_t hi, int mis) {
+                                       In* __restrict__ gx, In* __restrict__ gy, int64_t lo, int64_t hi, int mis,
+                                       int64_t first, int64_t step, bool edge) {
     constexpr int VW = VecOf<In>::W;
     using V = typename VecOf<In>::type;
     const int lane = lane_id();
@@ -950,7 +962,7 @@ __device__ inline void adjoint_segment(const PT& P, const In* __restrict__ x, co
         if (a > hi) a = hi;
         const int64_t nv = (hi - a) / VW;
         const int64_t b = a + nv * VW;
-        if (lane < a - lo) P.point((double)x[lo + lane], (double)y[lo + lane], gx[lo + lane], gy[lo + lane]);
+        if (edge && lane < a - lo) P.point((double)x[lo + lane], (double)y[lo + lane], gx[lo + lane], gy[lo + lane]);
         const V* xv = reinterpret_cast<const V*>(x + a);
         const V* yv = reinterpret_cast<const V*>(y + a);
         V* gxv = reinterpret_cast<V*>(gx + a);
@@ -967,52 +979,121 @@ __device__ inline void adjoint_segment(const PT& P, const In* __restrict__ x, co
             __builtin_nontemporal_store(ox, gxv + j);
             __builtin_nontemporal_store(oy, gyv + j);
         };
-        int64_t j = lane;
-        for (; j + (int64_t)(U - 1) * kWave < nv; j += (int64_t)U * kWave) {
+        int64_t j = first;
+        for (; j + (int64_t)(U - 1) * step < nv; j += (int64_t)U * step) {
             V xs[U], ys[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                xs[u] = ld_stream(xv + j + u * kWave);
-                ys[u] = ld_stream(yv + j + u * kWave);
+                xs[u] = ld_stream(xv + j + u * step);
+                ys[u] = ld_stream(yv + j + u * step);
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) vec(xs[u], ys[u], j + u * kWave);
+            for (int u = 0; u < U; ++u) vec(xs[u], ys[u], j + u * step);
         }
-        for (; j < nv; j += kWave) vec(ld_stream(xv + j), ld_stream(yv + j), j);
-        if (lane < hi - b) P.point((double)x[b + lane], (double)y[b + lane], gx[b + lane], gy[b + lane]);
+        for (; j < nv; j += step) vec(ld_stream(xv + j), ld_stream(yv + j), j);
+        if (edge && lane < hi - b) P.point((double)x[b + lane], (double)y[b + lane], gx[b + lane], gy[b + lane]);
     } else {
-        for (int64_t i = lo + lane; i < hi; i += kWave) P.point((double)x[i], (double)y[i], gx[i], gy[i]);
+        for (int64_t i = lo + first; i < hi; i += step) P.point((double)x[i], (double)y[i], gx[i], gy[i]);
     }
 }
 
-// fits whose status is not OK get NaN gradients
+// fits whose status is not OK get NaN gradients (the block's lanes take turns)
 template <typename In>
-__device__ inline void adjoint_nan(In* __restrict__ gx, In* __restrict__ gy, int64_t lo, int64_t hi) {
-    for (int64_t i = lo + lane_id(); i < hi; i += kWave) {
+__device__ inline void adjoint_nan(In* __restrict__ gx, In* __restrict__ gy, int64_t lo, int64_t hi, int64_t first,
+                                   int64_t step) {
+    for (int64_t i = lo + first; i < hi; i += step) {
         gx[i] = (In)NAN;
         gy[i] = (In)NAN;
     }
 }
 
+// what the adjoint pass needs of one fit: its tiles and points, status and
+// degree, (c, s), the t-basis solution b and the adjoint solution lambda
+template <int MAXM>
+struct AdjMeta {
+    int64_t fs, fe, lo, hi;
+    double c, s;
+    double b[MAXM + 1], lam[MAXM + 1];
+    int st, deg;
+};
+
+template <int MAXM>
+__device__ inline AdjMeta<MAXM> load_adj_meta(const FitDesc& d, const Work& w, int64_t f) {
+    constexpr int rl = rec_len(MAXM);
+    AdjMeta<MAXM> m;
+    m.fs = w.tile_start[f];
+    m.fe = w.tile_start[f + 1];
+    m.lo = fit_lo(d, f);
+    m.hi = fit_hi(d, f);
+    m.st = w.pstatus[f];
+    m.deg = fit_deg(d, f);
+    const double* r = w.rec + f * rl;
+    m.c = r[0];
+    m.s = r[1];
+#pragma unroll
+    for (int j = 0; j <= MAXM; ++j) {   // entries past the fit's degree are read but not used
+        m.b[j] = r[rec_b(MAXM) + j];
+        m.lam[j] = r[rec_lam(MAXM) + j];
+    }
+    return m;
+}
+
+// The adjoint pass has no per-wave partial sums, so its tiles go to blocks, not
+// waves: block k takes tiles floor(k NT / K) .. floor((k+1) NT / K) - 1 of the
+// forward's tile table (K blocks) and streams each fit inside that range as
+// one segment, its waves together (adjoint_segment).  The next fit's record is
+// loaded before the current segment is streamed.
 template <int MAXM, typename In, int U>
 __global__ void __launch_bounds__(256)
     k_adjoint_stream(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ gx,
                      In* __restrict__ gy, int64_t W, int mis) {
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
-    constexpr int rl = rec_len(MAXM);
-    walk_segments(d, w.tile_start, wave, W, [&](int64_t f, int64_t lo, int64_t hi, int64_t) {
-        if (w.pstatus[f] != LSEFIT_OK) {
-            adjoint_nan(gx, gy, lo, hi);
-            return;
+    const KernelClock kclock_(w.clock);
+    (void)W;
+    const int64_t K = gridDim.x;
+    const int64_t NT = w.tile_start[d.batch];
+    const int64_t tile = w.tile_start[d.batch + 1];
+    const int64_t t0 = (int64_t)blockIdx.x * NT / K;
+    const int64_t t1 = ((int64_t)blockIdx.x + 1) * NT / K;
+    if (t0 >= t1) return;
+    const int64_t first = (int64_t)wave_id_in_block() * kWave + lane_id();
+    const int64_t step = (int64_t)(blockDim.x / kWave) * kWave;
+    const bool edge = wave_id_in_block() == 0;
+    int64_t lo = 0, hi = d.batch;   // largest f with tile_start[f] <= t0
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (w.tile_start[mid] <= t0) lo = mid;
+        else hi = mid;
+    }
+    int64_t f = lo;
+    AdjMeta<MAXM> cur = load_adj_meta<MAXM>(d, w, f);
+    int64_t t = t0;
+    while (t < t1) {
+        if (cur.fe <= t) {   // a fit without tiles
+            ++f;
+            cur = load_adj_meta<MAXM>(d, w, f);
+            continue;
         }
-        const double* r = w.rec + f * rl;
-        auto body = [&]<int M>() {
-            AdjointPoint<M, In> P;
-            P.init(r, MAXM);
-            adjoint_segment<U>(P, x, y, gx, gy, lo, hi, mis);
-        };
-        dispatch_degree<MAXM>(fit_deg(d, f), body);
-    });
+        const int64_t te = cur.fe < t1 ? cur.fe : t1;
+        const bool more = te < t1;   // then fit f + 1 < B holds the next tile
+        AdjMeta<MAXM> nxt = cur;
+        if (more) nxt = load_adj_meta<MAXM>(d, w, f + 1);
+        const int64_t plo = cur.lo + (t - cur.fs) * tile;
+        int64_t phi = cur.lo + (te - cur.fs) * tile;
+        if (phi > cur.hi) phi = cur.hi;
+        if (cur.st != LSEFIT_OK) {
+            adjoint_nan(gx, gy, plo, phi, first, step);
+        } else {
+            auto body = [&]<int M>() {
+                AdjointPoint<M, In> P;
+                P.template init<MAXM>(cur.c, cur.s, cur.b, cur.lam);
+                adjoint_segment<U>(P, x, y, gx, gy, plo, phi, mis, first, step, edge);
+            };
+            dispatch_degree<MAXM>(cur.deg, body);
+        }
+        t = te;
+        ++f;
+        cur = nxt;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1097,6 +1178,7 @@ template <int MAXM, typename In, int U>
 __global__ void __launch_bounds__(256)
     k_residual(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ resid,
                int64_t W, int mis) {
+    const KernelClock kclock_(w.clock);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     constexpr int stride = nacc(MAXM);
     constexpr int rl = rec_len(MAXM);

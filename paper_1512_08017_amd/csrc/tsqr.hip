@@ -263,6 +263,7 @@ template <typename In, int U, int M>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(qr_waves_per_eu(M))))
     k_qr_single(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t W, int mis,
                 RangeArg ra) {
+    const KernelClock kclock_(w.clock);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     double c, inv_s;
     single_range(d, w, x, ra, &c, &inv_s);
@@ -330,6 +331,7 @@ template <int M>
 __global__ void __launch_bounds__(256)
     k_qr_finish(FitDesc d, Work w, int64_t G, int maxm, double* __restrict__ coef, int32_t* __restrict__ status,
                 double* __restrict__ info) {
+    const KernelClock kclock_(w.clock);
     constexpr int N = M + 1;
     constexpr int LEN = GivensQR<N>::LEN;
     __shared__ double sh[4][LEN];
@@ -366,6 +368,7 @@ template <typename In, int MAXC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(qr_waves_per_eu(MAXC))))
     k_qr_batch(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, int64_t W,
                int mis, int maxm) {
+    const KernelClock kclock_(w.clock);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id_in_block();
     const int stride = qr_len(maxm);
     const int rl = rec_len(maxm);
@@ -394,6 +397,7 @@ template <int MAXC>
 __global__ void __launch_bounds__(256)
     k_qr_combine(FitDesc d, Work w, int64_t W, int maxm, double* __restrict__ coef, int32_t coef_stride,
                  int32_t* __restrict__ status, double* __restrict__ sse) {
+    const KernelClock kclock_(w.clock);
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.batch) return;
     double* out = coef + f * (int64_t)coef_stride;

@@ -218,7 +218,7 @@ def test_copy_probe_validation():
     odd = ctypes.c_void_p(0x1004)
     assert L.lsefit_copy_probe(FAKE, FAKE, None, FAKE, 1024, None, 0, 1, None) == _lib.INVALID_ARG
     assert L.lsefit_copy_probe(FAKE, FAKE, odd, FAKE, 1024, None, 0, 1, None) == _lib.INVALID_ARG
-    assert L.lsefit_copy_probe(FAKE, FAKE, FAKE, FAKE, 1024, None, 2, 1, None) == _lib.INVALID_ARG
+    assert L.lsefit_copy_probe(FAKE, FAKE, FAKE, FAKE, 1024, None, 3, 1, None) == _lib.INVALID_ARG
     assert L.lsefit_copy_probe(FAKE, FAKE, FAKE, FAKE, 3, None, 0, 1, None) == _lib.INVALID_ARG
 
 

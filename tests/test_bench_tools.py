@@ -38,7 +38,8 @@ def test_summarize_counters(tmp_path):
     text = out.read_text().splitlines()
     assert text[0] == "# rocprofv3 counter summary: title"
     assert "#   the command" in text
-    body = [ln for ln in text if not ln.startswith("#")]
+    assert f"kernel_hash {bench.kernel_hash()}" in text
+    body = [ln for ln in text if not ln.startswith("#") and not ln.startswith("kernel_hash")]
     # library kernels only, the longest in total first; averages per dispatch
     assert body[0] == "void lsefit::k_moments<3, 0, float, 2>  dispatches 2  avg 119.00 us"
     vals = {ln.split()[0]: ln.split()[1] for ln in body[1:3]}
@@ -46,3 +47,43 @@ def test_summarize_counters(tmp_path):
     assert body[3] == "lsefit::k_finish_single<3>  dispatches 1  avg 8.00 us"
     assert not any("elementwise" in ln for ln in text)
     assert os.path.getsize(out) < 4096
+
+
+STATS_FIELDS = ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"]
+
+
+def test_summarize_trace_timed_region(tmp_path, monkeypatch):
+    """The trace summary averages the dispatches of the timed region (by launch
+    order, skipping the warm-up ones) and bench.py reads that average back only
+    while the kernel sources hash the same."""
+    k1 = "void lsefit::k_moments<3, 0, float, 2>(lsefit::FitDesc, lsefit::Work)"
+    k2 = "lsefit::k_finish_single<3>(lsefit::FitDesc)"
+    trace, t = [], 0
+    durs = [200, 150, 100, 110, 120, 900]          # 2 warm-up, 3 timed, 1 later (us)
+    for i, d in enumerate(durs):
+        trace.append({"Dispatch_Id": 2 * i, "Kernel_Name": k1, "Start_Timestamp": t, "End_Timestamp": t + d * 1000})
+        t += d * 1000
+        trace.append({"Dispatch_Id": 2 * i + 1, "Kernel_Name": k2, "Start_Timestamp": t, "End_Timestamp": t + 7000})
+        t += 7000
+    # rows out of launch order in the file: the summary sorts by start time
+    trace = trace[::-1]
+    stats = [{"Name": k1, "Calls": 6, "TotalDurationNs": 1580000, "AverageNs": 263333.3, "Percentage": 90,
+              "MinNs": 100000, "MaxNs": 900000, "StdDev": 0},
+             {"Name": k2, "Calls": 6, "TotalDurationNs": 42000, "AverageNs": 7000, "Percentage": 10,
+              "MinNs": 7000, "MaxNs": 7000, "StdDev": 0}]
+    sub = tmp_path / "run"
+    sub.mkdir()
+    write_csv(sub / "run_kernel_trace.csv", TRACE_FIELDS, trace)
+    write_csv(sub / "run_kernel_stats.csv", STATS_FIELDS, stats)
+    out = tmp_path / "trace.txt"
+    bench.summarize_trace(str(tmp_path), "title", "the command", out_path=str(out),
+                          timed=("k_moments<3, 0, float, 2>", "2", "3"))
+    text = out.read_text().splitlines()
+    timed = [ln for ln in text if ln.startswith("timed_region")]
+    assert timed == ["timed_region k_moments<3, 0, float, 2> dispatches 2..4 of 6  "
+                     "avg 110.00 us  min 100.00 us  max 120.00 us"]
+    monkeypatch.setattr(bench, "TRACE_FILE", str(out))
+    assert abs(bench.profile_timed_avg_ms() - 0.110) < 1e-12
+    # another source hash: the stored figure no longer describes these kernels
+    monkeypatch.setattr(bench, "kernel_hash", lambda: "0000000000000000")
+    assert bench.profile_timed_avg_ms() is None

@@ -24,6 +24,9 @@
  *    call, except that a plan caches a captured graph that refers to the
  *    arrays of its last call (see fit_batched).
  *  - x and y share one dtype (LSEFIT_F32 or LSEFIT_F64); gradients have it too.
+ *    Integer codes (dtype, status) travel as int32_t, so that any value a
+ *    caller passes is well defined and an unknown one is reported as
+ *    INVALID_ARG (or "unknown status") rather than read as an enumeration.
  *    Coefficients and power sums are always float64, lowest power first.
  *  - Work is enqueued on `stream` (a hipStream_t; NULL is the default stream).
  *    No entry point synchronises the device except fit_plan_tune.
@@ -179,9 +182,14 @@ size_t lsefit_workspace_bytes(int64_t batch, int32_t max_degree, const lsefit_sc
 /* (max_degree up to LSEFIT_MAX_DEGREE_CHEBYSHEV for Chebyshev-basis calls) */
 
 /* The schedule used when no plan is given (initially sized to this device's
- * compute units).  lsefit_set_default_schedule replaces it for the whole
+ * compute units: 8 waves per unit, 4 per block, tiles of 2,048 points, 2
+ * vectors in flight).  lsefit_set_default_schedule replaces it for the whole
  * process (NULL restores the initial one); it is not synchronised with calls
- * running on other host threads.  Workspace sizes depend on it. */
+ * running on other host threads.  Workspace sizes depend on it.  While the
+ * initial schedule is in force, the power-sum, refinement and residual passes
+ * of a single fit (monomial basis) over fewer than 32 MiB of points run 4
+ * waves per unit instead (4 vectors in flight for float64 points), which
+ * needs no more workspace; a schedule set by the caller is used as given. */
 lsefit_status lsefit_default_schedule(lsefit_schedule* out);
 lsefit_status lsefit_set_default_schedule(const lsefit_schedule* schedule);
 
@@ -194,7 +202,7 @@ lsefit_status lsefit_set_default_schedule(const lsefit_schedule* schedule);
  *            t = (x - c)/s (S_0 = n exactly)
  * Errors: INVALID_ARG (null pointer, n < m+1, bad degree/option), UNSUPPORTED
  * (F32C with float64 data), WORKSPACE (ws too small), DEVICE (launch failure). */
-lsefit_status fit_moments(const void* x, const void* y, int64_t n, lsefit_dtype dt,
+lsefit_status fit_moments(const void* x, const void* y, int64_t n, int32_t dt,
                           const lsefit_options* opt, void* ws, size_t ws_bytes,
                           double* moments, void* stream);
 
@@ -208,7 +216,7 @@ lsefit_status fit_moments(const void* x, const void* y, int64_t n, lsefit_dtype 
  *  status:   output, device int32 [1]
  * x and y may be NULL when no refinement is requested. */
 lsefit_status fit_solve(const double* moments, const lsefit_options* opt,
-                        const void* x, const void* y, int64_t n, lsefit_dtype dt,
+                        const void* x, const void* y, int64_t n, int32_t dt,
                         void* ws, size_t ws_bytes, double* coef, int32_t* status, void* stream);
 
 /* fit_moments followed by fit_solve in one call, with fewer launches: the
@@ -218,7 +226,7 @@ lsefit_status fit_solve(const double* moments, const lsefit_options* opt,
  *  status:   output, device int32 [1]
  *  moments:  optional output (NULL to skip), device float64 [3m+4] as in fit_moments
  * Errors as fit_moments. */
-lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
+lsefit_status fit_single(const void* x, const void* y, int64_t n, int32_t dt, const lsefit_options* opt,
                          void* ws, size_t ws_bytes, double* coef, int32_t* status, double* moments, void* stream);
 
 /* fit_single for callers that cannot allocate device memory (code under HIP
@@ -240,7 +248,7 @@ lsefit_status fit_single(const void* x, const void* y, int64_t n, lsefit_dtype d
  * schedule's wave count) exceeds LSEFIT_NOALLOC_SCRATCH_BYTES, and DEVICE when
  * the array's address cannot be resolved on the current device. */
 #define LSEFIT_NOALLOC_SCRATCH_BYTES (4u << 20)
-lsefit_status fit_single_noalloc(const void* x, const void* y, int64_t n, lsefit_dtype dt,
+lsefit_status fit_single_noalloc(const void* x, const void* y, int64_t n, int32_t dt,
                                  const lsefit_options* opt, double* coef, int32_t* status, double* moments,
                                  void* stream);
 
@@ -263,7 +271,7 @@ lsefit_status fit_single_noalloc(const void* x, const void* y, int64_t n, lsefit
  *  info:     optional output (NULL to skip), device float64 [3]: c, s and the
  *            residual sum of squares sum_i (y_i - f(x_i))^2 (NaN unless OK)
  * fit_residuals may follow on the same workspace.  Errors as fit_moments. */
-lsefit_status fit_qr(const void* x, const void* y, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
+lsefit_status fit_qr(const void* x, const void* y, int64_t n, int32_t dt, const lsefit_options* opt,
                      void* ws, size_t ws_bytes, double* coef, int32_t* status, double* info, void* stream);
 
 /* fit_qr for B independent fits over CSR segments (layout as fit_batched):
@@ -277,7 +285,7 @@ lsefit_status fit_qr(const void* x, const void* y, int64_t n, lsefit_dtype dt, c
  *            default schedule; no plan)
  * opt, errors and limits as fit_qr; fit_residuals may follow on the same ws. */
 lsefit_status fit_qr_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
-                             int64_t batch, lsefit_dtype dt, const lsefit_options* opt, void* ws, size_t ws_bytes,
+                             int64_t batch, int32_t dt, const lsefit_options* opt, void* ws, size_t ws_bytes,
                              double* coef, int32_t coef_stride, int32_t* status, double* sse, void* stream);
 
 /* B independent fits over CSR segments: fit f owns points offsets[f] ..
@@ -296,7 +304,7 @@ lsefit_status fit_qr_batched(const void* x, const void* y, const int64_t* offset
  * All fits run in one launch of the persistent streaming kernel (plus a tile
  * table kernel before it and one solve kernel after it). */
 lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
-                          int64_t batch, lsefit_dtype dt, const lsefit_options* opt,
+                          int64_t batch, int32_t dt, const lsefit_options* opt,
                           lsefit_plan* plan, void* ws, size_t ws_bytes,
                           double* coef, int32_t coef_stride, int32_t* status, void* stream);
 
@@ -317,7 +325,7 @@ lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, 
  * cuts every fit where the forward did); `ws_bytes` must still cover the
  * workspace size of the schedule in force (else WORKSPACE). */
 lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
-                           int64_t batch, lsefit_dtype dt, const lsefit_options* opt,
+                           int64_t batch, int32_t dt, const lsefit_options* opt,
                            lsefit_plan* plan, void* ws, size_t ws_bytes,
                            const double* grad_coef, int32_t coef_stride,
                            void* grad_x, void* grad_y, void* stream);
@@ -334,7 +342,7 @@ lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets,
  *              status is not OK
  *  residuals:  optional output (NULL to skip), device, dtype dt, one per point */
 lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
-                            int64_t batch, int64_t n, lsefit_dtype dt, const lsefit_options* opt,
+                            int64_t batch, int64_t n, int32_t dt, const lsefit_options* opt,
                             lsefit_plan* plan, void* ws, size_t ws_bytes, double* sse, void* residuals,
                             void* stream);
 
@@ -344,7 +352,7 @@ lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets
  * schedules on the given data (it synchronises `stream`) and keeps the
  * fastest; fit_plan_set_schedule installs a known one (for example from a
  * cache).  A plan must be used from one stream at a time. */
-lsefit_status fit_plan_create(lsefit_plan** plan, int64_t batch, int32_t max_degree, lsefit_dtype dt,
+lsefit_status fit_plan_create(lsefit_plan** plan, int64_t batch, int32_t max_degree, int32_t dt,
                               int32_t precision);
 lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, const int64_t* offsets,
                             const int32_t* degrees, int64_t batch, const lsefit_options* opt,
@@ -367,7 +375,9 @@ lsefit_status fit_plan_get_schedule(const lsefit_plan* plan, lsefit_schedule* ou
 lsefit_status fit_plan_set_graph(lsefit_plan* plan, int32_t enable);
 void fit_plan_destroy(lsefit_plan* plan);
 
-const char* lsefit_status_string(lsefit_status s);
+/* A short description of a status code: any lsefit_status value, and
+ * "unknown status" for every other integer. */
+const char* lsefit_status_string(int32_t status);
 
 /* Read-bandwidth probe, for measurement only (no part of the fit): streams two
  * float32 arrays of n elements (n rounded down to a multiple of 4; both

@@ -15,11 +15,14 @@ BUILD_NOTE = _build.BUILD_NOTE
 
 
 def lib():
+    """The oracle library (LSE_ORACLE_LIB: another build of it, such as the
+    sanitized one the CPU sanitizer test loads)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("LSE_ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        L = ctypes.CDLL(path)
         L.lse_oracle_power_sums.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                             ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                             _dbl_p, _dbl_p, ctypes.c_int]

@@ -5,7 +5,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblsefit.so")
+# LSEFIT_LIB names another build of the same library (the host-sanitized build
+# that the CPU sanitizer test loads); by default the in-tree liblsefit.so
+LIB_PATH = os.environ.get("LSEFIT_LIB") or os.path.join(HERE, "liblsefit.so")
 
 LSEFIT_MAX_DEGREE = 8
 OK, INVALID_ARG, SINGULAR, NONFINITE, WORKSPACE, DEVICE, UNSUPPORTED = range(7)

@@ -249,14 +249,20 @@ __device__ inline void stream_segment(const In* __restrict__ x, const In* __rest
 // U vectors per array are loaded before the current round is accumulated, so
 // that a wave covers its own load latency with its arithmetic (few waves fit
 // per SIMD at high degree).
-template <int U, typename In, class Acc>
+//
+// `prologue` runs once per lane after the first round's loads are issued and
+// before anything is accumulated (it must be called by every wave of the
+// block: it may hold a barrier); the power-sum pass derives (c, s) there, so
+// that the range sample's latency overlaps the first loads.
+template <int U, bool PRO, typename In, class Acc, class Pro>
 __device__ inline void stream_strided(const In* __restrict__ x, const In* __restrict__ y, int64_t n, int mis,
-                                      int64_t gwave, int64_t W, Acc& acc) {
+                                      int64_t gwave, int64_t W, Acc& acc, Pro&& prologue) {
     constexpr int VW = VecOf<In>::W;
     using V = typename VecOf<In>::type;
     const int lane = lane_id();
     const int64_t step = W * kWave;
     if (mis < 0) {
+        prologue();
         for (int64_t i = gwave * kWave + lane; i < n; i += step) acc.scalar(ld_scalar(x + i), ld_scalar(y + i));
         return;
     }
@@ -264,7 +270,9 @@ __device__ inline void stream_strided(const In* __restrict__ x, const In* __rest
     if (a > n) a = n;
     const int64_t nv = (n - a) / VW;
     const int64_t b = a + nv * VW;
-    if (gwave == 0 && lane < a) acc.scalar(ld_scalar(x + lane), ld_scalar(y + lane));
+    // without a prologue the head goes first, so that no vector is live across
+    // it (the register budget of the passes with large accumulators)
+    if (!PRO && gwave == 0 && lane < a) acc.scalar(ld_scalar(x + lane), ld_scalar(y + lane));
     const V* __restrict__ xv = reinterpret_cast<const V*>(x + a);
     const V* __restrict__ yv = reinterpret_cast<const V*>(y + a);
     const int64_t span = (int64_t)(U - 1) * step;
@@ -277,6 +285,10 @@ __device__ inline void stream_strided(const In* __restrict__ x, const In* __rest
             xs[u] = ld_stream(xv + j + u * step);
             ys[u] = ld_stream(yv + j + u * step);
         }
+    }
+    if constexpr (PRO) {
+        prologue();
+        if (gwave == 0 && lane < a) acc.scalar(ld_scalar(x + lane), ld_scalar(y + lane));
     }
     while (have) {
         const int64_t jn = j + (int64_t)U * step;
@@ -303,6 +315,12 @@ __device__ inline void stream_strided(const In* __restrict__ x, const In* __rest
     }
     for (; j < nv; j += step) acc.template vec<V, VW>(ld_stream(xv + j), ld_stream(yv + j));
     if (gwave == 0 && lane < n - b) acc.scalar(ld_scalar(x + b + lane), ld_scalar(y + b + lane));
+}
+
+template <int U, typename In, class Acc>
+__device__ inline void stream_strided(const In* __restrict__ x, const In* __restrict__ y, int64_t n, int mis,
+                                      int64_t gwave, int64_t W, Acc& acc) {
+    stream_strided<U, false>(x, y, n, mis, gwave, W, acc, [] {});
 }
 
 // run body.template operator()<m>() for the runtime degree m (1 <= m <= MAXM)
@@ -714,14 +732,16 @@ __global__ void __launch_bounds__(256)
     constexpr int stride = nacc(MAXM);
     constexpr int rl = rec_len(MAXM);
     if (is_single(d)) {
-        double c, inv_s;
-        single_range(d, w, x, ra, &c, &inv_s);
         auto body = [&]<int M>() {
             using Acc = std::conditional_t<PREC == LSEFIT_PREC_F64, AccF64<M>, AccF32C<M>>;
             double v[nacc(M)];
             Acc acc;
-            acc.init(c, inv_s);
-            stream_strided<U>(x, y, d.n_single, mis, wave, W, acc);
+            // (c, s) from the range sample while the first loads are in flight
+            stream_strided<U, true>(x, y, d.n_single, mis, wave, W, acc, [&] {
+                double c, inv_s;
+                single_range(d, w, x, ra, &c, &inv_s);
+                acc.init(c, inv_s);
+            });
             acc.out(v);
 #pragma unroll
             for (int k = 0; k < nacc(M); ++k) v[k] = wave_sum(v[k]);

@@ -13,7 +13,7 @@ import pytest
 
 from gpu_common import announce, normwise, to_dev, torch
 from oracle import adjoint, c_oracle, fp64
-from paper_1512_08017_amd import workloads as W
+from paper_1512_08017_amd import _lib, api, workloads as W
 
 pytestmark = pytest.mark.gpu
 
@@ -281,3 +281,83 @@ def test_residuals_table_v():
     # the residuals themselves (e = y - f(x)) against the exact fitted values
     fe = np.array([float(exact.polyval_exact(a_ex, xv)) for xv in x])
     assert np.max(np.abs(e.cpu().numpy() - (y - fe))) <= 1e-8
+
+
+# --- streams, graph capture and long runs of single fits --------------------------
+
+def test_single_fits_on_several_streams():
+    """Fits on three streams at once, each with its own workspace: each result
+    equals the same fit run alone, bit for bit."""
+    fits = [W.random_small(n, 3, seed=s, dtype=np.float32) for n, s in ((3_000_001, 61), (700_003, 62),
+                                                                          (5_000_011, 63))]
+    data = [(to_dev(f.x), to_dev(f.y)) for f in fits]
+    alone = []
+    for x, y in data:
+        r = lf.fit(x, y, 3)
+        torch.cuda.synchronize()
+        alone.append(r.coef.cpu().numpy())
+    streams = [torch.cuda.Stream() for _ in data]
+    outs = []
+    for _ in range(3):
+        res = []
+        for (x, y), s in zip(data, streams):
+            with torch.cuda.stream(s):
+                res.append(lf.fit(x, y, 3))
+        torch.cuda.synchronize()
+        outs.append([r.coef.cpu().numpy() for r in res])
+    for rep in outs:
+        for got, ref in zip(rep, alone):
+            assert np.array_equal(got, ref)
+    for f, ref in zip(fits, alone):
+        assert normwise(ref[:4], c_oracle.fit(f.x, f.y, 3)["a"]) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32c"])
+def test_captured_single_fit_matches_eager(precision):
+    """fit_single captured into a HIP graph: replays, with eager calls between
+    them, give the eager bits."""
+    fit = W.random_small(1_500_007, 3, seed=64, dtype=np.float32)
+    x, y = to_dev(fit.x), to_dev(fit.y)
+    L = _lib.load()
+    vp = ctypes.c_void_p
+    opt = api.options(3, precision, 1)
+    ws = torch.zeros(api.workspace_bytes(1, 3), dtype=torch.uint8, device=x.device)
+    coef = torch.zeros(8, dtype=torch.float64, device=x.device)
+    status = torch.zeros(1, dtype=torch.int32, device=x.device)
+    er = lf.fit(x, y, 3, precision=precision)
+    torch.cuda.synchronize()
+    eager = np.concatenate([er.coef.cpu().numpy(), er.coef_t.cpu().numpy()])   # a, then b
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        args = (vp(x.data_ptr()), vp(y.data_ptr()), x.numel(), _lib.F32, ctypes.byref(opt), vp(ws.data_ptr()),
+                ws.numel(), vp(coef.data_ptr()), vp(status.data_ptr()), None, vp(s.cuda_stream))
+        _lib.check(L.fit_single(*args), "fit_single")     # eager call on the capture stream first
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            _lib.check(L.fit_single(*args), "fit_single")
+    for i in range(3):
+        coef.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(coef.cpu().numpy(), eager), i
+        assert int(status.cpu()[0]) == 0
+        lf.fit(x, y, 3, precision=precision)                  # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_single_fit_stress_against_split():
+    """Many fits in a row of changing size and degree on one stream: fit_single
+    gives, every time, the power sums of fit_moments bit for bit."""
+    rng = np.random.default_rng(65)
+    base = W.random_small(4_000_037, 4, seed=65, dtype=np.float32)
+    x, y = to_dev(base.x), to_dev(base.y)
+    for i in range(120):
+        n = int(rng.integers(50_000, 4_000_037))
+        m = int(rng.integers(1, 5))
+        xs, ys = x[:n], y[:n]
+        fused = lf.fit(xs, ys, m)
+        split_mom, _ = lf.fit_moments(xs, ys, m)
+        torch.cuda.synchronize()
+        assert int(fused.status.cpu()[0]) == 0, i
+        assert np.array_equal(fused.moments.cpu().numpy(), split_mom.cpu().numpy()), (i, n, m)

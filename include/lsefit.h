@@ -323,7 +323,11 @@ lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, 
  * into that workspace.  The tile table carries the tile size it was built
  * with, so the default schedule may change between the two calls (the pass
  * cuts every fit where the forward did); `ws_bytes` must still cover the
- * workspace size of the schedule in force (else WORKSPACE). */
+ * workspace size of the schedule in force (else WORKSPACE).  The streaming
+ * pass of the adjoint keeps no partial sums: it runs its own launch shape
+ * (16 waves per compute unit, 2 per block, 1 vector in flight per lane), not
+ * the plan's, unless the caller has set a default schedule, which it then
+ * uses; the gradients are the same bits under any shape. */
 lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
                            int64_t batch, int32_t dt, const lsefit_options* opt,
                            lsefit_plan* plan, void* ws, size_t ws_bytes,

@@ -449,9 +449,12 @@ __device__ inline void fail_fit(const FitDesc& d, const Work& w, int64_t f, cons
 // solved with a row per lane (wave_gepp / wave_cholesky, the same operations
 // per entry as hankel_solve / hankel_cholesky) and the change back to the
 // x-basis runs with a coefficient per lane.  sm: 3M+2 doubles of this wave's LDS.
+//
+// rin: a copy of the fit's record to read from (NULL: the record itself); the
+// results are always written to the record in the workspace.
 template <int M, int MAXM>
 __device__ inline void finish_fit_wave(const FitDesc& d, const Work& w, int64_t f, const double (&v)[nacc(M)],
-                                       const Finish& fz, double* sm) {
+                                       const Finish& fz, double* sm, const double* rin = nullptr) {
     constexpr int N = M + 1;
     constexpr int rl = rec_len(MAXM);
     const int lane = lane_id();
@@ -461,12 +464,13 @@ __device__ inline void finish_fit_wave(const FitDesc& d, const Work& w, int64_t 
         return;
     }
     double* r = w.rec + f * rl;
-    const double c = r[0], s = r[1];
+    const double* rr = rin ? rin : r;
+    const double c = rr[0], s = rr[1];
     // S_0..S_2M and the right side (T, or the refinement sums) into LDS
     if (lane == 0) {
         if (fz.mode == kRefine) {
 #pragma unroll
-            for (int k = 0; k <= 2 * M; ++k) sm[k] = r[rec_S(MAXM) + k];
+            for (int k = 0; k <= 2 * M; ++k) sm[k] = rr[rec_S(MAXM) + k];
 #pragma unroll
             for (int j = 0; j < N; ++j) sm[2 * M + 1 + j] = v[j];
         } else {
@@ -509,7 +513,7 @@ __device__ inline void finish_fit_wave(const FitDesc& d, const Work& w, int64_t 
                                                                       : wave_gepp<M>(row, x));
     if (st == LSEFIT_OK && __ballot(mine && !isfinite(x))) st = LSEFIT_ERR_NONFINITE;
     double b = x;
-    if (fz.mode == kRefine && mine) b = r[rec_b(MAXM) + lane] + x;
+    if (fz.mode == kRefine && mine) b = rr[rec_b(MAXM) + lane] + x;
     // a_k = sum_(j>=k) b_j C(j,k) (-c)^(j-k) s^-j, lane k (the order of to_x_basis)
     double a = 0.0;
     if (st == LSEFIT_OK) {
@@ -592,16 +596,20 @@ __device__ inline void block_combine_fit(const FitDesc& d, const Work& w, int64_
 
 // single fit: the threads of one block sum the G block partials (thread t takes
 // blocks t, t + blockDim, ...; then waves in order) and wave 0 finishes the fit
+//
+// Every load the finish needs is issued at its start -- the fit's status and
+// range record with the partials -- so that they cost one memory round trip,
+// not three in a row; the partials are summed whatever the status (the pass
+// before always writes them) and the status only decides what is written.
 template <int MAXM>
 __device__ inline void finish_single_block(const FitDesc& d, const Work& w, int64_t G, const Finish& fz) {
     constexpr int stride = nacc(MAXM);
+    constexpr int rl = rec_len(MAXM);
     __shared__ double sh[16][stride];
     __shared__ double sm[3 * MAXM + 2];
+    __shared__ double rs[rl];
     const int pst = w.pstatus[0];
-    if (pst != LSEFIT_OK) {
-        if (threadIdx.x == 0 && fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, 0, fz, pst);
-        return;
-    }
+    const double rv = threadIdx.x < rl ? w.rec[threadIdx.x] : 0.0;
     auto body = [&]<int M>() {
         constexpr int K = nacc(M);
         const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
@@ -620,10 +628,15 @@ __device__ inline void finish_single_block(const FitDesc& d, const Work& w, int6
 #pragma unroll
             for (int k = 0; k < K; ++k) sh[wave_id_in_block()][k] = v[k];
         }
+        if (threadIdx.x < rl) rs[threadIdx.x] = rv;
         __syncthreads();
         if (wave_id_in_block() == 0) {
-            wave_column_sums<K, stride>(sh, blockDim.x / kWave, v);
-            finish_fit_wave<M, MAXM>(d, w, 0, v, fz, sm);
+            if (pst != LSEFIT_OK) {
+                if (lane_id() == 0 && fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, 0, fz, pst);
+            } else {
+                wave_column_sums<K, stride>(sh, blockDim.x / kWave, v);
+                finish_fit_wave<M, MAXM>(d, w, 0, v, fz, sm, rs);
+            }
         }
     };
     dispatch_degree<MAXM>(d.degree, body);

@@ -212,9 +212,9 @@ def test_split_calls_match_fused_call(precision):
     assert int(fused.status.cpu()[0]) == int(split.status.cpu()[0]) == 0
 
 
-def test_ticket_reuse_across_calls_and_workspaces():
-    """The single-fit ticket resets itself: many calls on one workspace, and a
-    fresh workspace holding stale bytes, give identical results."""
+def test_reuse_across_calls_and_workspaces():
+    """Nothing in the workspace has to start at zero: many calls on one
+    workspace that first holds arbitrary bytes give identical results."""
     fit = W.random_small(2_000_003, 2, seed=46, dtype=np.float32)
     x, y = to_dev(fit.x), to_dev(fit.y)
     ws = torch.full((lf.workspace_bytes(1, 2),), 0x5A, dtype=torch.uint8, device=x.device)

@@ -523,40 +523,31 @@ __device__ __forceinline__ void cheb_store_sums(const Work& w, int64_t f, int ma
     wave_lds_fence();
 }
 
-// Single fit of degree M (one block of finish_threads(W) threads): the threads
-// sum the W block partials (sum-major; thread t takes blocks t, t + blockDim,
-// ...; then waves in order) and wave 0 finishes.
+// Single fit of degree M: the finish block adds up the W block partials
+// (block_sum_partials) and wave 0 finishes.  The fit's status and range are
+// loaded at the start, with the partials; the partials are summed whatever the
+// status and the status only decides what is written.
 template <int M>
-__global__ void __launch_bounds__(kFinishMaxThreads)
+__global__ void __launch_bounds__(kFinishWaves * kWave)
     k_finish_cheb_single(FitDesc d, Work w, int64_t W, int maxm, Finish fz) {
     const KernelClock kclock_(w.clock);
     constexpr int K = nacc(M);
-    __shared__ double sh[kFinishMaxThreads / kWave][K];
+    __shared__ double sums[K];
     __shared__ double S[3 * M + 2];
-    const int wid = wave_id_in_block(), lane = lane_id();
     const int pst = w.pstatus[0];
+    const double c = w.rec[0], s = w.rec[1];
+    block_sum_partials<K>(w.part, W, sums);
+    __syncthreads();
+    if (wave_id_in_block() != 0) return;
     if (pst != LSEFIT_OK) {
-        if (threadIdx.x == 0 && fz.mode != kMomentsOnly) cheb_fail(d, w, 0, maxm, fz, pst);
+        if (lane_id() == 0 && fz.mode != kMomentsOnly) cheb_fail(d, w, 0, maxm, fz, pst);
         return;
     }
     double v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0.0;
-    for (int64_t g = threadIdx.x; g < W; g += blockDim.x) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += w.part[(int64_t)k * W + g];
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) sh[wid][k] = v[k];
-    }
-    __syncthreads();
-    if (wid != 0) return;
-    wave_column_sums<K, K>(sh, blockDim.x / kWave, v);
+    for (int k = 0; k < K; ++k) v[k] = sums[k];
     cheb_store_sums<M>(w, 0, maxm, (double)d.n_single, v, fz, S);
-    if (fz.mode != kMomentsOnly) cheb_solve_wave<M>(w, 0, maxm, w.rec[0], w.rec[1], S, fz);
+    if (fz.mode != kMomentsOnly) cheb_solve_wave<M>(w, 0, maxm, c, s, S, fz);
 }
 
 // Batch, degrees up to MAXC: wave v of block b finishes fits 4b + v,
@@ -1076,7 +1067,7 @@ hipError_t launch_finish_cheb(const FitDesc& d, const Work& w, int maxm, int64_t
                               hipStream_t st) {
     if (is_single(d)) {
         auto body = [&]<int M>() {
-            launch_timed(k_finish_cheb_single<M>, dim3(1), dim3(finish_threads(W)), st, d, w, W, maxm, fz);
+            launch_timed(k_finish_cheb_single<M>, dim3(1), dim3(kFinishWaves * kWave), st, d, w, W, maxm, fz);
         };
         dispatch_degree<kChebMax>(d.degree, body);
         return hipGetLastError();

@@ -350,6 +350,19 @@ __host__ __device__ inline void dispatch_degree(int m, Body&& body) {
 // ---------------------------------------------------------------------------
 // per-fit combine and solve
 // ---------------------------------------------------------------------------
+
+// run body.template operator()<NK>() for the number of partial sums a finish
+// of this mode reads: the M + 1 refinement sums, the one sum of squares, or all
+// nacc(M).  With NK fixed at compile time the loads of a partial slot carry no
+// per-sum condition, so they are issued together rather than each behind a
+// branch of its own (a wait per load).
+template <int M, class Body>
+__device__ inline void dispatch_sum_count(int mode, Body&& body) {
+    if (mode == kRefine) body.template operator()<M + 1>();
+    else if (mode == kSSE) body.template operator()<1>();
+    else body.template operator()<nacc(M)>();
+}
+
 template <int M, int MAXM>
 __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, const double (&v)[nacc(M)],
                                   const Finish& fz) {
@@ -566,19 +579,19 @@ __device__ inline void block_combine_fit(const FitDesc& d, const Work& w, int64_
     const int64_t w0 = wave_of_tile(ts, NT, W), w1 = wave_of_tile(te - 1, NT, W);
     auto body = [&]<int M>() {
         constexpr int K = nacc(M);
-        const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
         double v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = 0.0;
-        for (int64_t wv = w0 + threadIdx.x; wv <= w1; wv += blockDim.x) {
-            if (!wave_owns_tiles(wv, NT, W)) continue;
-            const double* p = w.part + (wv + f) * stride;
+        dispatch_sum_count<M>(fz.mode, [&]<int NK>() {
+            for (int64_t wv = w0 + threadIdx.x; wv <= w1; wv += blockDim.x) {
+                if (!wave_owns_tiles(wv, NT, W)) continue;
+                const double* p = w.part + (wv + f) * stride;
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k < nk) v[k] += p[k];
-        }
+                for (int k = 0; k < NK; ++k) v[k] += p[k];
+            }
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+            for (int k = 0; k < NK; ++k) v[k] = wave_sum(v[k]);
+        });
         const int wv = wave_id_in_block();
         if (lane_id() == 0) {
 #pragma unroll
@@ -594,47 +607,79 @@ __device__ inline void block_combine_fit(const FitDesc& d, const Work& w, int64_
     dispatch_degree<MAXM>(fit_deg(d, f), body);
 }
 
-// single fit: the threads of one block sum the G block partials (thread t takes
-// blocks t, t + blockDim, ...; then waves in order) and wave 0 finishes the fit
-//
-// Every load the finish needs is issued at its start -- the fit's status and
-// range record with the partials -- so that they cost one memory round trip,
-// not three in a row; the partials are summed whatever the status (the pass
-// before always writes them) and the status only decides what is written.
+// The G block partials of a single fit, stored sum-major (part[k * G + g]), are
+// added up by a finish block of kFinishWaves waves: wave v takes sums v,
+// v + kFinishWaves, ...; lane l adds blocks l, l + 64, l + 128, ... in that
+// order, then the wave's butterfly (wave_sum) adds the lanes, and lane 0 writes
+// the total of sum k to out[k] (LDS).  All of a wave's loads are issued
+// together, kFinishChunk per lane and sum at a time, so that one memory round
+// trip covers up to 512 blocks: a lane past the last block reads the last block
+// again and drops it, rather than branching around its load.
+constexpr int kFinishWaves = 8;
+constexpr int kFinishChunk = 8;
+
+template <int NK>
+__device__ inline void block_sum_partials(const double* __restrict__ part, int64_t G, double* out) {
+    constexpr int C = (NK + kFinishWaves - 1) / kFinishWaves;   // sums per wave, at most
+    const int wv = wave_id_in_block(), lane = lane_id();
+    if (wv >= NK) return;
+    const double* p[C];
+    double t[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        p[c] = part + (int64_t)min(wv + c * kFinishWaves, NK - 1) * G;
+        t[c] = 0.0;
+    }
+    for (int64_t g0 = 0; g0 < G; g0 += kFinishChunk * kWave) {
+        double x[kFinishChunk][C];
+#pragma unroll
+        for (int i = 0; i < kFinishChunk; ++i) {
+            const int64_t g = min(g0 + i * kWave + lane, G - 1);
+#pragma unroll
+            for (int c = 0; c < C; ++c) x[i][c] = p[c][g];
+        }
+#pragma unroll
+        for (int i = 0; i < kFinishChunk; ++i) {
+            const bool in = g0 + i * kWave + lane < G;
+#pragma unroll
+            for (int c = 0; c < C; ++c) t[c] = in ? t[c] + x[i][c] : t[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const double tot = wave_sum(t[c]);
+        const int k = wv + c * kFinishWaves;
+        if (lane == 0 && k < NK) out[k] = tot;
+    }
+}
+
+// single fit: the finish block adds up the partials (block_sum_partials) and
+// wave 0 finishes the fit.  Every load the finish needs is issued at its start
+// -- the fit's status and range record with the partials -- so that they cost
+// one memory round trip, not three in a row; the partials are summed whatever
+// the status (the pass before always writes them) and the status only decides
+// what is written.
 template <int MAXM>
 __device__ inline void finish_single_block(const FitDesc& d, const Work& w, int64_t G, const Finish& fz) {
-    constexpr int stride = nacc(MAXM);
     constexpr int rl = rec_len(MAXM);
-    __shared__ double sh[16][stride];
+    __shared__ double sums[nacc(MAXM)];
     __shared__ double sm[3 * MAXM + 2];
     __shared__ double rs[rl];
     const int pst = w.pstatus[0];
     const double rv = threadIdx.x < rl ? w.rec[threadIdx.x] : 0.0;
     auto body = [&]<int M>() {
         constexpr int K = nacc(M);
-        const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
-        double v[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = 0.0;
-#pragma unroll 4
-        for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k < nk) v[k] += w.part[(int64_t)k * G + g];
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-        if (lane_id() == 0) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) sh[wave_id_in_block()][k] = v[k];
-        }
+        dispatch_sum_count<M>(fz.mode, [&]<int NK>() { block_sum_partials<NK>(w.part, G, sums); });
         if (threadIdx.x < rl) rs[threadIdx.x] = rv;
         __syncthreads();
         if (wave_id_in_block() == 0) {
             if (pst != LSEFIT_OK) {
                 if (lane_id() == 0 && fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, 0, fz, pst);
             } else {
-                wave_column_sums<K, stride>(sh, blockDim.x / kWave, v);
+                const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
+                double v[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) v[k] = k < nk ? sums[k] : 0.0;
                 finish_fit_wave<M, MAXM>(d, w, 0, v, fz, sm, rs);
             }
         }
@@ -642,19 +687,8 @@ __device__ inline void finish_single_block(const FitDesc& d, const Work& w, int6
     dispatch_degree<MAXM>(d.degree, body);
 }
 
-// The finish block has one thread per block partial (a multiple of 64), at
-// most 512: the loop over a thread's partials does not overlap its loads, so
-// every further partial per thread costs a memory round trip, and up to 512
-// threads the solve keeps a budget of 256 registers.
-constexpr int kFinishMaxThreads = 512;
-
-__host__ __device__ inline int finish_threads(int64_t G) {
-    const int64_t t = (G + kWave - 1) / kWave * kWave;
-    return (int)(t < kWave ? kWave : (t > kFinishMaxThreads ? kFinishMaxThreads : t));
-}
-
 template <int MAXM>
-__global__ void __launch_bounds__(kFinishMaxThreads) k_finish_single(FitDesc d, Work w, int64_t G, Finish fz) {
+__global__ void __launch_bounds__(kFinishWaves * kWave) k_finish_single(FitDesc d, Work w, int64_t G, Finish fz) {
     const KernelClock kclock_(w.clock);
     finish_single_block<MAXM>(d, w, G, fz);
 }
@@ -854,17 +888,17 @@ __global__ void __launch_bounds__(256) k_combine_lane(FitDesc d, Work w, int64_t
     const int64_t w0 = wave_of_tile(ts, NT, W), w1 = wave_of_tile(te - 1, NT, W);
     auto body = [&]<int M>() {
         constexpr int K = nacc(M);
-        const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
         double v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = 0.0;
-        for (int64_t wv = w0; wv <= w1; ++wv) {
-            if (!wave_owns_tiles(wv, NT, W)) continue;
-            const double* p = w.part + (wv + f) * stride;
+        dispatch_sum_count<M>(fz.mode, [&]<int NK>() {
+            for (int64_t wv = w0; wv <= w1; ++wv) {
+                if (!wave_owns_tiles(wv, NT, W)) continue;
+                const double* p = w.part + (wv + f) * stride;
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k < nk) v[k] += p[k];
-        }
+                for (int k = 0; k < NK; ++k) v[k] += p[k];
+            }
+        });
         finish_fit<M, MAXM>(d, w, f, v, fz);
     };
     dispatch_degree<MAXM>(fit_deg(d, f), body);
@@ -1299,7 +1333,7 @@ hipError_t Launchers<MAXM>::combine(const FitDesc& d, const Work& w, const Launc
 
 template <int MAXM>
 hipError_t Launchers<MAXM>::finish_single(const FitDesc& d, const Work& w, int64_t G, const Finish& fz, hipStream_t st) {
-    launch_timed(k_finish_single<MAXM>, dim3(1), dim3(finish_threads(G)), st, d, w, G, fz);
+    launch_timed(k_finish_single<MAXM>, dim3(1), dim3(kFinishWaves * kWave), st, d, w, G, fz);
     return hipGetLastError();
 }
 

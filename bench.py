@@ -421,6 +421,20 @@ def timed_form(fn, steps, warmup):
     return ms, plain, kern
 
 
+def _both_forms(plan, fn, args):
+    """A tuned plan's step in both replay forms: graph replays (after the capture),
+    then eager launches (kernel clock armed, and a plain region).  Returns the
+    form the tuning kept (True: graph), the graph time, the armed and plain
+    eager times and the kernel times; the plan keeps its tuned form."""
+    graph = plan.graph
+    plan.set_graph(True)
+    graph_ms = _time(fn, args.steps, args.warmup)
+    plan.set_graph(False)
+    ms, plain, kern = timed_form(fn, args.steps, 2)
+    plan.set_graph(graph)
+    return graph, graph_ms, ms, plain, kern
+
+
 MALL_FLUSH_BYTES = 1 << 30   # > the 256 MB Infinity Cache
 
 
@@ -738,14 +752,15 @@ def bench_ragged(args, full=False):
         if not args.no_tune:
             plan.tune(x, y, off, dg, precision=prec, reps=3)
         step = lambda: lf.fit_batched(x, y, off, dg, 3, precision=prec, plan=plan, out=(coef, status))
-        graph_ms = _time(step, args.steps, args.warmup)          # graph replays (after the capture)
-        plan.set_graph(False)
-        ms, plain, kern = timed_form(step, args.steps, 2)         # eager launches, kernel clock armed
+        graph, graph_ms, ms, plain, kern = _both_forms(plan, step, args)
+        tuned_ms = graph_ms if graph else plain
         passes = 2 if prec == "f32c" else 1
         km = kern["moments"]["avg_ms"]
-        out[prec] = {"ms_per_step": _r(graph_ms), "eager_ms_per_step": _r(ms), "eager_plain_ms_per_step": _r(plain),
-                     "points_per_s": _r(P / (graph_ms * 1e-3)), "tuned_schedule": plan.schedule,
-                     "step_gbps": round(8.0 * P * passes / (graph_ms * 1e-3) / 1e9, 1),
+        out[prec] = {"ms_per_step": _r(tuned_ms), "replay_form": "graph" if graph else "eager",
+                     "graph_ms_per_step": _r(graph_ms), "eager_ms_per_step": _r(ms),
+                     "eager_plain_ms_per_step": _r(plain),
+                     "points_per_s": _r(P / (tuned_ms * 1e-3)), "tuned_schedule": plan.schedule,
+                     "step_gbps": round(8.0 * P * passes / (tuned_ms * 1e-3) / 1e9, 1),
                      "kernel": "k_moments", "kernel_ms": _r(km), "kernel_gbps": round(8.0 * P / (km * 1e-3) / 1e9, 1),
                      "kernels": kern, "all_ok": bool((status.cpu().numpy() == 0).all()),
                      "max_rel_coef_err": _batched_err(bf, coef.cpu().numpy(), ref)}
@@ -767,11 +782,11 @@ def bench_ragged(args, full=False):
         if not args.no_tune:
             cplan.tune(x, y, off, dg, reps=3, basis="chebyshev")
         cfn = lambda: lf.fit_batched(x, y, off, dg, 3, plan=cplan, out=(coef, status), basis="chebyshev")
-        cgraph_ms = _time(cfn, args.steps, args.warmup)
-        cplan.set_graph(False)
-        ms, plain, kern = timed_form(cfn, args.steps, 2)
-        out["chebyshev"] = {"ms_per_step": _r(cgraph_ms), "eager_ms_per_step": _r(ms),
-                            "points_per_s": _r(P / (cgraph_ms * 1e-3)), "tuned_schedule": cplan.schedule,
+        graph, cgraph_ms, ms, plain, kern = _both_forms(cplan, cfn, args)
+        tuned_ms = cgraph_ms if graph else plain
+        out["chebyshev"] = {"ms_per_step": _r(tuned_ms), "replay_form": "graph" if graph else "eager",
+                            "graph_ms_per_step": _r(cgraph_ms), "eager_ms_per_step": _r(ms),
+                            "points_per_s": _r(P / (tuned_ms * 1e-3)), "tuned_schedule": cplan.schedule,
                             "kernels": kern, "all_ok": bool((status.cpu().numpy() == 0).all()),
                             "kernel_gbps": round(8.0 * P / (kern["moments"]["avg_ms"] * 1e-3) / 1e9, 1)}
         cplan.close()
@@ -816,18 +831,17 @@ def bench_grad(args, full=False):
     vp = ctypes.c_void_p
     stream = vp(torch.cuda.current_stream(dev).cuda_stream)
     g = torch.empty(B, 3, dtype=torch.float64, device=dev)
+    neg2t = -2.0 * target
 
     def fwd_bwd():
         lf.fit_batched(x, y, off, dg, 2, plan=plan, out=(coef, status))
-        torch.sub(coef, target, out=g)
-        g.mul_(2.0)
+        torch.add(neg2t, coef, alpha=2.0, out=g)   # dL/da = 2 (a - target), one kernel
         _lib.check(L.fit_backward(vp(x.data_ptr()), vp(y.data_ptr()), vp(off.data_ptr()), vp(dg.data_ptr()), B,
                                   _lib.F32, ctypes.byref(o), plan.handle, None, 0, vp(g.data_ptr()), 3,
                                   vp(gx.data_ptr()), vp(gy.data_ptr()), stream), "fit_backward")
 
-    graph_ms = _time(fwd_bwd, args.steps, args.warmup)          # forward replayed from the plan's graph
-    plan.set_graph(False)
-    ms, plain, kern = timed_form(fwd_bwd, args.steps, 2)
+    graph, graph_ms, ms, plain, kern = _both_forms(plan, fwd_bwd, args)
+    tuned_ms = graph_ms if graph else plain
     torch.cuda.synchronize()
     rng = np.random.default_rng(4064)
     sample = np.sort(rng.choice(B, 64, replace=False))
@@ -840,9 +854,10 @@ def bench_grad(args, full=False):
     fwd_bytes, bwd_bytes = 8.0 * P, 16.0 * P
     out = {"workload": f"grad_batch: {B} fits x 4096 float32 points, m=2, loss sum ||a - a_target||^2, "
                        "forward + adjoint", "points": P,
-           "ms_per_step": _r(graph_ms), "eager_ms_per_step": _r(ms), "eager_plain_ms_per_step": _r(plain),
-           "points_per_s": _r(P / (graph_ms * 1e-3)), "tuned_schedule": plan.schedule,
-           "step_gbps": round((fwd_bytes + bwd_bytes) / (graph_ms * 1e-3) / 1e9, 1), "kernels": kern,
+           "ms_per_step": _r(tuned_ms), "replay_form": "graph" if graph else "eager",
+           "graph_ms_per_step": _r(graph_ms), "eager_ms_per_step": _r(ms), "eager_plain_ms_per_step": _r(plain),
+           "points_per_s": _r(P / (tuned_ms * 1e-3)), "tuned_schedule": plan.schedule,
+           "step_gbps": round((fwd_bytes + bwd_bytes) / (tuned_ms * 1e-3) / 1e9, 1), "kernels": kern,
            "moments_gbps": round(fwd_bytes / (kern["moments"]["avg_ms"] * 1e-3) / 1e9, 1),
            "adjoint_gbps": round(bwd_bytes / (kern["adjoint"]["avg_ms"] * 1e-3) / 1e9, 1),
            "all_ok": bool((status.cpu().numpy() == 0).all()),

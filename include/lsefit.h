@@ -299,8 +299,9 @@ lsefit_status fit_qr_batched(const void* x, const void* y, const int64_t* offset
  *  status:    output, device int32 [B]
  *  plan:      NULL -> the default schedule and the caller's workspace `ws`;
  *             otherwise the plan's tuned schedule and its own workspace (ws
- *             and ws_bytes ignored) and, after the first call with the same
- *             arguments, one replay of a captured HIP graph.
+ *             and ws_bytes ignored) and, in the graph form (see
+ *             fit_plan_tune), after the first call with the same arguments,
+ *             one replay of a captured HIP graph.
  * All fits run in one launch of the persistent streaming kernel (plus a tile
  * table kernel before it and one solve kernel after it). */
 lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
@@ -354,7 +355,11 @@ lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets
  * the plan's workspace (device memory, freed by fit_plan_destroy) for up to
  * `batch` fits of degree <= max_degree.  fit_plan_tune times candidate
  * schedules on the given data (it synchronises `stream`) and keeps the
- * fastest; fit_plan_set_schedule installs a known one (for example from a
+ * fastest; it then times that schedule as eager launches and as replays of a
+ * captured graph on the same call and keeps the faster form, unless
+ * fit_plan_set_graph chose one (enable 1: replay a captured graph, 0: launch
+ * eagerly; a new plan replays graphs).  fit_plan_get_graph reports the form in
+ * use.  fit_plan_set_schedule installs a known schedule (for example from a
  * cache).  A plan must be used from one stream at a time. */
 lsefit_status fit_plan_create(lsefit_plan** plan, int64_t batch, int32_t max_degree, int32_t dt,
                               int32_t precision);
@@ -366,10 +371,11 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
  * many processes).  With a path set, fit_plan_tune first looks the call's
  * shape up in that text file: the key is the device (architecture, compute
  * units), dtype, options, batch and the total points rounded down to a power
- * of two.  On a hit it installs the cached schedule, runs the fit once with
- * it (coef and status are written as by a tuning run), writes the cached time
- * to best_ms_out and times nothing; on a miss it tunes as usual and appends
- * the result as one line.  Appends within a process are serialised; a file
+ * of two.  On a hit it installs the cached schedule and the cached form (when
+ * the line records one and the caller did not set one), runs the fit once
+ * with it (coef and status are written as by a tuning run), writes the cached
+ * time to best_ms_out and times nothing; on a miss it tunes as usual and
+ * appends the result as one line.  Appends within a process are serialised; a file
  * that cannot be read is treated as empty and one that cannot be written is
  * left alone (the tuned schedule is still installed).  path NULL or "" turns
  * the cache off.  The string is copied. */
@@ -377,6 +383,7 @@ lsefit_status fit_plan_set_tune_cache(lsefit_plan* plan, const char* path);
 lsefit_status fit_plan_set_schedule(lsefit_plan* plan, const lsefit_schedule* schedule);
 lsefit_status fit_plan_get_schedule(const lsefit_plan* plan, lsefit_schedule* out);
 lsefit_status fit_plan_set_graph(lsefit_plan* plan, int32_t enable);
+lsefit_status fit_plan_get_graph(const lsefit_plan* plan, int32_t* enabled);
 void fit_plan_destroy(lsefit_plan* plan);
 
 /* A short description of a status code: any lsefit_status value, and

@@ -29,7 +29,7 @@ EXPORTS = (
     "fit_moments", "fit_solve", "fit_single", "fit_single_noalloc", "fit_qr", "fit_qr_batched", "fit_batched", "fit_backward",
     "fit_residuals",
     "fit_plan_create", "fit_plan_tune", "fit_plan_set_tune_cache", "fit_plan_set_schedule", "fit_plan_get_schedule",
-    "fit_plan_set_graph", "fit_plan_destroy", "lsefit_status_string", "lsefit_device_cus",
+    "fit_plan_set_graph", "fit_plan_get_graph", "fit_plan_destroy", "lsefit_status_string", "lsefit_device_cus",
     "lsefit_timing_enable", "lsefit_timing_reset", "lsefit_timing_read", "lsefit_read_probe", "lsefit_copy_probe",
 )
 
@@ -89,6 +89,7 @@ def load():
     L.fit_plan_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
     L.fit_plan_get_schedule.argtypes = [vp, SchP]
     L.fit_plan_set_graph.argtypes = [vp, i32]
+    L.fit_plan_get_graph.argtypes = [vp, ctypes.POINTER(i32)]
     L.fit_plan_destroy.argtypes = [vp]
     L.fit_plan_destroy.restype = None
     L.lsefit_status_string.argtypes = [i32]
@@ -103,7 +104,7 @@ def load():
                  "fit_qr", "fit_qr_batched", "fit_residuals",
                  "fit_batched", "fit_backward", "fit_plan_create", "fit_plan_tune", "fit_plan_set_tune_cache",
                  "fit_plan_set_schedule",
-                 "fit_plan_get_schedule", "fit_plan_set_graph", "lsefit_timing_enable", "lsefit_timing_reset",
+                 "fit_plan_get_schedule", "fit_plan_set_graph", "fit_plan_get_graph", "lsefit_timing_enable", "lsefit_timing_reset",
                  "lsefit_timing_read", "lsefit_read_probe", "lsefit_copy_probe"):
         getattr(L, name).restype = i32
     _lib = L

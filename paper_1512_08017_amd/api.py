@@ -324,7 +324,15 @@ class Plan:
         check(self._L.fit_plan_set_schedule(self.handle, ctypes.byref(s)), "fit_plan_set_schedule")
 
     def set_graph(self, enable: bool):
+        """Replay a captured graph (True) or launch eagerly (False); tune() then keeps this form."""
         check(self._L.fit_plan_set_graph(self.handle, 1 if enable else 0), "fit_plan_set_graph")
+
+    @property
+    def graph(self) -> bool:
+        """Whether calls replay a captured graph (tune() picks the faster form unless set_graph chose)."""
+        e = ctypes.c_int32(0)
+        check(self._L.fit_plan_get_graph(self.handle, ctypes.byref(e)), "fit_plan_get_graph")
+        return bool(e.value)
 
     def set_tune_cache(self, path):
         """Schedule cache file of tune() (None turns it off); see fit_plan_set_tune_cache."""

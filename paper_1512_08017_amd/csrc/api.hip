@@ -377,6 +377,7 @@ struct lsefit_plan {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     bool graph_enabled = true;
+    bool graph_user = false;   // the form was set by fit_plan_set_graph: tuning keeps it
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
     struct Key {
@@ -664,28 +665,15 @@ lsefit_status fit_qr_batched(const void* x, const void* y, const int64_t* offset
     return LSEFIT_OK;
 }
 
-lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
-                          int64_t batch, int32_t dt, const lsefit_options* opt, lsefit_plan* plan, void* ws,
-                          size_t ws_bytes, double* coef, int32_t coef_stride, int32_t* status, void* stream) {
-    if (batch < 0 || !opts_ok(opt, dt, true)) return LSEFIT_ERR_INVALID_ARG;
-    if (batch == 0) return LSEFIT_OK;
-    if (!x || !y || !offsets || !degrees || !coef || !status) return LSEFIT_ERR_INVALID_ARG;
-    if (!stride_ok(opt, coef_stride)) return LSEFIT_ERR_INVALID_ARG;
-    if (unsupported(opt, dt)) return LSEFIT_ERR_UNSUPPORTED;
-    hipStream_t st = (hipStream_t)stream;
-    const FitDesc d{offsets, degrees, 0, batch, opt->degree};
-    if (!plan) {
-        const lsefit_schedule sched = current_default();
-        const Layout lay = layout(batch, opt->degree, to_launch(sched).waves);
-        if (!ws || ws_bytes < lay.total) return LSEFIT_ERR_WORKSPACE;
-        return enqueue_batched(d, carve(ws, lay), opt, dt, x, y, coef, coef_stride, status, sched, st);
-    }
-    if (batch > plan->batch || opt->degree > plan->max_degree || dt != plan->dtype) return LSEFIT_ERR_INVALID_ARG;
-    const Layout lay = layout(plan->batch, plan->max_degree, plan->max_waves);
-    const Work w = carve(plan->ws, lay);
-    if (!plan->graph_enabled)
-        return enqueue_batched(d, w, opt, dt, x, y, coef, coef_stride, status, plan->sched, st);
-    lsefit_plan::Key key{x, y, offsets, degrees, batch, (int32_t)dt, *opt, coef, coef_stride, status};
+extern "C++" {
+namespace {
+
+// One call of a plan through its captured graph: capture (on the plan's own
+// stream) when the arguments differ from the captured call's, then replay.
+lsefit_status plan_graph_call(lsefit_plan* plan, const FitDesc& d, const Work& w, const lsefit_options* opt,
+                              int32_t dt, const void* x, const void* y, double* coef, int32_t coef_stride,
+                              int32_t* status, hipStream_t st) {
+    lsefit_plan::Key key{x, y, d.offsets, d.degrees, d.batch, dt, *opt, coef, coef_stride, status};
     if (!(plan->exec && plan->have_key && same_key(plan->key, key))) {
         plan->drop_graph();
         if (!plan->cap_stream) LSEFIT_TRY(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
@@ -709,6 +697,78 @@ lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, 
     }
     LSEFIT_TRY(hipGraphLaunch(plan->exec, st));
     return LSEFIT_OK;
+}
+
+// Time `reps` calls of fn (each returning an lsefit_status) on stream st, after
+// one untimed call: milliseconds per call.
+template <class F>
+lsefit_status time_calls(hipStream_t st, int reps, F&& fn, double* ms_per_call) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return LSEFIT_ERR_DEVICE;
+    }
+    lsefit_status r = fn();
+    if (r == LSEFIT_OK && hipEventRecord(e0, st) != hipSuccess) r = LSEFIT_ERR_DEVICE;
+    for (int i = 0; i < reps && r == LSEFIT_OK; ++i) r = fn();
+    float ms = 0.f;
+    if (r == LSEFIT_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        r = LSEFIT_ERR_DEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r == LSEFIT_OK) *ms_per_call = (double)ms / reps;
+    return r;
+}
+
+// The replay form of a tuned plan: eager launches of its schedule against
+// replays of the captured graph, timed on the same call; the faster is kept
+// (*graph_out = 1 for the graph).  A form set with fit_plan_set_graph is kept.
+lsefit_status choose_replay_form(lsefit_plan* plan, const FitDesc& d, const Work& w, const lsefit_options* opt,
+                                 const void* x, const void* y, double* coef, int32_t coef_stride, int32_t* status,
+                                 hipStream_t st, int reps, int* graph_out) {
+    *graph_out = -1;
+    if (plan->graph_user) return LSEFIT_OK;
+    const int32_t dt = plan->dtype;
+    double te = 0.0, tg = 0.0;
+    lsefit_status r = time_calls(st, reps, [&] {
+        return enqueue_batched(d, w, opt, dt, x, y, coef, coef_stride, status, plan->sched, st);
+    }, &te);
+    if (r != LSEFIT_OK) return r;
+    r = time_calls(st, reps, [&] { return plan_graph_call(plan, d, w, opt, dt, x, y, coef, coef_stride, status, st); },
+                   &tg);
+    if (r != LSEFIT_OK) return r;
+    plan->graph_enabled = tg < te;
+    if (!plan->graph_enabled) plan->drop_graph();
+    *graph_out = plan->graph_enabled ? 1 : 0;
+    return LSEFIT_OK;
+}
+
+}  // namespace
+}  // extern "C++"
+
+lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
+                          int64_t batch, int32_t dt, const lsefit_options* opt, lsefit_plan* plan, void* ws,
+                          size_t ws_bytes, double* coef, int32_t coef_stride, int32_t* status, void* stream) {
+    if (batch < 0 || !opts_ok(opt, dt, true)) return LSEFIT_ERR_INVALID_ARG;
+    if (batch == 0) return LSEFIT_OK;
+    if (!x || !y || !offsets || !degrees || !coef || !status) return LSEFIT_ERR_INVALID_ARG;
+    if (!stride_ok(opt, coef_stride)) return LSEFIT_ERR_INVALID_ARG;
+    if (unsupported(opt, dt)) return LSEFIT_ERR_UNSUPPORTED;
+    hipStream_t st = (hipStream_t)stream;
+    const FitDesc d{offsets, degrees, 0, batch, opt->degree};
+    if (!plan) {
+        const lsefit_schedule sched = current_default();
+        const Layout lay = layout(batch, opt->degree, to_launch(sched).waves);
+        if (!ws || ws_bytes < lay.total) return LSEFIT_ERR_WORKSPACE;
+        return enqueue_batched(d, carve(ws, lay), opt, dt, x, y, coef, coef_stride, status, sched, st);
+    }
+    if (batch > plan->batch || opt->degree > plan->max_degree || dt != plan->dtype) return LSEFIT_ERR_INVALID_ARG;
+    const Layout lay = layout(plan->batch, plan->max_degree, plan->max_waves);
+    const Work w = carve(plan->ws, lay);
+    if (!plan->graph_enabled)
+        return enqueue_batched(d, w, opt, dt, x, y, coef, coef_stride, status, plan->sched, st);
+    return plan_graph_call(plan, d, w, opt, dt, x, y, coef, coef_stride, status, st);
 }
 
 lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
@@ -850,7 +910,14 @@ lsefit_status fit_plan_get_schedule(const lsefit_plan* plan, lsefit_schedule* ou
 lsefit_status fit_plan_set_graph(lsefit_plan* plan, int32_t enable) {
     if (!plan) return LSEFIT_ERR_INVALID_ARG;
     plan->graph_enabled = enable != 0;
+    plan->graph_user = true;
     plan->drop_graph();
+    return LSEFIT_OK;
+}
+
+lsefit_status fit_plan_get_graph(const lsefit_plan* plan, int32_t* enabled) {
+    if (!plan || !enabled) return LSEFIT_ERR_INVALID_ARG;
+    *enabled = plan->graph_enabled ? 1 : 0;
     return LSEFIT_OK;
 }
 
@@ -875,14 +942,17 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
         key = tune_key(opt, plan->dtype, batch, ends[1] - ends[0]);
         lsefit_schedule cs{};
         double cms = 0.0;
-        if (tune_cache::lookup(plan->tune_cache, key, &cs, &cms) && schedule_ok(cs) &&
+        int cgraph = -1;
+        if (tune_cache::lookup(plan->tune_cache, key, &cs, &cms, &cgraph) && schedule_ok(cs) &&
             to_launch(cs).waves <= plan->max_waves) {
-            // a cached shape: one run with its schedule, no timing
+            // a cached shape: one run with its schedule, no timing; the cached
+            // replay form unless the caller set one
             const lsefit_status r = enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, cs, st);
             if (r != LSEFIT_OK) return r;
             if (hipStreamSynchronize(st) != hipSuccess) return LSEFIT_ERR_DEVICE;
             plan->sched = cs;
             plan->drop_graph();
+            if (cgraph >= 0 && !plan->graph_user) plan->graph_enabled = cgraph == 1;
             if (best_ms_out) *best_ms_out = cms;
             return LSEFIT_OK;
         }
@@ -897,42 +967,27 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
                     lsefit_schedule s{cus * wpc, wpb, tile, unroll};
                     if (to_launch(s).waves <= plan->max_waves) cands.push_back(s);
                 }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        if (e0) hipEventDestroy(e0);
-        return LSEFIT_ERR_DEVICE;
-    }
     double best = 1e300;
     lsefit_schedule best_s = plan->sched;
     lsefit_status r = LSEFIT_OK;
     for (const auto& s : cands) {
-        // one untimed run, then the timed ones
-        r = enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, s, st);
-        if (r != LSEFIT_OK) break;
-        if (hipEventRecord(e0, st) != hipSuccess) {
-            r = LSEFIT_ERR_DEVICE;
-            break;
-        }
-        for (int i = 0; i < reps && r == LSEFIT_OK; ++i)
-            r = enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, s, st);
-        float ms = 0.f;
-        if (r == LSEFIT_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            r = LSEFIT_ERR_DEVICE;
-        if (r != LSEFIT_OK) break;
-        const double per = ms / reps;
+        double per = 0.0;
+        r = time_calls(st, reps, [&] {
+            return enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, s, st);
+        }, &per);
+        if (r != LSEFIT_OK) return r;
         if (per < best) {
             best = per;
             best_s = s;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    if (r != LSEFIT_OK) return r;
     plan->sched = best_s;
     plan->drop_graph();
+    int form = -1;
+    r = choose_replay_form(plan, d, w, opt, x, y, coef, coef_stride, status, st, reps, &form);
+    if (r != LSEFIT_OK) return r;
     if (best_ms_out) *best_ms_out = best;
-    if (!key.empty()) tune_cache::store(plan->tune_cache, key, best_s, best);
+    if (!key.empty()) tune_cache::store(plan->tune_cache, key, best_s, best, form);
     return LSEFIT_OK;
 }
 

@@ -16,18 +16,41 @@ namespace lsefit {
 // scans the tile counts of its block.  Pass B adds the tile totals of the
 // blocks before it and stores the number of tiles and the tile size after the
 // last fit's entry.  Integer sums: the result does not depend on the order.
+//
+// A batch of at most kPlanFusedBlocks blocks with a power-of-two tile takes
+// one launch (FUSED): every block also counts the tiles of all the fits before
+// its own (at most kPlanFusedBlocks - 1 per thread, a shift each, loaded
+// together with its own fits' data) and writes the final table itself.
 // ---------------------------------------------------------------------------
 constexpr int kRangeBatchSamples = 16;
+constexpr int kPlanFusedBlocks = 32;
 
-template <typename In>
+template <typename In, bool FUSED>
 __global__ void __launch_bounds__(kPlanThreads)
     k_plan_count(FitDesc d, Work w, int maxM, int64_t tile, int range_given, double c, double s,
-                 const In* __restrict__ x, int64_t* __restrict__ block_tot) {
+                 const In* __restrict__ x, int64_t* __restrict__ block_tot, int tile_shift) {
     const KernelClock kclock_(w.clock);
     __shared__ int64_t sh[kPlanThreads];
+    __shared__ int64_t sp[FUSED ? kPlanThreads : 1];
     const int tid = threadIdx.x;
     const int64_t f = (int64_t)blockIdx.x * kPlanThreads + tid;
     const int rl = rec_len(maxM);
+    // FUSED: the tiles of fits tid, tid + 256, ... below this block's first fit;
+    // a thread past the end reads the last such fit again and drops it
+    int64_t prev = 0;
+    if constexpr (FUSED) {
+        const int64_t nprev = (int64_t)blockIdx.x * kPlanThreads;
+        if (nprev > 0) {
+#pragma unroll
+            for (int i = 0; i < kPlanFusedBlocks - 1; ++i) {
+                const int64_t j = tid + (int64_t)i * kPlanThreads;
+                const int64_t jc = j < nprev ? j : nprev - 1;
+                const int64_t L = fit_hi(d, jc) - fit_lo(d, jc);
+                const int64_t t = L <= 0 ? 0 : (L + tile - 1) >> tile_shift;
+                prev += j < nprev ? t : 0;
+            }
+        }
+    }
     int64_t tiles = 0;
     if (f < d.batch) {
         const int64_t lo = fit_lo(d, f);
@@ -68,15 +91,28 @@ __global__ void __launch_bounds__(kPlanThreads)
         w.rec[f * rl + 1] = ss;
     }
     sh[tid] = tiles;
+    if constexpr (FUSED) sp[tid] = prev;
     __syncthreads();
     for (int off = 1; off < kPlanThreads; off <<= 1) {
         const int64_t v = tid >= off ? sh[tid - off] : 0;
+        int64_t vp = 0;
+        if constexpr (FUSED) vp = tid >= off ? sp[tid - off] : 0;
         __syncthreads();
         sh[tid] += v;
+        if constexpr (FUSED) sp[tid] += vp;
         __syncthreads();
     }
-    if (f < d.batch) w.tile_start[f] = sh[tid] - tiles;
-    if (tid == kPlanThreads - 1) block_tot[blockIdx.x] = sh[tid];
+    if constexpr (FUSED) {
+        const int64_t base = sp[kPlanThreads - 1];
+        if (f < d.batch) w.tile_start[f] = base + sh[tid] - tiles;
+        if (blockIdx.x == gridDim.x - 1 && tid == kPlanThreads - 1) {
+            w.tile_start[d.batch] = base + sh[tid];
+            w.tile_start[d.batch + 1] = tile;   // the table's own tile size, for every later pass over it
+        }
+    } else {
+        if (f < d.batch) w.tile_start[f] = sh[tid] - tiles;
+        if (tid == kPlanThreads - 1) block_tot[blockIdx.x] = sh[tid];
+    }
 }
 
 __global__ void __launch_bounds__(kPlanThreads)
@@ -265,12 +301,24 @@ int64_t plan_blocks(int64_t batch) { return (batch + kPlanThreads - 1) / kPlanTh
 hipError_t launch_plan(const FitDesc& d, const Work& w, int maxM, int64_t tile, bool range_given, double c,
                        double s, int dtype, const void* x, int64_t* block_tot, hipStream_t st) {
     const int64_t nb = plan_blocks(d.batch);
+    const int rg = range_given ? 1 : 0;
+    int shift = 0;
+    while (shift < 62 && (int64_t(1) << shift) < tile) ++shift;
+    if (nb <= kPlanFusedBlocks && (int64_t(1) << shift) == tile) {
+        if (dtype == LSEFIT_F32)
+            hipLaunchKernelGGL((k_plan_count<float, true>), dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile,
+                               rg, c, s, (const float*)x, block_tot, shift);
+        else
+            hipLaunchKernelGGL((k_plan_count<double, true>), dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile,
+                               rg, c, s, (const double*)x, block_tot, shift);
+        return hipGetLastError();
+    }
     if (dtype == LSEFIT_F32)
-        hipLaunchKernelGGL(k_plan_count<float>, dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile,
-                           range_given ? 1 : 0, c, s, (const float*)x, block_tot);
+        hipLaunchKernelGGL((k_plan_count<float, false>), dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile, rg,
+                           c, s, (const float*)x, block_tot, 0);
     else
-        hipLaunchKernelGGL(k_plan_count<double>, dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile,
-                           range_given ? 1 : 0, c, s, (const double*)x, block_tot);
+        hipLaunchKernelGGL((k_plan_count<double, false>), dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile, rg,
+                           c, s, (const double*)x, block_tot, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_plan_offsets, dim3(nb), dim3(kPlanThreads), 0, st, d, w, block_tot, nb, tile);

@@ -79,7 +79,8 @@ struct RangeArg {
 constexpr int kRangeFromRecord = 2;
 
 // Batched: tile table, plan status and (c, s) of every fit (given, or from a
-// sample of the fit's x), in two launches; block_tot holds plan_blocks(B) int64.
+// sample of the fit's x), in two launches (one for at most 32 blocks of fits and
+// a power-of-two tile); block_tot holds plan_blocks(B) int64.
 int64_t plan_blocks(int64_t batch);
 hipError_t launch_plan(const FitDesc& d, const Work& w, int maxM, int64_t tile, bool range_given, double c,
                        double s, int dtype, const void* x, int64_t* block_tot, hipStream_t st);

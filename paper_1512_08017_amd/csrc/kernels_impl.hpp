@@ -363,9 +363,11 @@ __device__ inline void dispatch_sum_count(int mode, Body&& body) {
     else body.template operator()<nacc(M)>();
 }
 
+// n: the fit's number of points; (c, s): its range from the record (loaded by
+// the caller with its other loads, so that they share one memory round trip)
 template <int M, int MAXM>
 __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, const double (&v)[nacc(M)],
-                                  const Finish& fz) {
+                                  const Finish& fz, int64_t n, double c, double s) {
     constexpr int N = M + 1;
     constexpr int rl = rec_len(MAXM);
     if (fz.mode == kSSE) {
@@ -373,7 +375,6 @@ __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, co
         return;
     }
     double* r = w.rec + f * rl;
-    const double c = r[0], s = r[1];
     double* a_out = fz.coef + f * (int64_t)fz.coef_stride;
     double S[2 * M + 1];
     double b[1][N], a[N];
@@ -388,7 +389,7 @@ __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, co
 #pragma unroll
         for (int j = 0; j < N; ++j) b[0][j] = r[rec_b(MAXM) + j] + delta[0][j];
     } else {
-        S[0] = (double)(fit_hi(d, f) - fit_lo(d, f));
+        S[0] = (double)n;
 #pragma unroll
         for (int k = 1; k <= 2 * M; ++k) S[k] = v[k - 1];
         double T[1][N];
@@ -877,14 +878,20 @@ __global__ void __launch_bounds__(256) k_combine_lane(FitDesc d, Work w, int64_t
     const KernelClock kclock_(w.clock);
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.batch) return;
+    constexpr int stride = nacc(MAXM);
+    constexpr int rl = rec_len(MAXM);
+    // the loads that depend on no other, issued together: status, degree, tile
+    // range, point count and the range from the record
     const int pst = w.pstatus[f];
+    const int deg = fit_deg(d, f);
+    const int64_t NT = w.tile_start[d.batch];
+    const int64_t ts = w.tile_start[f], te = w.tile_start[f + 1];
+    const int64_t n = fit_hi(d, f) - fit_lo(d, f);
+    const double c = w.rec[f * rl], s = w.rec[f * rl + 1];
     if (pst != LSEFIT_OK) {
         if (fz.mode != kMomentsOnly) fail_fit<MAXM>(d, w, f, fz, pst);
         return;
     }
-    constexpr int stride = nacc(MAXM);
-    const int64_t NT = w.tile_start[d.batch];
-    const int64_t ts = w.tile_start[f], te = w.tile_start[f + 1];
     const int64_t w0 = wave_of_tile(ts, NT, W), w1 = wave_of_tile(te - 1, NT, W);
     auto body = [&]<int M>() {
         constexpr int K = nacc(M);
@@ -899,9 +906,9 @@ __global__ void __launch_bounds__(256) k_combine_lane(FitDesc d, Work w, int64_t
                 for (int k = 0; k < NK; ++k) v[k] += p[k];
             }
         });
-        finish_fit<M, MAXM>(d, w, f, v, fz);
+        finish_fit<M, MAXM>(d, w, f, v, fz, n, c, s);
     };
-    dispatch_degree<MAXM>(fit_deg(d, f), body);
+    dispatch_degree<MAXM>(deg, body);
 }
 
 constexpr int kCombineThreads = 256;
@@ -962,22 +969,33 @@ __global__ void __launch_bounds__(256)
     const KernelClock kclock_(w.clock);
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.batch) return;
-    if (w.pstatus[f] != LSEFIT_OK) return;
     constexpr int rl = rec_len(MAXM);
     double* r = w.rec + f * rl;
+    // every load at once, one memory round trip: status, degree, range, and the
+    // power sums and dL/da at the largest degree's size (the record holds
+    // 2 MAXM + 1 sums and coef_stride >= MAXM + 1; a lower degree uses the first)
+    const int pst = w.pstatus[f];
+    const int deg = fit_deg(d, f);
+    const double c = r[0], s = r[1];
+    double gall[MAXM + 1], Sall[2 * MAXM + 1];
+#pragma unroll
+    for (int k = 0; k <= MAXM; ++k) gall[k] = gcoef[f * (int64_t)coef_stride + k];
+#pragma unroll
+    for (int k = 0; k <= 2 * MAXM; ++k) Sall[k] = r[rec_S(MAXM) + k];
+    if (pst != LSEFIT_OK) return;
     auto body = [&]<int M>() {
         constexpr int N = M + 1;
         double g[N], gt[1][N], lam[1][N], S[2 * M + 1];
 #pragma unroll
-        for (int k = 0; k < N; ++k) g[k] = gcoef[f * (int64_t)coef_stride + k];
-        to_t_basis_adjoint<N>(g, r[0], r[1], gt[0]);
+        for (int k = 0; k < N; ++k) g[k] = gall[k];
+        to_t_basis_adjoint<N>(g, c, s, gt[0]);
 #pragma unroll
-        for (int k = 0; k <= 2 * M; ++k) S[k] = r[rec_S(MAXM) + k];
+        for (int k = 0; k <= 2 * M; ++k) S[k] = Sall[k];
         const int st = normal_solve<N, 1>(solver, S, gt, lam);
 #pragma unroll
         for (int k = 0; k < N; ++k) r[rec_lam(MAXM) + k] = st == LSEFIT_OK ? lam[0][k] : NAN;
     };
-    dispatch_degree<MAXM>(fit_deg(d, f), body);
+    dispatch_degree<MAXM>(deg, body);
 }
 
 template <int M, typename In>

@@ -63,6 +63,21 @@ int main(int argc, char** argv) {
     CHECK(s.waves == 1024 && s.waves_per_block == 2 && s.tile == 2048 && s.unroll == 1 && ms == 0.125);
     CHECK(tune_cache::lookup(path, ka, &s, &ms));
     CHECK(s.waves == 4096 && s.unroll == 2 && ms == 0.5);
+    // the replay form: absent on a line of five fields, 0 or 1 when stored,
+    // and absent again when the sixth field is not 0 or 1
+    int graph = 7;
+    CHECK(tune_cache::lookup(path, ka, &s, &ms, &graph) && graph == -1);
+    tune_cache::store(path, ka, lsefit_schedule{2048, 4, 2048, 4}, 0.25, 0);
+    CHECK(tune_cache::lookup(path, ka, &s, &ms, &graph) && graph == 0 && s.unroll == 4 && ms == 0.25);
+    tune_cache::store(path, ka, lsefit_schedule{2048, 4, 256, 1}, 0.375, 1);
+    CHECK(tune_cache::lookup(path, ka, &s, &ms, &graph) && graph == 1 && s.tile == 256 && ms == 0.375);
+    tune_cache::store(path, kb, lsefit_schedule{512, 1, 64, 1}, 2.0, 5);   // not a form: not written
+    CHECK(tune_cache::lookup(path, kb, &s, &ms, &graph) && graph == -1 && s.waves == 512);
+    f = std::fopen(path.c_str(), "a");
+    if (!f) return 2;
+    std::fprintf(f, "%s\t1024 2 2048 2 0.125 3\n", kb.c_str());
+    std::fclose(f);
+    CHECK(tune_cache::lookup(path, kb, &s, &ms, &graph) && graph == -1 && s.waves == 1024);
     // a path that cannot be written is left alone
     tune_cache::store(std::string(argv[1]) + "/no/such/dir/cache.txt", ka, s, 1.0);
 

@@ -140,6 +140,8 @@ def test_null_pointers_rejected():
                            FAKE, 1 << 30, FAKE, None, None) == _lib.INVALID_ARG   # n < m + 1
     h = ctypes.c_void_p()
     assert L.fit_plan_create(ctypes.byref(h), 10, 17, _lib.F32, 0) == _lib.INVALID_ARG
+    assert L.fit_plan_set_graph(None, 1) == _lib.INVALID_ARG
+    assert L.fit_plan_get_graph(None, ctypes.byref(ctypes.c_int32())) == _lib.INVALID_ARG
     L.fit_plan_destroy(None)
 
 

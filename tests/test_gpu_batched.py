@@ -106,8 +106,9 @@ def test_plan_graph_replays_match_eager():
     off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
     eager, est, _ = lf.fit_batched(x, y, off, dg, 3)
     plan = lf.Plan(bf.batch, 3)
+    plan.set_graph(True)           # a form set by the caller survives tuning
     best = plan.tune(x, y, off, dg, reps=1)
-    assert best > 0
+    assert best > 0 and plan.graph
     coef = torch.zeros_like(eager)
     status = torch.zeros_like(est)
     outs = []
@@ -140,16 +141,23 @@ def test_plan_tune_cache(tmp_path):
     assert len(lines) == 1
     key, vals = lines[0].split("\t")
     assert f"B={bf.batch} " in key and " m=3 " in key
-    w, wpb, tile, unroll, ms = vals.split()
+    w, wpb, tile, unroll, ms, form = vals.split()
     assert p1.schedule == {"waves": int(w), "waves_per_block": int(wpb), "tile": int(tile), "unroll": int(unroll)}
     assert float(ms) == pytest.approx(ms1, rel=1e-5)
-    # a hit installs the cached schedule without timing or appending
+    assert form in ("0", "1") and p1.graph == (form == "1")   # the replay form the tuning kept
+    # a hit installs the cached schedule and form without timing or appending
     p2 = lf.Plan(bf.batch, 3)
+    p2.set_graph(form == "0")
     p2.set_tune_cache(str(cache))
+    p2b = lf.Plan(bf.batch, 3)
+    p2b.set_tune_cache(str(cache))
     assert p2.tune(x, y, off, dg, reps=1) == pytest.approx(ms1, rel=1e-5)
-    assert p2.schedule == p1.schedule
+    assert p2b.tune(x, y, off, dg, reps=1) == pytest.approx(ms1, rel=1e-5)
+    assert p2.schedule == p1.schedule and p2b.schedule == p1.schedule
+    assert p2b.graph == p1.graph and p2.graph != p1.graph   # a form the caller set is kept
     assert len(cache.read_text().splitlines()) == 1
-    # the last line of a key wins; the plan then fits with that schedule
+    # the last line of a key wins (a line of five fields leaves the form as it
+    # is); the plan then fits with that schedule
     cus = lf.device_cus()
     with open(cache, "a") as fh:
         fh.write(f"{key}\t{cus * 4} 2 256 1 0.5\n")
@@ -157,6 +165,7 @@ def test_plan_tune_cache(tmp_path):
     p3.set_tune_cache(str(cache))
     assert p3.tune(x, y, off, dg, reps=1) == 0.5
     assert p3.schedule == {"waves": cus * 4, "waves_per_block": 2, "tile": 256, "unroll": 1}
+    assert p3.graph                                          # a new plan's form
     coef, status = run_batched(bf, 3, plan=p3)
     check_against_oracle(bf, coef, status, 1e-9)
     # another shape misses the cache and adds its own line
@@ -165,8 +174,46 @@ def test_plan_tune_cache(tmp_path):
     p4.tune(x, y, off[:-1].contiguous(), dg[:-1].contiguous(), reps=1)
     assert len(cache.read_text().splitlines()) == 3
     p4.set_tune_cache(None)
-    for p in (p1, p2, p3, p4):
+    for p in (p1, p2, p2b, p3, p4):
         p.close()
+
+
+@pytest.mark.parametrize("chosen", [None, False, True])
+def test_tuned_replay_form(chosen):
+    """tune() keeps the faster of eager launches and graph replays unless the
+    caller chose a form; either form gives the same bits as eager calls with
+    the tuned schedule, call after call."""
+    announce(f"tuned replay form (caller's choice {chosen})")
+    rng = np.random.default_rng(21)
+    L = W.ragged_lengths(3000, 16, 8_000, rng)
+    deg = rng.integers(1, 4, 3000)
+    bf = W.random_batch(L, deg, seed=22, lo=-5.0, hi=5.0)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    plan = lf.Plan(bf.batch, 3)
+    if chosen is not None:
+        plan.set_graph(chosen)
+    plan.tune(x, y, off, dg, reps=2)
+    if chosen is not None:
+        assert plan.graph == chosen
+    announce(f"  form: {'graph' if plan.graph else 'eager'}, schedule {plan.schedule}")
+    ref = lf.Plan(bf.batch, 3)
+    ref.set_schedule(plan.schedule)
+    ref.set_graph(False)
+    want, wst = run_batched(bf, 3, plan=ref)
+    coef = torch.zeros(bf.batch, 4, dtype=torch.float64, device=x.device)
+    status = torch.zeros(bf.batch, dtype=torch.int32, device=x.device)
+    for _ in range(3):
+        coef.zero_()                # entries past a fit's degree stay as they are
+        status.fill_(-1)
+        lf.fit_batched(x, y, off, dg, 3, plan=plan, out=(coef, status))
+        torch.cuda.synchronize()
+        assert np.array_equal(coef.cpu().numpy(), want, equal_nan=True)
+        assert np.array_equal(status.cpu().numpy(), wst)
+        _ = (x * 2).sum().item()    # eager work between calls
+    check_against_oracle(bf, want, wst, 1e-9)
+    plan.close()
+    ref.close()
 
 
 def test_graph_recaptures_when_pointers_change():

@@ -146,16 +146,19 @@ def test_ragged_full_plan_graph(ragged):
     bf, (x, y, off, dg), ref, rst = ragged
     plan = lf.Plan(bf.batch, 3)
     ms = plan.tune(x, y, off, dg, reps=2)
-    announce(f"  tuned schedule {plan.schedule} at {ms:.3f} ms")
+    announce(f"  tuned schedule {plan.schedule} at {ms:.3f} ms, {'graph' if plan.graph else 'eager'} form")
     coef = torch.zeros(bf.batch, 4, dtype=torch.float64, device=x.device)
     status = torch.zeros(bf.batch, dtype=torch.int32, device=x.device)
     first = None
-    for _ in range(3):
-        lf.fit_batched(x, y, off, dg, 3, plan=plan, out=(coef, status))
-        torch.cuda.synchronize()
-        got = coef.cpu().numpy().copy()
-        first = got if first is None else first
-        assert np.array_equal(got, first)
+    for form in (plan.graph, not plan.graph):   # the tuned form, then the other one
+        plan.set_graph(form)
+        for _ in range(3):
+            coef.fill_(7.0)
+            lf.fit_batched(x, y, off, dg, 3, plan=plan, out=(coef, status))
+            torch.cuda.synchronize()
+            got = coef.cpu().numpy().copy()
+            first = got if first is None else first
+            assert np.array_equal(got, first)
     assert (status.cpu().numpy() == 0).all()
     assert _batched_errors(bf, first, ref).max() <= 1e-9
     plan.close()

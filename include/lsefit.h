@@ -328,7 +328,10 @@ lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, 
  * pass of the adjoint keeps no partial sums: it runs its own launch shape
  * (16 waves per compute unit, 2 per block, 1 vector in flight per lane), not
  * the plan's, unless the caller has set a default schedule, which it then
- * uses; the gradients are the same bits under any shape. */
+ * uses; the gradients are the same bits under any shape.  Monomial basis: up
+ * to opt->degree 3 the streaming pass solves for each fit's lambda itself
+ * (one launch); above, one thread per fit solves first (two launches), with
+ * the same operations. */
 lsefit_status fit_backward(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
                            int64_t batch, int32_t dt, const lsefit_options* opt,
                            lsefit_plan* plan, void* ws, size_t ws_bytes,

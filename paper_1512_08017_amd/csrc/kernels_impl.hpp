@@ -963,6 +963,10 @@ __global__ void k_solve_moments(const double* __restrict__ mom, Work w, int solv
 // ---------------------------------------------------------------------------
 // adjoint
 // ---------------------------------------------------------------------------
+// largest degree for which the adjoint walk solves for lambda itself (above it,
+// the solve's registers would cost the walk occupancy)
+constexpr int kAdjointSolveInStream = 3;
+
 template <int MAXM>
 __global__ void __launch_bounds__(256)
     k_adjoint_solve(FitDesc d, Work w, int solver, const double* __restrict__ gcoef, int32_t coef_stride) {
@@ -1092,20 +1096,23 @@ __device__ inline void adjoint_nan(In* __restrict__ gx, In* __restrict__ gy, int
     }
 }
 
-// what the adjoint pass needs of one fit: its tiles and points, status and
-// degree, (c, s), the t-basis solution b and the adjoint solution lambda
-template <int MAXM>
+// What the adjoint walk reads of one fit: its tiles, points, status, degree,
+// range, b and lambda -- or, when the walk solves for lambda itself (SOLVE),
+// dL/da and the power sums instead of lambda.
+template <int MAXM, bool SOLVE>
 struct AdjMeta {
     int64_t fs, fe, lo, hi;
     double c, s;
     double b[MAXM + 1], lam[MAXM + 1];
+    double g[SOLVE ? MAXM + 1 : 1], S[SOLVE ? 2 * MAXM + 1 : 1];
     int st, deg;
 };
 
-template <int MAXM>
-__device__ inline AdjMeta<MAXM> load_adj_meta(const FitDesc& d, const Work& w, int64_t f) {
+template <int MAXM, bool SOLVE>
+__device__ inline AdjMeta<MAXM, SOLVE> load_adj_meta(const FitDesc& d, const Work& w, int64_t f,
+                                                     const double* __restrict__ gcoef, int32_t coef_stride) {
     constexpr int rl = rec_len(MAXM);
-    AdjMeta<MAXM> m;
+    AdjMeta<MAXM, SOLVE> m;
     m.fs = w.tile_start[f];
     m.fe = w.tile_start[f + 1];
     m.lo = fit_lo(d, f);
@@ -1115,12 +1122,37 @@ __device__ inline AdjMeta<MAXM> load_adj_meta(const FitDesc& d, const Work& w, i
     const double* r = w.rec + f * rl;
     m.c = r[0];
     m.s = r[1];
+    // entries past the fit's degree are read but not used (the record holds the
+    // largest degree's sizes, and coef_stride >= MAXM + 1)
 #pragma unroll
-    for (int j = 0; j <= MAXM; ++j) {   // entries past the fit's degree are read but not used
-        m.b[j] = r[rec_b(MAXM) + j];
-        m.lam[j] = r[rec_lam(MAXM) + j];
+    for (int j = 0; j <= MAXM; ++j) m.b[j] = r[rec_b(MAXM) + j];
+    if constexpr (SOLVE) {
+#pragma unroll
+        for (int j = 0; j <= MAXM; ++j) m.g[j] = gcoef[f * (int64_t)coef_stride + j];
+#pragma unroll
+        for (int k = 0; k <= 2 * MAXM; ++k) m.S[k] = r[rec_S(MAXM) + k];
+    } else {
+#pragma unroll
+        for (int j = 0; j <= MAXM; ++j) m.lam[j] = r[rec_lam(MAXM) + j];
     }
     return m;
+}
+
+// lambda = A_t^-1 M^T dL/da of a fit of degree M from its loaded dL/da and power
+// sums: the operations of k_adjoint_solve, so the same bits.  NaN when the solve
+// fails.
+template <int M, int MAXM>
+__device__ inline void adjoint_lambda(int solver, const AdjMeta<MAXM, true>& m, double (&lam)[MAXM + 1]) {
+    constexpr int N = M + 1;
+    double g[N], gt[1][N], l[1][N], S[2 * M + 1];
+#pragma unroll
+    for (int k = 0; k < N; ++k) g[k] = m.g[k];
+    to_t_basis_adjoint<N>(g, m.c, m.s, gt[0]);
+#pragma unroll
+    for (int k = 0; k <= 2 * M; ++k) S[k] = m.S[k];
+    const int st = normal_solve<N, 1>(solver, S, gt, l);
+#pragma unroll
+    for (int k = 0; k <= MAXM; ++k) lam[k] = k < N ? (st == LSEFIT_OK ? l[0][k] : NAN) : 0.0;
 }
 
 // The adjoint pass has no per-wave partial sums, so its tiles go to blocks, not
@@ -1128,10 +1160,17 @@ __device__ inline AdjMeta<MAXM> load_adj_meta(const FitDesc& d, const Work& w, i
 // forward's tile table (K blocks) and streams each fit inside that range as
 // one segment, its waves together (adjoint_segment).  The next fit's record is
 // loaded before the current segment is streamed.
-template <int MAXM, typename In, int U>
+//
+// SOLVE: no separate solve launch before this one -- the walk loads dL/da and
+// the power sums with the record and solves for lambda itself when the fit's
+// turn comes (every block that streams part of the fit, with the same
+// operations, so the same bits); the block that holds the fit's first tile
+// writes lambda to the record.
+template <int MAXM, typename In, int U, bool SOLVE>
 __global__ void __launch_bounds__(256)
     k_adjoint_stream(FitDesc d, Work w, const In* __restrict__ x, const In* __restrict__ y, In* __restrict__ gx,
-                     In* __restrict__ gy, int64_t W, int mis) {
+                     In* __restrict__ gy, int64_t W, int mis, int solver, const double* __restrict__ gcoef,
+                     int32_t coef_stride) {
     const KernelClock kclock_(w.clock);
     (void)W;
     const int64_t K = gridDim.x;
@@ -1150,18 +1189,18 @@ __global__ void __launch_bounds__(256)
         else hi = mid;
     }
     int64_t f = lo;
-    AdjMeta<MAXM> cur = load_adj_meta<MAXM>(d, w, f);
+    AdjMeta<MAXM, SOLVE> cur = load_adj_meta<MAXM, SOLVE>(d, w, f, gcoef, coef_stride);
     int64_t t = t0;
     while (t < t1) {
         if (cur.fe <= t) {   // a fit without tiles
             ++f;
-            cur = load_adj_meta<MAXM>(d, w, f);
+            cur = load_adj_meta<MAXM, SOLVE>(d, w, f, gcoef, coef_stride);
             continue;
         }
         const int64_t te = cur.fe < t1 ? cur.fe : t1;
         const bool more = te < t1;   // then fit f + 1 < B holds the next tile
-        AdjMeta<MAXM> nxt = cur;
-        if (more) nxt = load_adj_meta<MAXM>(d, w, f + 1);
+        AdjMeta<MAXM, SOLVE> nxt = cur;
+        if (more) nxt = load_adj_meta<MAXM, SOLVE>(d, w, f + 1, gcoef, coef_stride);
         const int64_t plo = cur.lo + (t - cur.fs) * tile;
         int64_t phi = cur.lo + (te - cur.fs) * tile;
         if (phi > cur.hi) phi = cur.hi;
@@ -1169,6 +1208,14 @@ __global__ void __launch_bounds__(256)
             adjoint_nan(gx, gy, plo, phi, first, step);
         } else {
             auto body = [&]<int M>() {
+                if constexpr (SOLVE) {
+                    adjoint_lambda<M, MAXM>(solver, cur, cur.lam);
+                    if (t == cur.fs && threadIdx.x == 0) {
+                        double* r = w.rec + f * rec_len(MAXM);
+#pragma unroll
+                        for (int k = 0; k <= M; ++k) r[rec_lam(MAXM) + k] = cur.lam[k];
+                    }
+                }
                 AdjointPoint<M, In> P;
                 P.template init<MAXM>(cur.c, cur.s, cur.b, cur.lam);
                 adjoint_segment<U>(P, x, y, gx, gy, plo, phi, mis, first, step, edge);
@@ -1406,19 +1453,25 @@ template <int MAXM>
 hipError_t Launchers<MAXM>::adjoint(const FitDesc& d, const Work& w, int solver, int dtype, const void* x,
                                     const void* y, const double* grad_coef, int32_t coef_stride, void* gx, void* gy,
                                     const Launch& L, int mis, hipStream_t st) {
-    const int64_t sblocks = (d.batch + 255) / 256;
-    hipLaunchKernelGGL(k_adjoint_solve<MAXM>, dim3(sblocks > 0 ? sblocks : 1), dim3(256), 0, st, d, w, solver,
-                       grad_coef, coef_stride);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    // up to kAdjointSolveInStream the walk solves for lambda itself (one launch);
+    // above it a thread per fit solves first, and the walk reads lambda
+    constexpr bool solve_in_stream = MAXM <= kAdjointSolveInStream;
+    if constexpr (!solve_in_stream) {
+        const int64_t sblocks = (d.batch + 255) / 256;
+        hipLaunchKernelGGL(k_adjoint_solve<MAXM>, dim3(sblocks > 0 ? sblocks : 1), dim3(256), 0, st, d, w, solver,
+                           grad_coef, coef_stride);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const dim3 grid(blocks_for(L)), block(L.wpb * kWave);
 #define LSEFIT_ADJ(UU)                                                                                           \
     if (dtype == LSEFIT_F32)                                                                                     \
-        launch_timed((k_adjoint_stream<MAXM, float, UU>), grid, block, st, d, w, (const float*)x,      \
-                           (const float*)y, (float*)gx, (float*)gy, L.waves, mis);                       \
+        launch_timed((k_adjoint_stream<MAXM, float, UU, solve_in_stream>), grid, block, st, d, w, (const float*)x, \
+                     (const float*)y, (float*)gx, (float*)gy, L.waves, mis, solver, grad_coef, coef_stride);    \
     else                                                                                                         \
-        launch_timed((k_adjoint_stream<MAXM, double, UU>), grid, block, st, d, w, (const double*)x,    \
-                           (const double*)y, (double*)gx, (double*)gy, L.waves, mis);
+        launch_timed((k_adjoint_stream<MAXM, double, UU, solve_in_stream>), grid, block, st, d, w,              \
+                     (const double*)x, (const double*)y, (double*)gx, (double*)gy, L.waves, mis, solver,       \
+                     grad_coef, coef_stride);
     switch (L.unroll) {
         case 1: LSEFIT_ADJ(1) break;
         case 2: LSEFIT_ADJ(2) break;

@@ -227,15 +227,18 @@ def test_graph_recaptures_when_pointers_change():
 
 # --- adjoint -------------------------------------------------------------------
 
+# largest degree 3: the walk solves for lambda itself; 6: a separate solve launch first
+@pytest.mark.parametrize("maxd,lengths,degrees", [(3, [4096, 1000, 257, 33], [2, 3, 1, 2]),
+                                                  (6, [4096, 1000, 257, 33, 3000, 5000], [2, 3, 1, 2, 5, 6])])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-def test_adjoint_against_oracle(dtype):
-    announce(f"adjoint {np.dtype(dtype).name}")
-    bf = W.random_batch([4096, 1000, 257, 33], [2, 3, 1, 2], seed=12, dtype=dtype, with_target=True)
+def test_adjoint_against_oracle(dtype, maxd, lengths, degrees):
+    announce(f"adjoint {np.dtype(dtype).name}, largest degree {maxd}")
+    bf = W.random_batch(lengths, degrees, seed=12, dtype=dtype, with_target=True)
     x = to_dev(bf.x).requires_grad_(True)
     y = to_dev(bf.y).requires_grad_(True)
     off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
     target = torch.from_numpy(bf.target).to(x.device)
-    coef = lf.lsefit(x, y, off, dg, 3, center=0.0, scale=1.0)
+    coef = lf.lsefit(x, y, off, dg, maxd, center=0.0, scale=1.0)
     mask = torch.zeros_like(coef)
     for f in range(bf.batch):
         mask[f, : int(bf.degrees[f]) + 1] = 1.0
@@ -311,6 +314,35 @@ def test_adjoint_after_compensated_forward():
         ref = adjoint.gradients(bf.x[lo:hi], bf.y[lo:hi], m, 2.0 * (a_all[f, : m + 1] - bf.target[f, : m + 1]))
         assert normwise(gx[lo:hi], ref["dx"]) <= 1e-5, f
         assert normwise(gy[lo:hi], ref["dy"]) <= 1e-5, f
+
+
+def test_adjoint_lambda_in_stream_matches_separate_solve():
+    """Up to degree 3 the adjoint walk solves for lambda itself; above, a
+    separate launch solves first.  The same fits (degrees 1-3) run with
+    largest degree 3 and 4: when the forward gives the same bits under both,
+    so do the gradients; otherwise they agree to rounding."""
+    announce("adjoint: lambda in the walk against the separate solve")
+    bf = W.random_batch([5000, 70_001, 1, 12_345, 999, 2048, 4096], [2, 3, 1, 2, 3, 1, 2], seed=41)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    g = torch.from_numpy(np.random.default_rng(42).standard_normal((bf.batch, 5))).to(x.device)
+    out = []
+    for maxd in (3, 4):
+        coef, status, ws = lf.fit_batched(x, y, off, dg, maxd)
+        gx, gy = lf.fit_backward(x, y, off, dg, maxd, g[:, : maxd + 1].contiguous(), ws=ws)
+        torch.cuda.synchronize()
+        out.append((coef.cpu().numpy()[:, :4], status.cpu().numpy(), gx.cpu().numpy(), gy.cpu().numpy()))
+    (c3, s3, gx3, gy3), (c4, s4, gx4, gy4) = out
+    assert np.array_equal(s3, s4) and s3[2] != 0 and (np.delete(s3, 2) == 0).all()
+    lo, hi = bf.offsets[2], bf.offsets[3]
+    assert np.isnan(gx3[lo:hi]).all() and np.isnan(gx4[lo:hi]).all()
+    same_forward = np.array_equal(c3, c4, equal_nan=True)
+    announce(f"  forward bits equal under both: {same_forward}")
+    if same_forward:
+        assert np.array_equal(gx3, gx4, equal_nan=True) and np.array_equal(gy3, gy4, equal_nan=True)
+    else:
+        keep = np.isfinite(gx4)
+        assert normwise(gx3[keep], gx4[keep]) <= 1e-6 and normwise(gy3[keep], gy4[keep]) <= 1e-6
 
 
 def test_backward_and_residuals_after_schedule_change():

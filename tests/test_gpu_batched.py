@@ -54,6 +54,7 @@ def test_ragged_mixed_degrees(precision, tol):
     {"waves": 1024, "waves_per_block": 2, "tile": 512, "unroll": 2},
     {"waves": 4096, "waves_per_block": 4, "tile": 4096, "unroll": 4},
     {"waves": 8192, "waves_per_block": 4, "tile": 256, "unroll": 2},
+    {"waves": 2048, "waves_per_block": 2, "tile": 1000, "unroll": 2},   # not a power of two: two plan launches
 ])
 def test_schedules_agree(schedule):
     announce(f"schedule {schedule}")
@@ -68,6 +69,27 @@ def test_schedules_agree(schedule):
     finally:
         lf.set_default_schedule(old)
     check_against_oracle(bf, coef, status, 1e-9)
+
+
+@pytest.mark.parametrize("batch", [8192, 8193])
+def test_tile_table_one_launch_and_two(batch):
+    """Up to 32 blocks of 256 fits (8,192) the tile table takes one launch, in
+    which every block also counts the tiles before its own; from 8,193 fits on
+    it takes two.  Short fits, some empty and some across tile boundaries."""
+    announce(f"tile table, {batch} fits")
+    rng = np.random.default_rng(batch)
+    L = rng.integers(0, 600, batch)
+    L[::97] = 0
+    deg = rng.integers(1, 4, batch)
+    bf = W.random_batch(L, deg, seed=batch + 1, lo=-5.0, hi=5.0)
+    old = lf.default_schedule().as_dict()
+    try:
+        lf.set_default_schedule({"waves": 4096, "waves_per_block": 2, "tile": 256, "unroll": 2})
+        coef, status = run_batched(bf, 3)
+    finally:
+        lf.set_default_schedule(old)
+    check_against_oracle(bf, coef, status, 1e-9)
+    assert (status[L < deg + 1] == 2).all()      # too few points (empty fits included)
 
 
 def test_degree_out_of_range_is_flagged():

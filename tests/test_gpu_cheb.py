@@ -97,6 +97,27 @@ def test_sweep_rounds(k, dtype, offset):
     assert e <= TOL
 
 
+@pytest.mark.parametrize("schedule", [
+    {"waves": 1000, "waves_per_block": 2, "tile": 2048, "unroll": 2},
+    {"waves": 8192, "waves_per_block": 1, "tile": 2048, "unroll": 2},
+])
+def test_single_fit_under_schedules(schedule):
+    """The finish adds the block partials of any grid (a partial round of 512
+    blocks; sixteen rounds) for the 37 sums of degree 12."""
+    announce(f"chebyshev single fit under {schedule}")
+    wl = W.runge(n=3_000_001, seed=950)
+    old = lf.default_schedule().as_dict()
+    try:
+        lf.set_default_schedule(schedule)
+        res = lf.fit(to_dev(wl.x), to_dev(wl.y), 12, basis="chebyshev", center=0.0, scale=1.0)
+        torch.cuda.synchronize()
+    finally:
+        lf.set_default_schedule(old)
+    ref = c_oracle.cheb_fit(wl.x, wl.y, 12, 0.0, 1.0)
+    assert int(res.status.cpu()[0]) == 0
+    assert normwise(res.coef_cheb.cpu().numpy(), ref["c"]) <= TOL
+
+
 @pytest.mark.parametrize("lo,hi,m,dtype", [
     (-7.25, 3.5, 9, np.float64),
     (1000.0, 1001.0, 16, np.float32),

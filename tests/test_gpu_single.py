@@ -39,6 +39,44 @@ def test_f64_form_sizes(n, dtype):
     assert normwise(res.coef.cpu().numpy(), ref["a"]) <= 1e-9
 
 
+# block counts of the streaming grid: 16 (fewer than a wave's lanes); 64; 500
+# (a partial chunk of the finish's 512 blocks per round); 1,024; 8,192
+# (sixteen rounds)
+SINGLE_SCHEDULES = [
+    {"waves": 64, "waves_per_block": 4, "tile": 2048, "unroll": 2},
+    {"waves": 64, "waves_per_block": 1, "tile": 2048, "unroll": 1},
+    {"waves": 1000, "waves_per_block": 2, "tile": 2048, "unroll": 2},
+    {"waves": 4096, "waves_per_block": 4, "tile": 2048, "unroll": 4},
+    {"waves": 8192, "waves_per_block": 1, "tile": 2048, "unroll": 2},
+]
+
+
+@pytest.mark.parametrize("schedule", SINGLE_SCHEDULES)
+@pytest.mark.parametrize("m,precision", [(3, "f64"), (3, "f32c"), (8, "f64")])
+def test_single_fit_under_schedules(schedule, m, precision):
+    """The finish adds the block partials of any grid: a few blocks, a partial
+    round, several rounds; each against the oracle and with its power sums."""
+    announce(f"single fit m={m} {precision} under {schedule}")
+    fit = W.random_small(2_000_003, m, seed=300 + m, lo=-1.0, hi=1.0, dtype=np.float32)
+    old = lf.default_schedule().as_dict()
+    try:
+        lf.set_default_schedule(schedule)
+        res = run_fit(fit, m, precision=precision, center=0.0, scale=1.0)
+    finally:
+        lf.set_default_schedule(old)
+    ref = c_oracle.fit(fit.x, fit.y, m, center=0.0, scale=1.0)
+    assert int(res.status.cpu()[0]) == 0
+    mom = res.moments.cpu().numpy()
+    S = mom[2:3 + 2 * m]
+    assert S[0] == fit.n
+    if precision == "f64":
+        T = mom[3 + 2 * m:]
+        assert np.max(np.abs(S - ref["S"]) / np.abs(ref["S"]).max()) <= 1e-12
+        assert np.max(np.abs(T - ref["T"]) / np.abs(ref["T"]).max()) <= 1e-12
+    tol = (1e-9 if m <= 5 else 1e-7) if precision == "f64" else 1e-6
+    assert normwise(res.coef_t.cpu().numpy(), ref["b"]) <= tol
+
+
 @pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_every_degree_given_range(m):
     """Given (c, s): compare power sums and t-basis solution in the same basis."""

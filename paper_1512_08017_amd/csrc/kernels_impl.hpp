@@ -58,18 +58,23 @@ struct AccF64 {
         nc = -c * is;
     }
     __device__ inline void point(double xv, double yv) {
-        // powers by a product tree, p_k = p_(k/2) p_(k - k/2): depth ceil(log2 2M)
-        // instead of a chain of 2M - 1 dependent multiplies
-        double p[2 * M + 1];
+        // powers up to t^M by a product tree, p_k = p_(k/2) p_(k - k/2) (depth
+        // ceil(log2 M) instead of a chain of dependent multiplies); a power above
+        // t^M is only ever added to its sum, so its product p_(k/2) p_(k - k/2)
+        // is formed inside the fused multiply-add of that sum, as are the t^j y
+        // of the right-hand side: 4M + 1 float64 operations per point
+        double p[M + 1];
         p[1] = fma(xv, inv_s, nc);
 #pragma unroll
-        for (int k = 2; k <= 2 * M; ++k) p[k] = p[k / 2] * p[k - k / 2];
+        for (int k = 2; k <= M; ++k) p[k] = p[k / 2] * p[k - k / 2];
         T[0] += yv;
 #pragma unroll
-        for (int k = 1; k <= 2 * M; ++k) {
+        for (int k = 1; k <= M; ++k) {
             S[k - 1] += p[k];
-            if (k <= M) T[k] = fma(yv, p[k], T[k]);
+            T[k] = fma(yv, p[k], T[k]);
         }
+#pragma unroll
+        for (int k = M + 1; k <= 2 * M; ++k) S[k - 1] = fma(p[k / 2], p[k - k / 2], S[k - 1]);
     }
     template <typename V, int VW>
     __device__ inline void vec(const V& xv, const V& yv) {

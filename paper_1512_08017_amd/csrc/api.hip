@@ -395,7 +395,7 @@ struct lsefit_plan {
     std::string tune_cache;   // schedule cache file of fit_plan_tune ("" = none)
 
     void drop_graph() {
-        if (exec) hipGraphExecDestroy(exec);
+        if (exec) (void)hipGraphExecDestroy(exec);
         exec = nullptr;
         have_key = false;
     }
@@ -683,11 +683,11 @@ lsefit_status plan_graph_call(lsefit_plan* plan, const FitDesc& d, const Work& w
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(plan->cap_stream, &graph);
         if (s != LSEFIT_OK || e != hipSuccess || !graph) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return s != LSEFIT_OK ? s : LSEFIT_ERR_DEVICE;
         }
         const hipError_t ie = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (ie != hipSuccess) {
             plan->exec = nullptr;
             return LSEFIT_ERR_DEVICE;
@@ -724,6 +724,8 @@ lsefit_status time_calls(hipStream_t st, int reps, F&& fn, double* ms_per_call) 
 // The replay form of a tuned plan: eager launches of its schedule against
 // replays of the captured graph, timed on the same call; the faster is kept
 // (*graph_out = 1 for the graph).  A form set with fit_plan_set_graph is kept.
+// The eager launches have just run with these arguments, so a graph that
+// cannot be captured or replayed here leaves the plan eager, not failed.
 lsefit_status choose_replay_form(lsefit_plan* plan, const FitDesc& d, const Work& w, const lsefit_options* opt,
                                  const void* x, const void* y, double* coef, int32_t coef_stride, int32_t* status,
                                  hipStream_t st, int reps, int* graph_out) {
@@ -737,7 +739,14 @@ lsefit_status choose_replay_form(lsefit_plan* plan, const FitDesc& d, const Work
     if (r != LSEFIT_OK) return r;
     r = time_calls(st, reps, [&] { return plan_graph_call(plan, d, w, opt, dt, x, y, coef, coef_stride, status, st); },
                    &tg);
-    if (r != LSEFIT_OK) return r;
+    if (r != LSEFIT_OK) {
+        (void)hipGetLastError();   // the failed capture or launch, not the caller's
+        if (hipStreamSynchronize(st) != hipSuccess) return LSEFIT_ERR_DEVICE;
+        plan->graph_enabled = false;
+        plan->drop_graph();
+        *graph_out = 0;
+        return LSEFIT_OK;
+    }
     plan->graph_enabled = tg < te;
     if (!plan->graph_enabled) plan->drop_graph();
     *graph_out = plan->graph_enabled ? 1 : 0;
@@ -878,7 +887,10 @@ lsefit_status fit_plan_create(lsefit_plan** out, int64_t batch, int32_t max_degr
     p->max_degree = max_degree;
     p->dtype = dt;
     p->precision = precision;
-    hipGetDevice(&p->device);
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return LSEFIT_ERR_DEVICE;
+    }
     p->sched = current_default();
     int cus = device_cus();
     if (cus <= 0) cus = 256;
@@ -1094,8 +1106,8 @@ lsefit_status lsefit_timing_read(int32_t kind, double* total_ms, int64_t* launch
 void fit_plan_destroy(lsefit_plan* plan) {
     if (!plan) return;
     plan->drop_graph();
-    if (plan->cap_stream) hipStreamDestroy(plan->cap_stream);
-    if (plan->ws) hipFree(plan->ws);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    if (plan->ws) (void)hipFree(plan->ws);
     delete plan;
 }
 

@@ -338,6 +338,34 @@ def test_adjoint_after_compensated_forward():
         assert normwise(gy[lo:hi], ref["dy"]) <= 1e-5, f
 
 
+@pytest.mark.parametrize("maxd,degrees", [(3, [2, 3, 1, 2]), (6, [2, 3, 1, 6])])
+def test_adjoint_with_cholesky(maxd, degrees):
+    """The adjoint solve with the Cholesky factorisation (in the walk up to
+    degree 3, in its own launch above) against the float64 adjoint oracle."""
+    announce(f"adjoint, Cholesky, largest degree {maxd}")
+    bf = W.random_batch([4096, 1000, 257, 3001], degrees, seed=14, dtype=np.float64, with_target=True)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    coef, status, ws = lf.fit_batched(x, y, off, dg, maxd, center=0.0, scale=1.0, solver="cholesky")
+    torch.cuda.synchronize()
+    assert (status.cpu().numpy() == 0).all()
+    a_all = coef.cpu().numpy()
+    gbar = np.zeros_like(a_all)
+    for f in range(bf.batch):
+        m = int(bf.degrees[f])
+        gbar[f, : m + 1] = 2.0 * (a_all[f, : m + 1] - bf.target[f, : m + 1])
+    gx, gy = lf.fit_backward(x, y, off, dg, maxd, torch.from_numpy(gbar).to(x.device), ws=ws,
+                             center=0.0, scale=1.0, solver="cholesky")
+    torch.cuda.synchronize()
+    gx, gy = gx.cpu().numpy(), gy.cpu().numpy()
+    for f in range(bf.batch):
+        lo, hi = bf.offsets[f], bf.offsets[f + 1]
+        m = int(bf.degrees[f])
+        ref = adjoint.gradients(bf.x[lo:hi], bf.y[lo:hi], m, gbar[f, : m + 1])
+        assert normwise(gx[lo:hi], ref["dx"]) <= 1e-9, f
+        assert normwise(gy[lo:hi], ref["dy"]) <= 1e-9, f
+
+
 def test_adjoint_lambda_in_stream_matches_separate_solve():
     """Up to degree 3 the adjoint walk solves for lambda itself; above, a
     separate launch solves first.  The same fits (degrees 1-3) run with

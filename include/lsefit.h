@@ -177,7 +177,10 @@ typedef struct lsefit_plan lsefit_plan;   /* opaque: schedule, workspace, captur
 /* Bytes of workspace needed by fit_moments/fit_solve (batch = 1, total_points = n)
  * or by fit_batched/fit_backward (batch fits) with `schedule` (NULL: the default
  * schedule).  The workspace holds per-wave partial sums, the tile table and one
- * record per fit (c, s, power sums, t-basis solution) that fit_backward reads. */
+ * record per fit (c, s, power sums, t-basis solution) that fit_backward reads.
+ * Its contents on entry to a fitting call do not matter (every call writes what
+ * it reads), so a caller need not clear it; fit_backward and fit_residuals read
+ * what the preceding fit left there. */
 size_t lsefit_workspace_bytes(int64_t batch, int32_t max_degree, const lsefit_schedule* schedule);
 /* (max_degree up to LSEFIT_MAX_DEGREE_CHEBYSHEV for Chebyshev-basis calls) */
 

@@ -131,7 +131,7 @@ def fit_moments(x, y, degree, precision="f64", center=None, scale=None, ws=None,
     o = options(degree, precision, 0, center, scale, solver, basis)
     nbytes = workspace_bytes(1, degree)
     if ws is None or ws.numel() < nbytes:
-        ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
     mom = torch.empty(3 * degree + 4, dtype=torch.float64, device=x.device)
     check(L.fit_moments(_ptr(x), _ptr(y), x.numel(), _DT[x.dtype], ctypes.byref(o), _ptr(ws), ws.numel(),
                         _ptr(mom), _stream(x.device)), "fit_moments")
@@ -147,7 +147,7 @@ def fit_solve(moments, degree, precision="f64", refine=1, x=None, y=None, ws=Non
     dev = moments.device
     nbytes = workspace_bytes(1, degree)
     if ws is None or ws.numel() < nbytes:
-        ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     coef = torch.empty(2 * (degree + 1), dtype=torch.float64, device=dev)
     status = torch.empty(1, dtype=torch.int32, device=dev)
     n = x.numel() if x is not None else 0
@@ -169,7 +169,7 @@ def fit(x, y, degree: int, precision: str = "f64", refine: int = 1, center=None,
     o = options(degree, precision, refine, center, scale, solver, basis)
     nbytes = workspace_bytes(1, degree)
     if ws is None or ws.numel() < nbytes:
-        ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
     m1 = degree + 1
     coef = torch.empty(2 * m1, dtype=torch.float64, device=x.device)
     status = torch.empty(1, dtype=torch.int32, device=x.device)
@@ -210,7 +210,7 @@ def fit_qr(x, y, degree: int, center=None, scale=None, ws=None) -> QRResult:
     o = options(degree, "f64", 0, center, scale)
     nbytes = workspace_bytes(1, degree)
     if ws is None or ws.numel() < nbytes:
-        ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
     m1 = degree + 1
     coef = torch.empty(2 * m1, dtype=torch.float64, device=x.device)
     status = torch.empty(1, dtype=torch.int32, device=x.device)
@@ -237,7 +237,7 @@ def fit_qr_batched(x, y, offsets, degrees, max_degree: int, center=None, scale=N
         coef, status, sse = out
     nbytes = workspace_bytes(max(B, 1), max_degree)
     if ws is None or ws.numel() < nbytes:
-        ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
     check(L.fit_qr_batched(_ptr(x), _ptr(y), _ptr(offsets), _ptr(degrees), B, _DT[x.dtype], ctypes.byref(o),
                            _ptr(ws), ws.numel(), _ptr(coef), stride, _ptr(status), _ptr(sse), _stream(x.device)),
           "fit_qr_batched")
@@ -389,7 +389,7 @@ def fit_batched(x, y, offsets, degrees, max_degree: int, precision: str = "f64",
     if plan is None:
         nbytes = workspace_bytes(max(B, 1), max_degree)
         if ws is None or ws.numel() < nbytes:
-            ws = torch.zeros(nbytes, dtype=torch.uint8, device=x.device)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
     check(L.fit_batched(_ptr(x), _ptr(y), _ptr(offsets), _ptr(degrees), B, _DT[x.dtype], ctypes.byref(o),
                         plan.handle if plan is not None else None, _ptr(ws) if plan is None else None,
                         ws.numel() if plan is None else 0, _ptr(coef), stride, _ptr(status), _stream(x.device)),

@@ -395,6 +395,30 @@ def test_adjoint_lambda_in_stream_matches_separate_solve():
         assert normwise(gx3[keep], gx4[keep]) <= 1e-6 and normwise(gy3[keep], gy4[keep]) <= 1e-6
 
 
+def test_batched_workspace_need_not_be_cleared():
+    """A batch fitted, differentiated and its residuals summed on a workspace
+    that starts with arbitrary bytes gives the same bits as on a cleared one."""
+    announce("batched calls on an uncleared workspace")
+    bf = W.random_batch([5000, 70_001, 1, 12_345, 999, 0, 4096], [2, 3, 1, 2, 3, 1, 2], seed=43,
+                        with_target=True)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    g = torch.from_numpy(np.nan_to_num(bf.target)).to(x.device)
+    nbytes = lf.workspace_bytes(bf.batch, 3)
+    out = []
+    for fill in (0x00, 0x5A, 0xFF):
+        ws = torch.full((nbytes,), fill, dtype=torch.uint8, device=x.device)
+        coef, status, _ = lf.fit_batched(x, y, off, dg, 3, ws=ws)
+        gx, gy = lf.fit_backward(x, y, off, dg, 3, g, ws=ws)
+        sse, _ = lf.residuals_batched(x, y, off, dg, 3, ws=ws)
+        torch.cuda.synchronize()
+        out.append([t.cpu().numpy() for t in (coef, status, gx, gy, sse)])
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b, equal_nan=True)
+    assert out[0][1][2] == 2 and out[0][1][5] == 2      # the one-point and the empty fit
+
+
 def test_backward_and_residuals_after_schedule_change():
     """The adjoint and the residual pass read the tile size from the forward's
     tile table, so a default schedule changed between forward and backward

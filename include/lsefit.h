@@ -360,14 +360,15 @@ lsefit_status fit_residuals(const void* x, const void* y, const int64_t* offsets
 /* Plans for repeated batched calls of one shape.  fit_plan_create allocates
  * the plan's workspace (device memory, freed by fit_plan_destroy) for up to
  * `batch` fits of degree <= max_degree.  fit_plan_tune times candidate
- * schedules on the given data (it synchronises `stream`) and keeps the
- * fastest; it then times that schedule as eager launches and as replays of a
- * captured graph on the same call and keeps the faster form (eager when the
- * graph cannot be captured or replayed), unless fit_plan_set_graph chose one
- * (enable 1: replay a captured graph, 0: launch eagerly; a new plan replays
- * graphs).  fit_plan_get_graph reports the form in
- * use.  fit_plan_set_schedule installs a known schedule (for example from a
- * cache).  A plan must be used from one stream at a time. */
+ * schedules on the given data (it synchronises `stream`): every candidate
+ * with `reps` calls, then the four fastest again with 3 * reps calls each,
+ * keeping the fastest of those.  It then times that schedule as eager
+ * launches and as replays of a captured graph on the same call and keeps the
+ * faster form (eager when the graph cannot be captured or replayed), unless
+ * fit_plan_set_graph chose one (enable 1: replay a captured graph, 0: launch
+ * eagerly; a new plan replays graphs).  fit_plan_get_graph reports the form
+ * in use.  fit_plan_set_schedule installs a known schedule (for example from
+ * a cache).  A plan must be used from one stream at a time. */
 lsefit_status fit_plan_create(lsefit_plan** plan, int64_t batch, int32_t max_degree, int32_t dt,
                               int32_t precision);
 lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, const int64_t* offsets,

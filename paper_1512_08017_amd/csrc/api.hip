@@ -6,6 +6,7 @@
 // kernels of kernels_impl.hpp and dispatch.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdint>
@@ -979,12 +980,27 @@ lsefit_status fit_plan_tune(lsefit_plan* plan, const void* x, const void* y, con
                     lsefit_schedule s{cus * wpc, wpb, tile, unroll};
                     if (to_launch(s).waves <= plan->max_waves) cands.push_back(s);
                 }
-    double best = 1e300;
-    lsefit_schedule best_s = plan->sched;
+    // first round: every candidate, `reps` timed calls each; second round: the
+    // kTuneFinalists fastest again with 3 * reps calls each (one round's timing
+    // moves by a few percent from run to run, about the gap between the leaders)
+    constexpr size_t kTuneFinalists = 4;
+    std::vector<std::pair<double, size_t>> first;
     lsefit_status r = LSEFIT_OK;
-    for (const auto& s : cands) {
+    for (size_t i = 0; i < cands.size(); ++i) {
         double per = 0.0;
         r = time_calls(st, reps, [&] {
+            return enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, cands[i], st);
+        }, &per);
+        if (r != LSEFIT_OK) return r;
+        first.emplace_back(per, i);
+    }
+    std::sort(first.begin(), first.end());
+    double best = 1e300;
+    lsefit_schedule best_s = plan->sched;
+    for (size_t j = 0; j < first.size() && j < kTuneFinalists; ++j) {
+        const lsefit_schedule& s = cands[first[j].second];
+        double per = 0.0;
+        r = time_calls(st, 3 * reps, [&] {
             return enqueue_batched(d, w, opt, plan->dtype, x, y, coef, coef_stride, status, s, st);
         }, &per);
         if (r != LSEFIT_OK) return r;

@@ -56,7 +56,7 @@ TRACE_FILE = os.path.join(PROFILES, "moments_cubic_f32_kernel_trace.txt")
 TRAFFIC_FILE = os.path.join(PROFILES, "moments_cubic_f32_traffic.txt")
 CEILING_FILE = os.path.join(PROFILES, "read_probe_ceiling.txt")
 KIND_NAMES = ((0, "moments"), (1, "refine"), (2, "adjoint"), (3, "combine"), (4, "probe"), (5, "residual"),
-              (6, "range"))
+              (6, "range"), (7, "plan"))
 
 
 def kernel_hash() -> str:

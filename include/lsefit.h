@@ -441,7 +441,9 @@ lsefit_status lsefit_copy_probe(const float* x, const float* y, float* ox, float
  *        solve), 3 = per-fit combine and solve (the finish kernel of a single
  *        fit), 4 = read or copy probe, 5 = residual pass (not its per-fit
  *        fold), 6 = range pass (Chebyshev basis, automatic range; not its
- *        per-fit fold).
+ *        per-fit fold), 7 = tile table of a batch (its first launch: the
+ *        whole table when the batch has at most 32 blocks of 256 fits and a
+ *        power-of-two tile, else the per-block counts, not the block offsets).
  * Not synchronised with calls on other host threads. */
 lsefit_status lsefit_timing_enable(int32_t enable);
 lsefit_status lsefit_timing_reset(void);

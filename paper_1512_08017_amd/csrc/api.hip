@@ -237,7 +237,8 @@ enum TimedKind {
     kTimeProbe = 4,
     kTimeResidual = 5,
     kTimeRange = 6,
-    kTimeKinds = 7
+    kTimePlan = 7,
+    kTimeKinds = 8
 };
 
 // the launches of each kind get one clock slot each (kClockWords uint64
@@ -328,8 +329,10 @@ lsefit_status enqueue_batched(const FitDesc& d, const Work& w, const lsefit_opti
     refine.mode = kRefine;
     if (chebyshev(o)) {
         // the plan takes the given (c, s), or a placeholder the range pass replaces
-        LSEFIT_TRY(launch_plan(d, w, maxM, L.tile, true, given ? o->center : 0.0, given ? o->scale : 1.0, dt, x,
-                               w.block_tot, st));
+        LSEFIT_TRY(timed(kTimePlan, st, [&] {
+            return launch_plan(d, w, maxM, L.tile, true, given ? o->center : 0.0, given ? o->scale : 1.0, dt, x,
+                               w.block_tot, st);
+        }));
         if (!given)
             LSEFIT_TRY(timed(kTimeRange, st, [&] { return launch_range_cheb(d, w, maxM, dt, x, L, mis, st); }));
         const RangeArg ra{LSEFIT_RANGE_GIVEN, 0.0, 1.0};
@@ -338,7 +341,8 @@ lsefit_status enqueue_batched(const FitDesc& d, const Work& w, const lsefit_opti
         LSEFIT_TRY(timed(kTimeCombine, st, [&] { return launch_finish_cheb(d, w, maxM, L.waves, solve, st); }));
         return LSEFIT_OK;
     }
-    LSEFIT_TRY(launch_plan(d, w, maxM, L.tile, given, o->center, o->scale, dt, x, w.block_tot, st));
+    LSEFIT_TRY(timed(kTimePlan, st,
+                     [&] { return launch_plan(d, w, maxM, L.tile, given, o->center, o->scale, dt, x, w.block_tot, st); }));
     const RangeArg ra{LSEFIT_RANGE_GIVEN, 0.0, 1.0};   // per-fit (c, s) are in the records
     LSEFIT_TRY(timed(kTimeMoments, st,
                      [&] { return launch_moments(d, w, maxM, o->precision, dt, x, y, L, mis, ra, st); }));
@@ -658,7 +662,9 @@ lsefit_status fit_qr_batched(const void* x, const void* y, const int64_t* offset
     const Work w = carve(ws, lay);
     const bool given = opt->range_mode == LSEFIT_RANGE_GIVEN;
     const int mis = common_mis(dt, {x, y});
-    LSEFIT_TRY(launch_plan(d, w, opt->degree, L.tile, given, opt->center, opt->scale, dt, x, w.block_tot, st));
+    LSEFIT_TRY(timed(kTimePlan, st, [&] {
+        return launch_plan(d, w, opt->degree, L.tile, given, opt->center, opt->scale, dt, x, w.block_tot, st);
+    }));
     LSEFIT_TRY(timed(kTimeMoments, st, [&] { return launch_qr_batch(d, w, opt->degree, dt, x, y, L, mis, st); }));
     LSEFIT_TRY(timed(kTimeCombine, st, [&] {
         return launch_qr_combine(d, w, opt->degree, L.waves, coef, coef_stride, status, sse, st);

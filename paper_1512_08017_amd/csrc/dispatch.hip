@@ -19,118 +19,143 @@ namespace lsefit {
 //
 // A batch of at most kPlanFusedBlocks blocks with a power-of-two tile takes
 // one launch (FUSED): every block also counts the tiles of all the fits before
-// its own (at most kPlanFusedBlocks - 1 per thread, a shift each, loaded
+// its own (at most NPREV per thread, the number of blocks before the last one
+// rounded up to 2^k - 1, a shift each, loaded
 // together with its own fits' data) and writes the final table itself.
 // ---------------------------------------------------------------------------
 constexpr int kRangeBatchSamples = 16;
 constexpr int kPlanFusedBlocks = 32;
+constexpr int kPlanWaves = kPlanThreads / kWave;
 
-template <typename In, bool FUSED>
+template <typename In, bool FUSED, int NPREV>
 __global__ void __launch_bounds__(kPlanThreads)
     k_plan_count(FitDesc d, Work w, int maxM, int64_t tile, int range_given, double c, double s,
                  const In* __restrict__ x, int64_t* __restrict__ block_tot, int tile_shift) {
     const KernelClock kclock_(w.clock);
-    __shared__ int64_t sh[kPlanThreads];
-    __shared__ int64_t sp[FUSED ? kPlanThreads : 1];
     const int tid = threadIdx.x;
     const int64_t f = (int64_t)blockIdx.x * kPlanThreads + tid;
     const int rl = rec_len(maxM);
+    // this thread's fit; a thread past the last fit loads the last one and
+    // drops it, so that no load sits behind a branch of its own
+    const int64_t fc = f < d.batch ? f : d.batch - 1;
+    const int64_t lo = fit_lo(d, fc);
+    const int64_t L = fit_hi(d, fc) - lo;
+    const int m = fit_deg(d, fc);
     // FUSED: the tiles of fits tid, tid + 256, ... below this block's first fit;
-    // a thread past the end reads the last such fit again and drops it
+    // a thread past the end reads the last such fit again and drops it.  A
+    // block with fits before it belongs to a batch, which has offsets: read
+    // directly (not through the null check of fit_lo / fit_hi), the two
+    // offsets of a fit come in one 16-byte load, half the load instructions
     int64_t prev = 0;
     if constexpr (FUSED) {
         const int64_t nprev = (int64_t)blockIdx.x * kPlanThreads;
         if (nprev > 0) {
 #pragma unroll
-            for (int i = 0; i < kPlanFusedBlocks - 1; ++i) {
+            for (int i = 0; i < NPREV; ++i) {
                 const int64_t j = tid + (int64_t)i * kPlanThreads;
                 const int64_t jc = j < nprev ? j : nprev - 1;
-                const int64_t L = fit_hi(d, jc) - fit_lo(d, jc);
-                const int64_t t = L <= 0 ? 0 : (L + tile - 1) >> tile_shift;
+                const int64_t Lj = d.offsets[jc + 1] - d.offsets[jc];
+                const int64_t t = Lj <= 0 ? 0 : (Lj + tile - 1) >> tile_shift;
                 prev += j < nprev ? t : 0;
             }
         }
     }
+    double cc = c, ss = s;
+    if (!range_given) {
+        // the first and the last kRangeBatchSamples / 2 points (all of a
+        // shorter fit, whose last point is read again in place of the missing
+        // ones): two cache lines per fit, the exact extent of sorted data, and
+        // one round of loads
+        constexpr int H = kRangeBatchSamples / 2;
+        double v[kRangeBatchSamples];
+        if (L > 0) {
+#pragma unroll
+            for (int i = 0; i < kRangeBatchSamples; ++i) {
+                const int64_t k = L <= kRangeBatchSamples ? (i < L ? i : L - 1)
+                                                          : (i < H ? i : L - kRangeBatchSamples + i);
+                v[i] = (double)x[lo + k];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kRangeBatchSamples; ++i) v[i] = NAN;
+        }
+        double mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < kRangeBatchSamples; ++i) {
+            if (isfinite(v[i])) {
+                mn = fmin(mn, v[i]);
+                mx = fmax(mx, v[i]);
+            }
+        }
+        snap_range(mn, mx, &cc, &ss);
+    }
     int64_t tiles = 0;
     if (f < d.batch) {
-        const int64_t lo = fit_lo(d, f);
-        const int64_t L = fit_hi(d, f) - lo;
-        const int m = fit_deg(d, f);
         tiles = L <= 0 ? 0 : (L + tile - 1) / tile;
         int st = LSEFIT_OK;
         if (m < 1 || m > maxM || L < 0) st = LSEFIT_ERR_INVALID_ARG;
         else if (L < m + 1) st = LSEFIT_ERR_SINGULAR;
         w.pstatus[f] = st;
-        double cc = c, ss = s;
-        if (!range_given) {
-            // the first and the last kRangeBatchSamples / 2 points (all of a
-            // shorter fit): two cache lines per fit, and the exact extent of
-            // sorted data
-            constexpr int H = kRangeBatchSamples / 2;
-            double v[kRangeBatchSamples];
-#pragma unroll
-            for (int i = 0; i < kRangeBatchSamples; ++i) {
-                v[i] = NAN;
-                if (L <= kRangeBatchSamples) {
-                    if (i < L) v[i] = (double)x[lo + i];
-                } else {
-                    v[i] = (double)x[i < H ? lo + i : lo + L - kRangeBatchSamples + i];
-                }
-            }
-            double mn = INFINITY, mx = -INFINITY;
-#pragma unroll
-            for (int i = 0; i < kRangeBatchSamples; ++i) {
-                if (isfinite(v[i])) {
-                    mn = fmin(mn, v[i]);
-                    mx = fmax(mx, v[i]);
-                }
-            }
-            snap_range(mn, mx, &cc, &ss);
-        }
         w.rec[f * rl + 0] = cc;
         w.rec[f * rl + 1] = ss;
     }
-    sh[tid] = tiles;
-    if constexpr (FUSED) sp[tid] = prev;
-    __syncthreads();
-    for (int off = 1; off < kPlanThreads; off <<= 1) {
-        const int64_t v = tid >= off ? sh[tid - off] : 0;
-        int64_t vp = 0;
-        if constexpr (FUSED) vp = tid >= off ? sp[tid - off] : 0;
-        __syncthreads();
-        sh[tid] += v;
-        if constexpr (FUSED) sp[tid] += vp;
-        __syncthreads();
+    // inclusive scan of the tile counts within the wave, then the wave totals
+    // (and the FUSED earlier-fit counts, summed) meet in LDS
+    int64_t incl = tiles;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int64_t v = __shfl_up(incl, off, kWave);
+        incl += lane_id() >= off ? v : 0;
     }
     if constexpr (FUSED) {
-        const int64_t base = sp[kPlanThreads - 1];
-        if (f < d.batch) w.tile_start[f] = base + sh[tid] - tiles;
+#pragma unroll
+        for (int off = kWave / 2; off >= 1; off >>= 1) prev += __shfl_xor(prev, off, kWave);
+    }
+    __shared__ int64_t wtot[kPlanWaves], wprev[FUSED ? kPlanWaves : 1];
+    const int wv = tid / kWave;
+    if (lane_id() == kWave - 1) wtot[wv] = incl;
+    if constexpr (FUSED) {
+        if (lane_id() == 0) wprev[wv] = prev;
+    }
+    __syncthreads();
+    int64_t before = 0, total = 0, base = 0;
+#pragma unroll
+    for (int i = 0; i < kPlanWaves; ++i) {
+        before += i < wv ? wtot[i] : 0;
+        total += wtot[i];
+        if constexpr (FUSED) base += wprev[i];
+    }
+    const int64_t start = before + incl - tiles;   // tiles of this block's fits before f
+    if constexpr (FUSED) {
+        if (f < d.batch) w.tile_start[f] = base + start;
         if (blockIdx.x == gridDim.x - 1 && tid == kPlanThreads - 1) {
-            w.tile_start[d.batch] = base + sh[tid];
+            w.tile_start[d.batch] = base + total;
             w.tile_start[d.batch + 1] = tile;   // the table's own tile size, for every later pass over it
         }
     } else {
-        if (f < d.batch) w.tile_start[f] = sh[tid] - tiles;
-        if (tid == kPlanThreads - 1) block_tot[blockIdx.x] = sh[tid];
+        if (f < d.batch) w.tile_start[f] = start;
+        if (tid == kPlanThreads - 1) block_tot[blockIdx.x] = total;
     }
 }
 
 __global__ void __launch_bounds__(kPlanThreads)
     k_plan_offsets(FitDesc d, Work w, const int64_t* __restrict__ block_tot, int64_t nblocks, int64_t tile) {
     const KernelClock kclock_(w.clock);
-    __shared__ int64_t sh[kPlanThreads];
     const int tid = threadIdx.x;
+    const int64_t f = (int64_t)blockIdx.x * kPlanThreads + tid;
+    // this thread's entry, loaded with the block totals
+    const int64_t local = f < d.batch ? w.tile_start[f] : 0;
     int64_t part = 0;
     for (int64_t b = tid; b < blockIdx.x; b += kPlanThreads) part += block_tot[b];
-    sh[tid] = part;
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) part += __shfl_xor(part, off, kWave);
+    __shared__ int64_t wsum[kPlanWaves];
+    if (lane_id() == 0) wsum[tid / kWave] = part;
     __syncthreads();
-    for (int off = kPlanThreads / 2; off >= 1; off >>= 1) {
-        if (tid < off) sh[tid] += sh[tid + off];
-        __syncthreads();
-    }
-    const int64_t base = sh[0];
-    const int64_t f = (int64_t)blockIdx.x * kPlanThreads + tid;
-    if (f < d.batch) w.tile_start[f] += base;
+    int64_t base = 0;
+#pragma unroll
+    for (int i = 0; i < kPlanWaves; ++i) base += wsum[i];
+    if (f < d.batch) w.tile_start[f] = base + local;
     if (blockIdx.x == nblocks - 1 && tid == 0) {
         w.tile_start[d.batch] = base + block_tot[blockIdx.x];
         w.tile_start[d.batch + 1] = tile;   // the table's own tile size, for every later pass over it
@@ -305,20 +330,28 @@ hipError_t launch_plan(const FitDesc& d, const Work& w, int maxM, int64_t tile, 
     int shift = 0;
     while (shift < 62 && (int64_t(1) << shift) < tile) ++shift;
     if (nb <= kPlanFusedBlocks && (int64_t(1) << shift) == tile) {
-        if (dtype == LSEFIT_F32)
-            hipLaunchKernelGGL((k_plan_count<float, true>), dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile,
-                               rg, c, s, (const float*)x, block_tot, shift);
-        else
-            hipLaunchKernelGGL((k_plan_count<double, true>), dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile,
-                               rg, c, s, (const double*)x, block_tot, shift);
+        auto fused = [&]<int NPREV>() {
+            if (dtype == LSEFIT_F32)
+                launch_timed(k_plan_count<float, true, NPREV>, dim3(nb), dim3(kPlanThreads), st, d, w, maxM, tile, rg,
+                             c, s, (const float*)x, block_tot, shift);
+            else
+                launch_timed(k_plan_count<double, true, NPREV>, dim3(nb), dim3(kPlanThreads), st, d, w, maxM, tile,
+                             rg, c, s, (const double*)x, block_tot, shift);
+        };
+        static_assert(kPlanFusedBlocks == 32, "one instantiation per power of two of earlier blocks");
+        if (nb <= 1) fused.template operator()<0>();
+        else if (nb <= 4) fused.template operator()<3>();
+        else if (nb <= 8) fused.template operator()<7>();
+        else if (nb <= 16) fused.template operator()<15>();
+        else fused.template operator()<31>();
         return hipGetLastError();
     }
     if (dtype == LSEFIT_F32)
-        hipLaunchKernelGGL((k_plan_count<float, false>), dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile, rg,
-                           c, s, (const float*)x, block_tot, 0);
+        launch_timed(k_plan_count<float, false, 0>, dim3(nb), dim3(kPlanThreads), st, d, w, maxM, tile, rg, c, s,
+                     (const float*)x, block_tot, 0);
     else
-        hipLaunchKernelGGL((k_plan_count<double, false>), dim3(nb), dim3(kPlanThreads), 0, st, d, w, maxM, tile, rg,
-                           c, s, (const double*)x, block_tot, 0);
+        launch_timed(k_plan_count<double, false, 0>, dim3(nb), dim3(kPlanThreads), st, d, w, maxM, tile, rg, c, s,
+                     (const double*)x, block_tot, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_plan_offsets, dim3(nb), dim3(kPlanThreads), 0, st, d, w, block_tot, nb, tile);

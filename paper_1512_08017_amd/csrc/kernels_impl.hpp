@@ -898,19 +898,27 @@ __global__ void __launch_bounds__(256) k_combine_lane(FitDesc d, Work w, int64_t
         return;
     }
     const int64_t w0 = wave_of_tile(ts, NT, W), w1 = wave_of_tile(te - 1, NT, W);
+    // the sums of the largest degree's count, whatever this fit's degree: a
+    // degree-m fit's sums are the first ones of its slots, and the loads then
+    // sit outside the degree switch, so that a wave of mixed degrees waits for
+    // its partial sums once
+    double all[stride];
+#pragma unroll
+    for (int k = 0; k < stride; ++k) all[k] = 0.0;
+    dispatch_sum_count<MAXM>(fz.mode, [&]<int NK>() {
+        for (int64_t wv = w0; wv <= w1; ++wv) {
+            if (!wave_owns_tiles(wv, NT, W)) continue;
+            const double* p = w.part + (wv + f) * stride;
+#pragma unroll
+            for (int k = 0; k < NK; ++k) all[k] += p[k];
+        }
+    });
     auto body = [&]<int M>() {
         constexpr int K = nacc(M);
+        const int nk = fz.mode == kRefine ? M + 1 : (fz.mode == kSSE ? 1 : K);
         double v[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = 0.0;
-        dispatch_sum_count<M>(fz.mode, [&]<int NK>() {
-            for (int64_t wv = w0; wv <= w1; ++wv) {
-                if (!wave_owns_tiles(wv, NT, W)) continue;
-                const double* p = w.part + (wv + f) * stride;
-#pragma unroll
-                for (int k = 0; k < NK; ++k) v[k] += p[k];
-            }
-        });
+        for (int k = 0; k < K; ++k) v[k] = k < nk ? all[k] : 0.0;
         finish_fit<M, MAXM>(d, w, f, v, fz, n, c, s);
     };
     dispatch_degree<MAXM>(deg, body);

@@ -603,36 +603,50 @@ __global__ void __launch_bounds__(256) k_finish_cheb_lane(FitDesc d, Work w, int
     const KernelClock kclock_(w.clock);
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.batch) return;
+    // the loads that depend on no other, issued together: status, degree,
+    // tile range, point count and the range from the record
     const int pst = w.pstatus[f];
+    const int deg = fit_deg(d, f);
+    const int64_t NT = w.tile_start[d.batch];
+    const int64_t ts = w.tile_start[f], te = w.tile_start[f + 1];
+    const int64_t n = fit_hi(d, f) - fit_lo(d, f);
+    double* r = w.rec + f * rec_len(maxm);
+    const double rc = r[0], rs = r[1];
     if (pst != LSEFIT_OK) {
         if (fz.mode != kMomentsOnly) cheb_fail(d, w, f, maxm, fz, pst);
         return;
     }
     const int stride = nacc(maxm);
-    const int64_t NT = w.tile_start[d.batch];
-    const int64_t w0 = wave_of_tile(w.tile_start[f], NT, W);
-    const int64_t w1 = wave_of_tile(w.tile_start[f + 1] - 1, NT, W);
+    const int64_t w0 = wave_of_tile(ts, NT, W);
+    const int64_t w1 = wave_of_tile(te - 1, NT, W);
+    // the sums of the largest degree's count, whatever this fit's degree (a
+    // degree-m fit's sums are the first ones of its slots; an index past the
+    // slot reads its last sum again), so that the loads sit outside the degree
+    // switch and a wave of mixed degrees waits for its partial sums once
+    constexpr int KMAX = nacc(MAXC);
+    double all[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) all[k] = 0.0;
+    for (int64_t wv = w0; wv <= w1; ++wv) {
+        if (!wave_owns_tiles(wv, NT, W)) continue;
+        const double* p = w.part + (wv + f) * stride;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) all[k] += p[k < stride ? k : stride - 1];
+    }
     auto body = [&]<int M>() {
         constexpr int N = M + 1;
         constexpr int K = nacc(M);
         double v[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = 0.0;
-        for (int64_t wv = w0; wv <= w1; ++wv) {
-            if (!wave_owns_tiles(wv, NT, W)) continue;
-            const double* p = w.part + (wv + f) * stride;
-#pragma unroll
-            for (int k = 0; k < K; ++k) v[k] += p[k];
-        }
+        for (int k = 0; k < K; ++k) v[k] = all[k];
         double S[2 * M + 1], D[N];
-        S[0] = (double)(fit_hi(d, f) - fit_lo(d, f));
+        S[0] = (double)n;
 #pragma unroll
         for (int k = 1; k <= M; ++k) S[k] = v[k - 1];
 #pragma unroll
         for (int j = 1; j <= M; ++j) S[M + j] = 2.0 * v[M + j - 1] - S[M - j];
 #pragma unroll
         for (int j = 0; j <= M; ++j) D[j] = v[2 * M + j];
-        double* r = w.rec + f * rec_len(maxm);
 #pragma unroll
         for (int k = 0; k <= 2 * M; ++k) r[rec_S(maxm) + k] = S[k];
 #pragma unroll
@@ -654,13 +668,13 @@ __global__ void __launch_bounds__(256) k_finish_cheb_lane(FitDesc d, Work w, int
             r[rec_b(maxm) + k] = c;
         }
         if (st == LSEFIT_OK && fz.coef_stride >= N + 2) {
-            out[N] = r[0];
-            out[N + 1] = r[1];
+            out[N] = rc;
+            out[N + 1] = rs;
         }
         w.pstatus[f] = st;
         if (fz.status) fz.status[f] = st;
     };
-    dispatch_degree<MAXC>(fit_deg(d, f), body);
+    dispatch_degree<MAXC>(deg, body);
 }
 
 // ---------------------------------------------------------------------------

@@ -71,19 +71,21 @@ def test_schedules_agree(schedule):
     check_against_oracle(bf, coef, status, 1e-9)
 
 
-@pytest.mark.parametrize("batch", [256, 257, 1024, 1025, 2048, 2049, 4096, 4097, 8192, 8193])
-def test_tile_table_one_launch_and_two(batch):
+@pytest.mark.parametrize("batch,dtype", [(b, np.float32) for b in (256, 257, 1024, 1025, 2048, 2049, 4096, 4097,
+                                                                  8192, 8193)]
+                         + [(b, np.float64) for b in (300, 1025, 4097, 8193)])
+def test_tile_table_one_launch_and_two(batch, dtype):
     """Up to 32 blocks of 256 fits (8,192) the tile table takes one launch, in
     which every block also counts the tiles before its own, with a loop sized
     for 0, 3, 7, 15 or 31 earlier blocks (each size at its first and last block
     count here); from 8,193 fits on it takes two.  Short fits, some empty and
     some across tile boundaries."""
-    announce(f"tile table, {batch} fits")
+    announce(f"tile table, {batch} fits, {np.dtype(dtype).name}")
     rng = np.random.default_rng(batch)
     L = rng.integers(0, 600, batch)
     L[::97] = 0
     deg = rng.integers(1, 4, batch)
-    bf = W.random_batch(L, deg, seed=batch + 1, lo=-5.0, hi=5.0)
+    bf = W.random_batch(L, deg, seed=batch + 1, lo=-5.0, hi=5.0, dtype=dtype)
     old = lf.default_schedule().as_dict()
     try:
         lf.set_default_schedule({"waves": 4096, "waves_per_block": 2, "tile": 256, "unroll": 2})
@@ -116,7 +118,7 @@ def _documented_auto_range(xs):
     return float(np.float32(c)), s
 
 
-@pytest.mark.parametrize("batch,dtype", [(300, np.float32), (9000, np.float32), (9000, np.float64)])
+@pytest.mark.parametrize("batch,dtype", [(300, np.float32), (9000, np.float32), (300, np.float64), (9000, np.float64)])
 def test_batched_auto_range_follows_the_documented_rule(batch, dtype):
     """The (c, s) each fit of a batch gets from its own x: bit for bit the
     documented sample rule, with the tile table in one launch (300 fits) and in

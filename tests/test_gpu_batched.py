@@ -153,6 +153,27 @@ def test_degree_out_of_range_is_flagged():
     assert np.isnan(coef[1]).all()         # every entry of an out-of-range fit
 
 
+def test_decreasing_segment_is_flagged():
+    """A fit whose end offset lies before its start (a bad segment) is flagged
+    INVALID_ARG with NaN coefficients and no tiles; its neighbours, which then
+    overlap in x, are fitted on their own ranges as usual."""
+    bf = W.random_batch([2000], [3], seed=41)
+    x, y = bf.x, bf.y
+    offsets = np.array([0, 1000, 500, 2000], dtype=np.int64)
+    degrees = np.array([3, 2, 3], dtype=np.int32)
+    coef, status, _ = lf.fit_batched(to_dev(x), to_dev(y), to_dev(offsets), to_dev(degrees), 3)
+    torch.cuda.synchronize()
+    coef, status = coef.cpu().numpy(), status.cpu().numpy()
+    assert list(status) == [0, 1, 0]
+    assert np.isnan(coef[1, :3]).all() and coef[1, 3] == 0.0   # its m + 1 coefficients; the row's rest untouched
+    # the two valid fits, laid out one after the other for the oracle
+    x2 = np.concatenate([x[0:1000], x[500:2000]])
+    y2 = np.concatenate([y[0:1000], y[500:2000]])
+    ref, rst = c_oracle.fit_batched(x2, y2, np.array([0, 1000, 2500]), np.array([3, 3], dtype=np.int32), stride=4)
+    assert list(rst) == [0, 0]
+    assert normwise(coef[0], ref[0]) <= 1e-9 and normwise(coef[2], ref[1]) <= 1e-9
+
+
 def test_nonfinite_fit_does_not_touch_neighbours():
     bf = W.random_batch([1000, 1000, 1000], [2, 2, 2], seed=6)
     bf.y[1500] = np.nan

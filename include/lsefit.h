@@ -293,7 +293,10 @@ lsefit_status fit_qr_batched(const void* x, const void* y, const int64_t* offset
 
 /* B independent fits over CSR segments: fit f owns points offsets[f] ..
  * offsets[f+1]-1 of x and y (Sec. II applied to each segment).
- *  offsets:   device int64 [B+1], non-decreasing, offsets[0] = 0
+ *  offsets:   device int64 [B+1], non-decreasing, offsets[0] = 0, every
+ *             offset within x and y (which the library cannot check: x and
+ *             y have no length argument); a fit whose end lies before its
+ *             start gets status INVALID_ARG and no points
  *  degrees:   device int32 [B], each in 1..opt->degree
  *  coef:      output, device float64 [B * coef_stride]: a_0..a_m of fit f at
  *             f*coef_stride; coef_stride >= opt->degree + 1; entries past m
@@ -305,8 +308,9 @@ lsefit_status fit_qr_batched(const void* x, const void* y, const int64_t* offset
  *             and ws_bytes ignored) and, in the graph form (see
  *             fit_plan_tune), after the first call with the same arguments,
  *             one replay of a captured HIP graph.
- * All fits run in one launch of the persistent streaming kernel (plus a tile
- * table kernel before it and one solve kernel after it). */
+ * All fits run in one launch of the persistent streaming kernel (plus the
+ * tile table before it -- one kernel for at most 32 blocks of 256 fits and a
+ * power-of-two tile, else two -- and one solve kernel after it). */
 lsefit_status fit_batched(const void* x, const void* y, const int64_t* offsets, const int32_t* degrees,
                           int64_t batch, int32_t dt, const lsefit_options* opt,
                           lsefit_plan* plan, void* ws, size_t ws_bytes,

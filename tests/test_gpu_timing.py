@@ -88,3 +88,31 @@ def test_noalloc_launches_are_not_timed():
         L.lsefit_timing_enable(0)
     assert _read(L, 0)[1] == 0 and _read(L, 3)[1] == 0
     assert int(status.cpu()[0]) == 0
+
+
+@pytest.mark.parametrize("batch", [300, 9000])
+def test_batched_call_times_its_tile_table(batch):
+    """A batched call is timed as one tile table (kind 7: its first launch, in
+    the one-launch form up to 8,192 fits and the two-launch form above), one
+    power-sum pass (kind 0) and one combine (kind 3)."""
+    import paper_1512_08017_amd as lf
+    announce(f"kernel clock: batched call of {batch} fits")
+    rng = np.random.default_rng(batch)
+    bf = W.random_batch(rng.integers(20, 400, batch), rng.integers(1, 4, batch), seed=batch)
+    x, y = to_dev(bf.x), to_dev(bf.y)
+    off, dg = to_dev(bf.offsets), to_dev(bf.degrees)
+    lf.fit_batched(x, y, off, dg, 3)
+    torch.cuda.synchronize()
+    L = _lib.load()
+    _lib.check(L.lsefit_timing_reset(), "lsefit_timing_reset")
+    _lib.check(L.lsefit_timing_enable(1), "lsefit_timing_enable")
+    try:
+        for _ in range(3):
+            _, status, _ = lf.fit_batched(x, y, off, dg, 3)
+        torch.cuda.synchronize()
+    finally:
+        L.lsefit_timing_enable(0)
+    for kind in (7, 0, 3):
+        tot, cnt = _read(L, kind)
+        assert cnt == 3 and tot > 0.0, (kind, tot, cnt)
+    assert (status.cpu().numpy() == 0).all()

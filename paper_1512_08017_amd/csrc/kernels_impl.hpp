@@ -369,10 +369,12 @@ __device__ inline void dispatch_sum_count(int mode, Body&& body) {
 }
 
 // n: the fit's number of points; (c, s): its range from the record (loaded by
-// the caller with its other loads, so that they share one memory round trip)
+// the caller with its other loads, so that they share one memory round trip);
+// rin: a copy of the fit's record to read the refinement's sums and solution
+// from (NULL: the record itself); the results always go to the record
 template <int M, int MAXM>
 __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, const double (&v)[nacc(M)],
-                                  const Finish& fz, int64_t n, double c, double s) {
+                                  const Finish& fz, int64_t n, double c, double s, const double* rin = nullptr) {
     constexpr int N = M + 1;
     constexpr int rl = rec_len(MAXM);
     if (fz.mode == kSSE) {
@@ -380,19 +382,20 @@ __device__ inline void finish_fit(const FitDesc& d, const Work& w, int64_t f, co
         return;
     }
     double* r = w.rec + f * rl;
+    const double* rr = rin ? rin : r;
     double* a_out = fz.coef + f * (int64_t)fz.coef_stride;
     double S[2 * M + 1];
     double b[1][N], a[N];
     int st;
     if (fz.mode == kRefine) {
 #pragma unroll
-        for (int k = 0; k <= 2 * M; ++k) S[k] = r[rec_S(MAXM) + k];
+        for (int k = 0; k <= 2 * M; ++k) S[k] = rr[rec_S(MAXM) + k];
         double R[1][N], delta[1][N];
 #pragma unroll
         for (int j = 0; j < N; ++j) R[0][j] = v[j];
         st = normal_solve<N, 1>(fz.solver, S, R, delta);
 #pragma unroll
-        for (int j = 0; j < N; ++j) b[0][j] = r[rec_b(MAXM) + j] + delta[0][j];
+        for (int j = 0; j < N; ++j) b[0][j] = rr[rec_b(MAXM) + j] + delta[0][j];
     } else {
         S[0] = (double)n;
 #pragma unroll
@@ -623,6 +626,11 @@ __device__ inline void block_combine_fit(const FitDesc& d, const Work& w, int64_
 // again and drops it, rather than branching around its load.
 constexpr int kFinishWaves = 8;
 constexpr int kFinishChunk = 8;
+// up to this degree one lane solves and changes the basis in registers
+// (finish_fit: the same operations as the wave form, so the same bits, and
+// 0.1-0.25 µs sooner without the lane exchanges); above it the wave does, a
+// row per lane (finish_fit_wave), which is sooner from degree 5 on
+constexpr int kFinishLaneMax = 4;
 
 template <int NK>
 __device__ inline void block_sum_partials(const double* __restrict__ part, int64_t G, double* out) {
@@ -686,7 +694,12 @@ __device__ inline void finish_single_block(const FitDesc& d, const Work& w, int6
                 double v[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) v[k] = k < nk ? sums[k] : 0.0;
-                finish_fit_wave<M, MAXM>(d, w, 0, v, fz, sm, rs);
+                if constexpr (M <= kFinishLaneMax) {
+                    if (lane_id() == 0)
+                        finish_fit<M, MAXM>(d, w, 0, v, fz, fit_hi(d, 0) - fit_lo(d, 0), rs[0], rs[1], rs);
+                } else {
+                    finish_fit_wave<M, MAXM>(d, w, 0, v, fz, sm, rs);
+                }
             }
         }
     };

@@ -250,6 +250,25 @@ def test_split_calls_match_fused_call(precision):
     assert int(fused.status.cpu()[0]) == int(split.status.cpu()[0]) == 0
 
 
+@pytest.mark.parametrize("solver", ["gepp", "cholesky"])
+@pytest.mark.parametrize("m", range(1, 9))
+def test_finish_forms_match_the_one_thread_solve(m, solver):
+    """The fused call's finish solves in registers by one lane up to degree 4
+    and by a wave, a row per lane, above it; fit_solve solves by one thread.
+    All do the same operations in the same order, so on the same power sums
+    (equal bit for bit) the coefficients in both bases are equal bit for bit."""
+    fit = W.random_small(200_003, m, seed=70 + m, dtype=np.float32)
+    x, y = to_dev(fit.x), to_dev(fit.y)
+    fused = lf.fit(x, y, m, solver=solver)
+    split = lf.fit_split(x, y, m, solver=solver)
+    torch.cuda.synchronize()
+    st = int(fused.status.cpu()[0])
+    assert st == int(split.status.cpu()[0]) and (st == 0 or solver == "cholesky")
+    assert np.array_equal(fused.moments.cpu().numpy(), split.moments.cpu().numpy())
+    assert np.array_equal(fused.coef.cpu().numpy(), split.coef.cpu().numpy(), equal_nan=True)
+    assert np.array_equal(fused.coef_t.cpu().numpy(), split.coef_t.cpu().numpy(), equal_nan=True)
+
+
 def test_reuse_across_calls_and_workspaces():
     """Nothing in the workspace has to start at zero: many calls on one
     workspace that first holds arbitrary bytes give identical results."""
